@@ -1,0 +1,62 @@
+"""The whole per-frame pipeline for one effect (Sec. 3: masks -> sub-images
+-> composition), and the naive full-resolution pass it is compared with
+(Sec. 5).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .masks import MaskParams, edge_image, build_pyramid, level_sample, Pyramid
+from .ssao import SSAOParams, ssao_level
+from .merge import upsample_merge
+from .shadow import ShadowParams, hard_shadow, shadow_edges, pcss_level
+from .ssgi import SSGIParams, ssgi_level
+
+
+@dataclass
+class Frame:
+    out: np.ndarray
+    pyramid: Pyramid = None
+    level_out: dict = field(default_factory=dict)
+
+
+def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None,
+          dtype=np.float32) -> Frame:
+    """effect in {"ssao", "shadow", "ssgi"}; params the matching *Params.
+
+    multires=False is the naive full-resolution pass."""
+    H, W = depth.shape
+    channels = 3 if effect == "ssgi" else 1
+
+    def evaluate(level, stencil):
+        zi = level_sample(depth, level)
+        if effect == "ssao":
+            ni = level_sample(normal, level)
+            return ssao_level(zi, ni, focal, level, params, stencil, dtype)
+        if effect == "shadow":
+            return pcss_level(zi, focal, level, params, stencil, dtype)
+        ni = level_sample(normal, level)
+        ci = level_sample(color, level)
+        return ssgi_level(zi, ni, ci, focal, level, params, stencil, dtype)
+
+    if not multires:
+        return Frame(out=evaluate(1, None))
+
+    E = edge_image(depth, normal, mp.depth_ratio, mp.normal_cos, dtype)
+    if effect == "shadow":
+        # Sec. 3.1: shadow edges from a one-sample shadow test, plus the
+        # geometry edges, combined by maximum.
+        hard = hard_shadow(depth, focal, 1, params, dtype)
+        E = E | shadow_edges(hard, depth)
+    pyr = build_pyramid(E, mp, dtype)
+    L = pyr.levels[-1]
+    lo = {}
+    for i in pyr.levels:
+        lo[i] = evaluate(i, None if i == L else pyr.stencil[i])
+    weights = {i: mp.weight[i - 1] for i in pyr.levels}
+    out = upsample_merge(W, H, pyr.levels, weights, pyr.alpha, pyr.stencil, lo, channels, dtype)
+    return Frame(out=out, pyramid=pyr, level_out=lo)
