@@ -1,0 +1,274 @@
+/*
+ * mr.h - multi-resolution screen-space lighting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libmr.so.  The operations follow Besenthal, Maisch and Ropinski,
+ * "Multi-Resolution Rendering for Computationally Expensive Lighting
+ * Effects" (arXiv 1906.04576):
+ *
+ *   mr_build_masks     Sec. 3.1 (edge image, downsampling, blur with the
+ *                      Table 1 variances, inclusive levels) and Sec. 4.1
+ *                      (stencil = mask > 0), plus per-level work lists that
+ *                      replace the stencil test.
+ *   mr_eval_ssao       Sec. 3.2 / 4.1: the effect rendered per sub-image only
+ *   mr_eval_shadow     where the level's stencil permits (Sec. 2.4 names the
+ *   mr_eval_ssgi       three effects); with no masks, the naive full-resolution
+ *                      pass of Sec. 5.
+ *   mr_upsample_merge  Sec. 3.3 / 4.2, Eq. 1: bilinear upsampling and the
+ *                      sequential blend from the coarsest level.
+ *   mr_frame           the whole pipeline for one effect.
+ *
+ * Conventions (all functions):
+ *  - Every array argument is DEVICE memory owned by the caller, unless the
+ *    comment says "host".  The library never allocates or frees memory;
+ *    intermediate storage comes from a caller-provided workspace sized by
+ *    mr_workspace_bytes.  Device pointers must be 16-byte aligned.
+ *  - Images are row-major [y][x], row 0 at the top; multi-channel images are
+ *    planar [c][y][x].  Level i (1-based) has scale s_i = 2^(i-1) and size
+ *    W_i = W / s_i, H_i = H / s_i; W and H must be divisible by 2^(N-1).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call only
+ *    enqueues work on it and returns; there is no host synchronisation and
+ *    work-list counts stay on the device.  Device faults surface at the
+ *    caller's next synchronisation.
+ *  - Every call validates all arguments before it enqueues anything; on
+ *    error it returns a negative MR_E_* code, enqueues nothing, leaves the
+ *    outputs untouched and sets a thread-local message (mr_last_error).
+ *  - Calls are re-entrant: the library has no mutable global state besides
+ *    the thread-local error message.  Calls that share output or workspace
+ *    memory must be ordered by the caller (same stream or events).
+ *  - Floating point: IEEE binary32, round to nearest even, no fused
+ *    multiply-add, correctly rounded division and square root, denormals
+ *    kept; results are deterministic run to run.
+ */
+#ifndef MR_H
+#define MR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MR_API __attribute__((visibility("default")))
+
+#define MR_MAX_LEVELS 6
+#define MR_MAX_RADIUS 16   /* largest blur radius in level texels */
+#define MR_MAX_SAMPLES 8192
+#define MR_MAX_DIM 16384
+#define MR_VERSION 100
+
+/* status codes */
+#define MR_OK 0
+#define MR_E_NULL (-1)      /* a required pointer is NULL */
+#define MR_E_SHAPE (-2)     /* width/height <= 0, > MR_MAX_DIM or not divisible by 2^(N-1) */
+#define MR_E_PARAM (-3)     /* a parameter is out of range, or a pointer is misaligned */
+#define MR_E_WORKSPACE (-4) /* workspace smaller than mr_workspace_bytes */
+#define MR_E_DTYPE (-5)     /* unsupported element type */
+#define MR_E_DEVICE (-6)    /* a HIP launch or query failed */
+
+/* element types */
+#define MR_F32 0
+#define MR_F16 1
+
+/* effects */
+#define MR_EFFECT_SSAO 0
+#define MR_EFFECT_SHADOW 1
+#define MR_EFFECT_SSGI 2
+#define MR_WS_MASKS (-1) /* mr_workspace_bytes purpose: scratch of mr_build_masks */
+
+/* G-buffer (Sec. 3.1 uses depth and normals; SSGI also reads a lit colour
+ * buffer).  depth: f32 [H][W] linear view depth, a pixel is geometry iff its
+ * depth is finite and > 0.  normal: [3][H][W] view-space unit normals,
+ * element type normal_dtype (MR_F32 or MR_F16).  color: [3][H][W] directly lit
+ * colour, color_dtype (MR_F32 or MR_F16); only mr_eval_ssgi reads it. */
+typedef struct {
+    const float* depth;
+    const void* normal;
+    int normal_dtype;
+    const void* color;
+    int color_dtype;
+} mr_gbuffer;
+
+/* Pinhole camera: pixel (x, y) has its centre ray along
+ * ((x + 0.5 - W/2) / f, (H/2 - (y + 0.5)) / f, -1) in view space. */
+typedef struct {
+    int width, height;
+    float focal_px;
+} mr_camera;
+
+/* Mask parameters (Sec. 3.1, Table 1, Sec. 4).
+ * num_levels   N in [1, MR_MAX_LEVELS].
+ * level_enable bit (i-1) set = level i used; bits 0 and N-1 must be set
+ *              (the paper's SSGI uses levels {1, 3, 4}).
+ * depth_ratio  edge if the depth second difference along x or y exceeds
+ *              depth_ratio * z (finite, >= 0).
+ * normal_cos   edge if the dot product with a 4-neighbour's normal is
+ *              below normal_cos (in [-1, 1]).
+ * sigma2[i-1]  blur variance of level i in level-i texels (>= 0).
+ * weight[i-1]  blend weight w_i (> 0, finite).
+ * radius[i-1]  blur radius in level-i texels, -1 = ceil(3 sigma), at most
+ *              MR_MAX_RADIUS.  Entries of disabled levels and of level N are
+ *              ignored. */
+typedef struct {
+    int num_levels;
+    uint32_t level_enable;
+    float depth_ratio;
+    float normal_cos;
+    float sigma2[MR_MAX_LEVELS];
+    float weight[MR_MAX_LEVELS];
+    int radius[MR_MAX_LEVELS];
+} mr_mask_params;
+
+/* Mask pyramid (outputs of mr_build_masks, inputs of eval/merge).  Index
+ * [i-1] is level i.  For every enabled level i < N:
+ *   alpha[i-1]     f32 [H_i][W_i] blurred mask a_i (required)
+ *   stencil[i-1]   u8  [H_i][W_i] S_i = a_i > 0 after nesting (required)
+ *   worklist[i-1]  u32 [H_i * W_i capacity] row-major ascending y*W_i + x of
+ *                  the texels with S_i = 1 (required)
+ * For every enabled level i >= 2:
+ *   level_depth[i-1] f32 [H_i][W_i] point-sampled depth z(s x + s/2, s y + s/2)
+ *                  (optional; NULL = the evaluators read the full-resolution
+ *                  depth with stride s).
+ * edge       u8 [H][W] full-resolution edge image (required).
+ * level_map  u8 [H][W] owner level of every pixel = finest enabled level
+ *            whose stencil covers it (optional, NULL = not written).
+ * count      u32 [MR_MAX_LEVELS] device counts; count[i-1] = list length of
+ *            level i (required; entries of other levels are set to 0).
+ * Stencil and work-list entries of level N are never read: level N is
+ * treated as covering the whole image. */
+typedef struct {
+    uint8_t* edge;
+    uint8_t* level_map;
+    float* alpha[MR_MAX_LEVELS];
+    uint8_t* stencil[MR_MAX_LEVELS];
+    uint32_t* worklist[MR_MAX_LEVELS];
+    float* level_depth[MR_MAX_LEVELS];
+    uint32_t* count;
+} mr_masks;
+
+/* SSAO (Sec. 2.4; estimator fixed by this library): normal-oriented
+ * hemisphere with a caller-supplied kernel.
+ * kernel   f32 [samples][3] sample offsets in the tangent frame (device)
+ * samples  in [1, MR_MAX_SAMPLES]
+ * radius   world-space radius r (> 0, finite)
+ * bias_rel relative depth bias (>= 0, finite) */
+typedef struct {
+    const float* kernel;
+    int samples;
+    float radius;
+    float bias_rel;
+} mr_ssao_params;
+
+/* Soft shadows (Sec. 2.4: shadow map, PCF, PCSS penumbra).
+ * shadow_map   f32 [sm_size][sm_size] linear light depth (device)
+ * view_to_light host 3x4 row-major affine map from camera view space to
+ *              light view space (the light looks down its -z axis)
+ * light_focal_px focal length of the light camera in texels
+ * light_size   side of the square area light, light_near its near plane
+ * bias         absolute depth bias of every shadow-map comparison
+ * blocker_disk f32 [n_blocker][2], pcf_disk f32 [n_pcf][2] unit-disk
+ *              points (device); n_* in [1, MR_MAX_SAMPLES] */
+typedef struct {
+    const float* shadow_map;
+    int sm_size;
+    float view_to_light[12];
+    float light_focal_px;
+    float light_size;
+    float light_near;
+    float bias;
+    const float* blocker_disk;
+    const float* pcf_disk;
+    int n_blocker, n_pcf;
+} mr_shadow_params;
+
+/* One-bounce screen-space indirect light (Sec. 2.4): same sampling as SSAO,
+ * occluding samples add the colour of the texel they hit. */
+typedef struct {
+    const float* kernel;
+    int samples;
+    float radius;
+    float bias_rel;
+} mr_ssgi_params;
+
+/* Whole-frame descriptor for mr_frame.
+ * effect     MR_EFFECT_*; the matching params pointer must be non-NULL (host).
+ * multires   0 = naive full-resolution pass (masks unused), 1 = multi-res.
+ * out        f32 [C][H][W], C = 3 for SSGI, else 1.
+ * level_map  optional u8 [H][W] owner-level output (multires only). */
+typedef struct {
+    int effect;
+    int multires;
+    mr_gbuffer g;
+    mr_camera cam;
+    mr_mask_params mp;
+    const mr_ssao_params* ssao;
+    const mr_shadow_params* shadow;
+    const mr_ssgi_params* ssgi;
+    float* out;
+    uint8_t* level_map;
+} mr_frame_desc;
+
+/* Workspace bytes needed by mr_frame for `effect` (MR_EFFECT_*) or by
+ * mr_build_masks (purpose MR_WS_MASKS); cam and mp are host pointers.
+ * Returns 0 and sets mr_last_error if the arguments are invalid. */
+MR_API size_t mr_workspace_bytes(const mr_camera* cam, const mr_mask_params* mp, int purpose);
+
+/* Sec. 3.1 + Sec. 4.1: edge image, OR-downsampled edges, blurred masks,
+ * stencils, nesting, owner-level map, work lists and counts.
+ * hard_shadow: optional u8 [H][W] one-sample shadow bits (mr_shadow_hard);
+ * when given, pixels whose shadow bit differs from a 4-neighbour's are
+ * edges too (the mask for soft shadows keeps geometry and shadow edges).
+ * ws / ws_bytes: device scratch, at least mr_workspace_bytes(..., MR_WS_MASKS). */
+MR_API int mr_build_masks(const mr_gbuffer* g, const mr_camera* cam, const mr_mask_params* mp,
+                          const uint8_t* hard_shadow, const mr_masks* out, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Sec. 3.2 / 4.1: SSAO occlusion per sub-image.  masks != NULL: for every
+ * enabled level i < N the texels of worklist[i-1] (count on the device) are
+ * evaluated, level N densely; out[i-1] is f32 [H_i][W_i] and is written only
+ * at evaluated texels.  masks == NULL: the naive full-resolution pass into
+ * out[0] (f32 [H][W]); other entries ignored.  Output 0 = unoccluded. */
+MR_API int mr_eval_ssao(const mr_gbuffer* g, const mr_camera* cam, const mr_mask_params* mp,
+                        const mr_masks* masks, const mr_ssao_params* p, float* const out[MR_MAX_LEVELS],
+                        void* stream);
+
+/* Sec. 3.1: one-sample hard shadow test per full-resolution pixel,
+ * hard u8 [H][W] (1 = shadowed). */
+MR_API int mr_shadow_hard(const mr_gbuffer* g, const mr_camera* cam, const mr_shadow_params* p,
+                          uint8_t* hard, void* stream);
+
+/* Soft-shadow visibility (1 = lit) per sub-image; same texel selection and
+ * output layout as mr_eval_ssao. */
+MR_API int mr_eval_shadow(const mr_gbuffer* g, const mr_camera* cam, const mr_mask_params* mp,
+                          const mr_masks* masks, const mr_shadow_params* p,
+                          float* const out[MR_MAX_LEVELS], void* stream);
+
+/* Indirect RGB per sub-image; out[i-1] is f32 [3][H_i][W_i]; needs g->color. */
+MR_API int mr_eval_ssgi(const mr_gbuffer* g, const mr_camera* cam, const mr_mask_params* mp,
+                        const mr_masks* masks, const mr_ssgi_params* p,
+                        float* const out[MR_MAX_LEVELS], void* stream);
+
+/* Sec. 3.3 / 4.2, Eq. 1: every enabled level is upsampled bilinearly (taps
+ * restricted to its stencil and renormalised), then blended from the
+ * coarsest: c' = c_N, c' = C_i alpha_i + c' (1 - alpha_i) for enabled i < N
+ * descending, alpha_i = min(bilinear(a_i) w_i, 1).  level_out[i-1] is
+ * f32 [C][H_i][W_i]; out is f32 [C][H][W]; channels C in {1, 3}. */
+MR_API int mr_upsample_merge(const mr_camera* cam, const mr_mask_params* mp, const mr_masks* masks,
+                             const float* const level_out[MR_MAX_LEVELS], int channels, float* out,
+                             void* stream);
+
+/* Whole frame for one effect: masks (with shadow edges for MR_EFFECT_SHADOW),
+ * per-level evaluation and merge, or the naive pass when multires == 0.
+ * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */
+MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream);
+
+/* Host helpers. */
+MR_API const char* mr_status_string(int status);
+MR_API const char* mr_last_error(void);
+MR_API int mr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MR_H */

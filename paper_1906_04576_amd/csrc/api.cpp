@@ -1,0 +1,714 @@
+// Host side of libmr: argument validation, Gaussian taps, workspace layout
+// and launch sequencing behind the C ABI declared in include/mr.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "mr_internal.hpp"
+
+using namespace mr;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Level geometry of one frame.
+struct Geo {
+    int N = 0, W = 0, H = 0, L = 0;
+    int Wi[kMaxLevels] = {}, Hi[kMaxLevels] = {};
+    int levels[kMaxLevels] = {};  // enabled levels ascending (1-based)
+    int nlev = 0;
+    bool enabled(int i) const {
+        for (int j = 0; j < nlev; ++j)
+            if (levels[j] == i) return true;
+        return false;
+    }
+    long long n(int i) const { return (long long)Wi[i - 1] * Hi[i - 1]; }
+};
+
+int check_geo(const mr_camera* cam, const mr_mask_params* mp, Geo& g) {
+    if (!cam) return fail(MR_E_NULL, "camera is NULL");
+    int N = 1;
+    uint32_t en = 1;
+    if (mp) {
+        N = mp->num_levels;
+        en = mp->level_enable;
+        if (N < 1 || N > kMaxLevels) return fail(MR_E_PARAM, "num_levels %d not in [1, %d]", N, kMaxLevels);
+        if (!(en & 1u) || !(en & (1u << (N - 1))))
+            return fail(MR_E_PARAM, "level_enable 0x%x must contain levels 1 and %d", en, N);
+        if (en >> N) return fail(MR_E_PARAM, "level_enable 0x%x names levels above %d", en, N);
+    }
+    const int W = cam->width, H = cam->height;
+    if (W <= 0 || H <= 0 || W > MR_MAX_DIM || H > MR_MAX_DIM)
+        return fail(MR_E_SHAPE, "image %dx%d outside [1, %d]", W, H, MR_MAX_DIM);
+    const int div = 1 << (N - 1);
+    if (W % div || H % div)
+        return fail(MR_E_SHAPE, "image %dx%d not divisible by 2^(N-1) = %d", W, H, div);
+    if (!(cam->focal_px > 0.0f) || !isfinite(cam->focal_px))
+        return fail(MR_E_PARAM, "focal_px must be finite and > 0");
+    g.N = N;
+    g.W = W;
+    g.H = H;
+    g.nlev = 0;
+    for (int i = 1; i <= N; ++i) {
+        g.Wi[i - 1] = W >> (i - 1);
+        g.Hi[i - 1] = H >> (i - 1);
+        if (en & (1u << (i - 1))) g.levels[g.nlev++] = i;
+    }
+    g.L = g.levels[g.nlev - 1];
+    return MR_OK;
+}
+
+// blur radius and normalised Gaussian taps of one level
+int gauss(const mr_mask_params* mp, int i, float* taps, int& r) {
+    const float s2f = mp->sigma2[i - 1];
+    if (!(s2f >= 0.0f) || !isfinite(s2f)) return fail(MR_E_PARAM, "sigma2[%d] must be finite and >= 0", i - 1);
+    const int rp = mp->radius[i - 1];
+    if (rp < -1) return fail(MR_E_PARAM, "radius[%d] = %d must be >= -1", i - 1, rp);
+    const double s2 = (double)s2f;
+    if (rp >= 0)
+        r = rp;
+    else if (s2 <= 0.0)
+        r = 0;
+    else
+        r = (int)ceil(3.0 * sqrt(s2));
+    if (r > kMaxRadius) return fail(MR_E_PARAM, "blur radius %d of level %d exceeds %d", r, i, kMaxRadius);
+    if (s2 <= 0.0) {
+        for (int k = -r; k <= r; ++k) taps[k + r] = k == 0 ? 1.0f : 0.0f;
+        return MR_OK;
+    }
+    double e[2 * kMaxRadius + 1];
+    double tot = 0.0;
+    for (int k = -r; k <= r; ++k) {
+        e[k + r] = exp(-(double)(k * k) / (2.0 * s2));
+        tot += e[k + r];
+    }
+    for (int k = -r; k <= r; ++k) taps[k + r] = (float)(e[k + r] / tot);
+    return MR_OK;
+}
+
+int check_mask_params(const mr_mask_params* mp, const Geo& g) {
+    if (!isfinite(mp->depth_ratio) || !(mp->depth_ratio >= 0.0f))
+        return fail(MR_E_PARAM, "depth_ratio must be finite and >= 0");
+    if (!(mp->normal_cos >= -1.0f && mp->normal_cos <= 1.0f))
+        return fail(MR_E_PARAM, "normal_cos must be in [-1, 1]");
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        float taps[2 * kMaxRadius + 1];
+        int r;
+        int st = gauss(mp, i, taps, r);
+        if (st) return st;
+        const float w = mp->weight[i - 1];
+        if (!(w > 0.0f) || !isfinite(w)) return fail(MR_E_PARAM, "weight[%d] must be finite and > 0", i - 1);
+    }
+    return MR_OK;
+}
+
+int check_gbuffer(const mr_gbuffer* g, bool need_normal, bool need_color) {
+    if (!g) return fail(MR_E_NULL, "gbuffer is NULL");
+    if (!g->depth) return fail(MR_E_NULL, "gbuffer.depth is NULL");
+    if (misaligned(g->depth)) return fail(MR_E_PARAM, "gbuffer.depth is not 16-byte aligned");
+    if (need_normal) {
+        if (!g->normal) return fail(MR_E_NULL, "gbuffer.normal is NULL");
+        if (misaligned(g->normal)) return fail(MR_E_PARAM, "gbuffer.normal is not 16-byte aligned");
+        if (g->normal_dtype != MR_F32 && g->normal_dtype != MR_F16)
+            return fail(MR_E_DTYPE, "normal_dtype %d unsupported", g->normal_dtype);
+    }
+    if (need_color) {
+        if (!g->color) return fail(MR_E_NULL, "gbuffer.color is NULL");
+        if (misaligned(g->color)) return fail(MR_E_PARAM, "gbuffer.color is not 16-byte aligned");
+        if (g->color_dtype != MR_F32 && g->color_dtype != MR_F16)
+            return fail(MR_E_DTYPE, "color_dtype %d unsupported", g->color_dtype);
+    }
+    return MR_OK;
+}
+
+// masks needed by the evaluators (need_alpha: also the merge)
+int check_masks(const mr_masks* m, const Geo& g, bool need_alpha, bool need_lists) {
+    if (!m) return fail(MR_E_NULL, "masks is NULL");
+    if (need_lists) {
+        if (!m->count) return fail(MR_E_NULL, "masks.count is NULL");
+        if (misaligned(m->count)) return fail(MR_E_PARAM, "masks.count is not 16-byte aligned");
+    }
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i >= 2 && m->level_depth[i - 1] && misaligned(m->level_depth[i - 1]))
+            return fail(MR_E_PARAM, "masks.level_depth[%d] is not 16-byte aligned", i - 1);
+        if (i == g.L) continue;
+        if (!m->stencil[i - 1]) return fail(MR_E_NULL, "masks.stencil[%d] is NULL", i - 1);
+        if (misaligned(m->stencil[i - 1])) return fail(MR_E_PARAM, "masks.stencil[%d] misaligned", i - 1);
+        if (need_lists) {
+            if (!m->worklist[i - 1]) return fail(MR_E_NULL, "masks.worklist[%d] is NULL", i - 1);
+            if (misaligned(m->worklist[i - 1])) return fail(MR_E_PARAM, "masks.worklist[%d] misaligned", i - 1);
+        }
+        if (need_alpha) {
+            if (!m->alpha[i - 1]) return fail(MR_E_NULL, "masks.alpha[%d] is NULL", i - 1);
+            if (misaligned(m->alpha[i - 1])) return fail(MR_E_PARAM, "masks.alpha[%d] misaligned", i - 1);
+        }
+    }
+    return MR_OK;
+}
+
+int check_outputs(float* const out[kMaxLevels], const Geo& g, bool plain) {
+    if (!out) return fail(MR_E_NULL, "out is NULL");
+    if (plain) {
+        if (!out[0]) return fail(MR_E_NULL, "out[0] is NULL");
+        if (misaligned(out[0])) return fail(MR_E_PARAM, "out[0] is not 16-byte aligned");
+        return MR_OK;
+    }
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (!out[i - 1]) return fail(MR_E_NULL, "out[%d] is NULL", i - 1);
+        if (misaligned(out[i - 1])) return fail(MR_E_PARAM, "out[%d] is not 16-byte aligned", i - 1);
+    }
+    return MR_OK;
+}
+
+int check_samples(const float* k, int n, const char* what) {
+    if (!k) return fail(MR_E_NULL, "%s is NULL", what);
+    if (misaligned(k)) return fail(MR_E_PARAM, "%s is not 16-byte aligned", what);
+    if (n < 1 || n > MR_MAX_SAMPLES) return fail(MR_E_PARAM, "%s count %d not in [1, %d]", what, n, MR_MAX_SAMPLES);
+    return MR_OK;
+}
+
+int check_shadow(const mr_shadow_params* p) {
+    if (!p) return fail(MR_E_NULL, "shadow params are NULL");
+    if (!p->shadow_map) return fail(MR_E_NULL, "shadow_map is NULL");
+    if (misaligned(p->shadow_map)) return fail(MR_E_PARAM, "shadow_map is not 16-byte aligned");
+    if (p->sm_size < 1 || p->sm_size > MR_MAX_DIM) return fail(MR_E_SHAPE, "sm_size %d not in [1, %d]", p->sm_size, MR_MAX_DIM);
+    for (int k = 0; k < 12; ++k)
+        if (!isfinite(p->view_to_light[k])) return fail(MR_E_PARAM, "view_to_light must be finite");
+    if (!(p->light_focal_px > 0.0f) || !isfinite(p->light_focal_px)) return fail(MR_E_PARAM, "light_focal_px must be finite and > 0");
+    if (!(p->light_size >= 0.0f) || !isfinite(p->light_size)) return fail(MR_E_PARAM, "light_size must be finite and >= 0");
+    if (!(p->light_near > 0.0f) || !isfinite(p->light_near)) return fail(MR_E_PARAM, "light_near must be finite and > 0");
+    if (!isfinite(p->bias)) return fail(MR_E_PARAM, "bias must be finite");
+    int st = check_samples(p->blocker_disk, p->n_blocker, "blocker_disk");
+    if (st) return st;
+    return check_samples(p->pcf_disk, p->n_pcf, "pcf_disk");
+}
+
+int check_sampling(const float* kernel, int S, float r, float b) {
+    int st = check_samples(kernel, S, "kernel");
+    if (st) return st;
+    if (!(r > 0.0f) || !isfinite(r)) return fail(MR_E_PARAM, "radius must be finite and > 0");
+    if (!(b >= 0.0f) || !isfinite(b)) return fail(MR_E_PARAM, "bias_rel must be finite and >= 0");
+    return MR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layouts
+// ---------------------------------------------------------------------------
+struct MaskScratch {
+    size_t Ei_off[kMaxLevels] = {};
+    size_t chunk_count_off = 0, chunk_off_off = 0;
+    unsigned nchunks = 0;
+    size_t bytes = 0;
+};
+
+MaskScratch mask_scratch(const Geo& g) {
+    MaskScratch s;
+    size_t off = 0;
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i < 2) continue;
+        s.Ei_off[i - 1] = off;
+        off += align256((size_t)g.n(i));
+    }
+    for (int j = 0; j + 1 < g.nlev; ++j) s.nchunks += (unsigned)((g.n(g.levels[j]) + kChunk - 1) / kChunk);
+    s.chunk_count_off = off;
+    off += align256((size_t)s.nchunks * 4 + 4);
+    s.chunk_off_off = off;
+    off += align256((size_t)s.nchunks * 4 + 4);
+    s.bytes = off;
+    return s;
+}
+
+struct FrameLayout {
+    size_t edge = 0, alpha[kMaxLevels] = {}, stencil[kMaxLevels] = {}, worklist[kMaxLevels] = {};
+    size_t level_depth[kMaxLevels] = {}, level_out[kMaxLevels] = {}, count = 0, hard = 0, scratch = 0;
+    size_t bytes = 0;
+};
+
+FrameLayout frame_layout(const Geo& g, int effect) {
+    FrameLayout f;
+    const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        size_t o = off;
+        off += align256(n);
+        return o;
+    };
+    f.edge = take((size_t)g.W * g.H);
+    f.count = take(4 * kMaxLevels);
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        const size_t n = (size_t)g.n(i);
+        if (i != g.L) {
+            f.alpha[i - 1] = take(4 * n);
+            f.stencil[i - 1] = take(n);
+            f.worklist[i - 1] = take(4 * n);
+        }
+        if (i >= 2) f.level_depth[i - 1] = take(4 * n);
+        f.level_out[i - 1] = take(4 * n * C);
+    }
+    if (effect == MR_EFFECT_SHADOW) f.hard = take((size_t)g.W * g.H);
+    f.scratch = off;
+    off += mask_scratch(g).bytes;
+    f.bytes = off;
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// pipeline pieces (arguments already validated)
+// ---------------------------------------------------------------------------
+int do_build_masks(const mr_gbuffer* gb, const Geo& g, const mr_mask_params* mp, const uint8_t* hard,
+                   const mr_masks* m, void* ws, hipStream_t s) {
+    const MaskScratch sc = mask_scratch(g);
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    EdgeArgs ea{};
+    ea.depth = gb->depth;
+    ea.normal = gb->normal;
+    ea.hard = hard;
+    ea.W = g.W;
+    ea.H = g.H;
+    ea.depth_ratio = mp->depth_ratio;
+    ea.normal_cos = mp->normal_cos;
+    ea.E = m->edge;
+    ea.num_levels = g.N;
+    uint8_t* Ei[kMaxLevels] = {};
+    for (int i = 1; i <= g.N; ++i) {
+        ea.Wi[i - 1] = g.Wi[i - 1];
+        ea.Hi[i - 1] = g.Hi[i - 1];
+    }
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i >= 2) ea.zi[i - 1] = m->level_depth[i - 1];
+        if (i == g.L) continue;
+        Ei[i - 1] = i == 1 ? m->edge : base + sc.Ei_off[i - 1];
+        if (i >= 2) ea.Ei[i - 1] = Ei[i - 1];
+    }
+    if (launch_edges(ea, gb->normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
+    int radius[kMaxLevels] = {};
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        BlurArgs ba{};
+        int r;
+        gauss(mp, i, ba.g, r);
+        radius[i - 1] = r;
+        ba.Ei = Ei[i - 1];
+        ba.a = m->alpha[i - 1];
+        ba.S = m->stencil[i - 1];
+        ba.W = g.Wi[i - 1];
+        ba.H = g.Hi[i - 1];
+        ba.r = r;
+        if (launch_blur(ba, s) != hipSuccess) return fail(MR_E_DEVICE, "blur kernel launch failed");
+    }
+    // Nesting: S_j |= pool(S_i) for consecutive enabled i < j < L.  When every
+    // earlier pair was a no-op, S_i is the Chebyshev dilation of E_i by r_i
+    // and the pair is a no-op too if r_j >= ceil(r_i / k); only pairs that can
+    // change anything are launched.
+    bool dirty = false;
+    for (int j = 0; j + 2 < g.nlev; ++j) {
+        const int fi = g.levels[j], ci = g.levels[j + 1];
+        const int k = 1 << (ci - fi);
+        if (!dirty && radius[ci - 1] >= (radius[fi - 1] + k - 1) / k) continue;
+        dirty = true;
+        NestArgs na{m->stencil[fi - 1], m->stencil[ci - 1], g.Wi[fi - 1], g.Hi[fi - 1], g.Wi[ci - 1], g.Hi[ci - 1], k};
+        if (launch_nest(na, s) != hipSuccess) return fail(MR_E_DEVICE, "nesting kernel launch failed");
+    }
+    if (m->level_map) {
+        LevelMapArgs la{};
+        la.nlev = g.nlev;
+        for (int j = 0; j < g.nlev; ++j) {
+            la.levels[j] = g.levels[j];
+            la.S[j] = m->stencil[g.levels[j] - 1];
+            la.Wi[j] = g.Wi[g.levels[j] - 1];
+        }
+        la.W = g.W;
+        la.H = g.H;
+        la.out = m->level_map;
+        if (launch_level_map(la, s) != hipSuccess) return fail(MR_E_DEVICE, "level map kernel launch failed");
+    }
+    CompactArgs ca{};
+    ca.nlev = g.nlev - 1;
+    unsigned cb = 0;
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        ca.S[j] = m->stencil[i - 1];
+        ca.list[j] = m->worklist[i - 1];
+        ca.n[j] = (uint32_t)g.n(i);
+        ca.chunk_base[j] = cb;
+        ca.count_idx[j] = i - 1;
+        cb += (unsigned)((g.n(i) + kChunk - 1) / kChunk);
+    }
+    ca.chunk_base[ca.nlev] = cb;
+    ca.chunk_count = reinterpret_cast<uint32_t*>(base + sc.chunk_count_off);
+    ca.chunk_off = reinterpret_cast<uint32_t*>(base + sc.chunk_off_off);
+    ca.count = m->count;
+    if (launch_compact(ca, s) != hipSuccess) return fail(MR_E_DEVICE, "compaction kernel launch failed");
+    return MR_OK;
+}
+
+// per-level views for an evaluation pass; returns the worst-case item count
+unsigned make_eval_common(const mr_gbuffer* gb, const Geo& g, const mr_masks* m, float* const out[kMaxLevels],
+                          int C, EvalCommon& c) {
+    c.counts = m ? m->count : nullptr;
+    c.normal = gb->normal;
+    c.color = gb->color;
+    c.plane = (long long)g.W * g.H;
+    unsigned hint = 0;
+    const int nl = m ? g.nlev : 1;
+    c.nlev = nl;
+    for (int j = 0; j < nl; ++j) {
+        const int i = m ? g.levels[j] : 1;
+        const int sft = i - 1, sc = 1 << sft;
+        EvalLevel& L = c.lv[j];
+        L.W = g.Wi[i - 1];
+        L.H = g.Hi[i - 1];
+        if (i == 1) {
+            L.z = gb->depth;
+            L.zpy = g.W;
+            L.zpx = 1;
+            L.goff = 0;
+        } else {
+            const long long off = (long long)(sc / 2) * g.W + sc / 2;
+            if (m && m->level_depth[i - 1]) {
+                L.z = m->level_depth[i - 1];
+                L.zpy = L.W;
+                L.zpx = 1;
+            } else {
+                L.z = gb->depth + off;
+                L.zpy = (long long)sc * g.W;
+                L.zpx = sc;
+            }
+            L.goff = off;
+        }
+        L.gpy = (long long)sc * g.W;
+        L.gpx = sc;
+        L.out = out[i - 1];
+        L.out_plane = (long long)L.W * L.H;
+        const bool dense = !m || i == g.L;
+        L.list = dense ? nullptr : m->worklist[i - 1];
+        L.count_idx = i - 1;
+        L.dense_n = (unsigned)((long long)L.W * L.H);
+        hint += L.dense_n;
+        (void)C;
+    }
+    return hint;
+}
+
+void set_level_cameras(const mr_camera* cam, const Geo& g, EvalCommon& c, bool plain) {
+    for (int j = 0; j < c.nlev; ++j) {
+        const int i = plain ? 1 : g.levels[j];
+        EvalLevel& L = c.lv[j];
+        L.f = cam->focal_px / (float)(1 << (i - 1));
+        L.cx = 0.5f * (float)L.W;
+        L.cy = 0.5f * (float)L.H;
+    }
+}
+
+int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g, const mr_masks* m,
+            const void* params, float* const out[kMaxLevels], hipStream_t s) {
+    const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    hipError_t e;
+    if (effect == MR_EFFECT_SSAO) {
+        const mr_ssao_params* p = static_cast<const mr_ssao_params*>(params);
+        SsaoArgs a{};
+        const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
+        set_level_cameras(cam, g, a.c, !m);
+        a.kernel = p->kernel;
+        a.S = p->samples;
+        a.r = p->radius;
+        a.b = p->bias_rel;
+        e = launch_ssao(a, gb->normal_dtype, hint, s);
+    } else if (effect == MR_EFFECT_SHADOW) {
+        const mr_shadow_params* p = static_cast<const mr_shadow_params*>(params);
+        ShadowArgs a{};
+        const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
+        set_level_cameras(cam, g, a.c, !m);
+        a.sm = p->shadow_map;
+        a.size = p->sm_size;
+        memcpy(a.M, p->view_to_light, sizeof(a.M));
+        a.fL = p->light_focal_px;
+        a.lsize = p->light_size;
+        a.nL = p->light_near;
+        a.bias = p->bias;
+        a.bd = p->blocker_disk;
+        a.pd = p->pcf_disk;
+        a.nb = p->n_blocker;
+        a.np = p->n_pcf;
+        e = launch_shadow(a, hint, s);
+    } else {
+        const mr_ssgi_params* p = static_cast<const mr_ssgi_params*>(params);
+        SsgiArgs a{};
+        const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
+        set_level_cameras(cam, g, a.c, !m);
+        a.kernel = p->kernel;
+        a.S = p->samples;
+        a.r = p->radius;
+        a.b = p->bias_rel;
+        e = launch_ssgi(a, gb->normal_dtype, gb->color_dtype, hint, s);
+    }
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "evaluation kernel launch failed: %s", hipGetErrorString(e));
+    return MR_OK;
+}
+
+int do_merge(const Geo& g, const mr_mask_params* mp, const mr_masks* m, const float* const lo[kMaxLevels], int C,
+             float* out, hipStream_t s) {
+    MergeArgs a{};
+    a.nlev = g.nlev;
+    a.W = g.W;
+    a.H = g.H;
+    a.C = C;
+    a.out = out;
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        MergeLevel& L = a.lv[j];
+        L.c = lo[i - 1];
+        L.c_plane = g.n(i);
+        L.s = 1 << (i - 1);
+        L.W = g.Wi[i - 1];
+        L.H = g.Hi[i - 1];
+        L.w = mp->weight[i - 1];
+        L.a = i == g.L ? nullptr : m->alpha[i - 1];
+        L.S = i == g.L ? nullptr : m->stencil[i - 1];
+    }
+    if (launch_merge(a, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
+    return MR_OK;
+}
+
+int check_effect_params(int effect, const mr_ssao_params* ssao, const mr_shadow_params* sh, const mr_ssgi_params* gi) {
+    if (effect == MR_EFFECT_SSAO) {
+        if (!ssao) return fail(MR_E_NULL, "ssao params are NULL");
+        return check_sampling(ssao->kernel, ssao->samples, ssao->radius, ssao->bias_rel);
+    }
+    if (effect == MR_EFFECT_SHADOW) return check_shadow(sh);
+    if (effect == MR_EFFECT_SSGI) {
+        if (!gi) return fail(MR_E_NULL, "ssgi params are NULL");
+        return check_sampling(gi->kernel, gi->samples, gi->radius, gi->bias_rel);
+    }
+    return fail(MR_E_PARAM, "unknown effect %d", effect);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+size_t mr_workspace_bytes(const mr_camera* cam, const mr_mask_params* mp, int purpose) {
+    if (!mp) {
+        fail(MR_E_NULL, "mask params are NULL");
+        return 0;
+    }
+    Geo g;
+    if (check_geo(cam, mp, g) || check_mask_params(mp, g)) return 0;
+    if (purpose == MR_WS_MASKS) return mask_scratch(g).bytes;
+    if (purpose != MR_EFFECT_SSAO && purpose != MR_EFFECT_SHADOW && purpose != MR_EFFECT_SSGI) {
+        fail(MR_E_PARAM, "unknown workspace purpose %d", purpose);
+        return 0;
+    }
+    return frame_layout(g, purpose).bytes;
+}
+
+int mr_build_masks(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp, const uint8_t* hard,
+                   const mr_masks* m, void* ws, size_t ws_bytes, void* stream) {
+    if (!mp) return fail(MR_E_NULL, "mask params are NULL");
+    Geo g;
+    int st = check_geo(cam, mp, g);
+    if (!st) st = check_mask_params(mp, g);
+    if (!st) st = check_gbuffer(gb, true, false);
+    if (!st) st = check_masks(m, g, true, true);
+    if (st) return st;
+    if (!m->edge) return fail(MR_E_NULL, "masks.edge is NULL");
+    if (misaligned(m->edge) || (m->level_map && misaligned(m->level_map)) || (hard && misaligned(hard)))
+        return fail(MR_E_PARAM, "edge, level_map and hard_shadow must be 16-byte aligned");
+    const size_t need = mask_scratch(g).bytes;
+    if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
+    return do_build_masks(gb, g, mp, hard, m, ws, static_cast<hipStream_t>(stream));
+}
+
+static int eval_entry(int effect, const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp,
+                      const mr_masks* m, const void* params, float* const out[kMaxLevels], void* stream) {
+    Geo g;
+    int st;
+    if (m) {
+        if (!mp) return fail(MR_E_NULL, "mask params are NULL (required with masks)");
+        st = check_geo(cam, mp, g);
+        if (!st) st = check_mask_params(mp, g);
+    } else {
+        st = check_geo(cam, nullptr, g);
+    }
+    if (!st) st = check_gbuffer(gb, effect != MR_EFFECT_SHADOW, effect == MR_EFFECT_SSGI);
+    if (!st && m) st = check_masks(m, g, false, true);
+    if (!st) st = check_outputs(out, g, !m);
+    if (!st)
+        st = check_effect_params(effect, static_cast<const mr_ssao_params*>(effect == MR_EFFECT_SSAO ? params : nullptr),
+                                 static_cast<const mr_shadow_params*>(effect == MR_EFFECT_SHADOW ? params : nullptr),
+                                 static_cast<const mr_ssgi_params*>(effect == MR_EFFECT_SSGI ? params : nullptr));
+    if (st) return st;
+    return do_eval(effect, gb, cam, g, m, params, out, static_cast<hipStream_t>(stream));
+}
+
+int mr_eval_ssao(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp, const mr_masks* m,
+                 const mr_ssao_params* p, float* const out[MR_MAX_LEVELS], void* stream) {
+    return eval_entry(MR_EFFECT_SSAO, gb, cam, mp, m, p, out, stream);
+}
+
+int mr_eval_shadow(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp, const mr_masks* m,
+                   const mr_shadow_params* p, float* const out[MR_MAX_LEVELS], void* stream) {
+    return eval_entry(MR_EFFECT_SHADOW, gb, cam, mp, m, p, out, stream);
+}
+
+int mr_eval_ssgi(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp, const mr_masks* m,
+                 const mr_ssgi_params* p, float* const out[MR_MAX_LEVELS], void* stream) {
+    return eval_entry(MR_EFFECT_SSGI, gb, cam, mp, m, p, out, stream);
+}
+
+int mr_shadow_hard(const mr_gbuffer* gb, const mr_camera* cam, const mr_shadow_params* p, uint8_t* hard,
+                   void* stream) {
+    Geo g;
+    int st = check_geo(cam, nullptr, g);
+    if (!st) st = check_gbuffer(gb, false, false);
+    if (!st) st = check_shadow(p);
+    if (st) return st;
+    if (!hard) return fail(MR_E_NULL, "hard is NULL");
+    if (misaligned(hard)) return fail(MR_E_PARAM, "hard is not 16-byte aligned");
+    HardArgs a{};
+    a.depth = gb->depth;
+    a.W = g.W;
+    a.H = g.H;
+    a.f = cam->focal_px;
+    a.sm = p->shadow_map;
+    a.size = p->sm_size;
+    memcpy(a.M, p->view_to_light, sizeof(a.M));
+    a.fL = p->light_focal_px;
+    a.bias = p->bias;
+    a.hard = hard;
+    if (launch_hard(a, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
+    return MR_OK;
+}
+
+int mr_upsample_merge(const mr_camera* cam, const mr_mask_params* mp, const mr_masks* m,
+                      const float* const level_out[MR_MAX_LEVELS], int channels, float* out, void* stream) {
+    if (!mp) return fail(MR_E_NULL, "mask params are NULL");
+    Geo g;
+    int st = check_geo(cam, mp, g);
+    if (!st) st = check_mask_params(mp, g);
+    if (!st) st = check_masks(m, g, true, false);
+    if (st) return st;
+    if (channels != 1 && channels != 3) return fail(MR_E_PARAM, "channels %d not 1 or 3", channels);
+    if (!level_out) return fail(MR_E_NULL, "level_out is NULL");
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (!level_out[i - 1]) return fail(MR_E_NULL, "level_out[%d] is NULL", i - 1);
+        if (misaligned(level_out[i - 1])) return fail(MR_E_PARAM, "level_out[%d] misaligned", i - 1);
+    }
+    if (!out) return fail(MR_E_NULL, "out is NULL");
+    if (misaligned(out)) return fail(MR_E_PARAM, "out is not 16-byte aligned");
+    return do_merge(g, mp, m, level_out, channels, out, static_cast<hipStream_t>(stream));
+}
+
+int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
+    if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int effect = d->effect;
+    int st = check_effect_params(effect, d->ssao, d->shadow, d->ssgi);
+    if (st) return st;
+    const void* params = effect == MR_EFFECT_SSAO ? (const void*)d->ssao
+                         : effect == MR_EFFECT_SHADOW ? (const void*)d->shadow : (const void*)d->ssgi;
+    if (!d->out) return fail(MR_E_NULL, "out is NULL");
+    if (misaligned(d->out)) return fail(MR_E_PARAM, "out is not 16-byte aligned");
+    const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    if (!d->multires) {
+        Geo g;
+        st = check_geo(&d->cam, nullptr, g);
+        if (!st) st = check_gbuffer(&d->g, effect != MR_EFFECT_SHADOW, effect == MR_EFFECT_SSGI);
+        if (st) return st;
+        float* out[kMaxLevels] = {d->out};
+        return do_eval(effect, &d->g, &d->cam, g, nullptr, params, out, s);
+    }
+    Geo g;
+    st = check_geo(&d->cam, &d->mp, g);
+    if (!st) st = check_mask_params(&d->mp, g);
+    if (!st) st = check_gbuffer(&d->g, true, effect == MR_EFFECT_SSGI);
+    if (st) return st;
+    if (d->level_map && misaligned(d->level_map)) return fail(MR_E_PARAM, "level_map is not 16-byte aligned");
+    const FrameLayout f = frame_layout(g, effect);
+    if (!ws || ws_bytes < f.bytes) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, f.bytes);
+    if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
+    uint8_t* b = static_cast<uint8_t*>(ws);
+    mr_masks m{};
+    m.edge = b + f.edge;
+    m.level_map = d->level_map;
+    m.count = reinterpret_cast<uint32_t*>(b + f.count);
+    float* lo[kMaxLevels] = {};
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i != g.L) {
+            m.alpha[i - 1] = reinterpret_cast<float*>(b + f.alpha[i - 1]);
+            m.stencil[i - 1] = b + f.stencil[i - 1];
+            m.worklist[i - 1] = reinterpret_cast<uint32_t*>(b + f.worklist[i - 1]);
+        }
+        if (i >= 2) m.level_depth[i - 1] = reinterpret_cast<float*>(b + f.level_depth[i - 1]);
+        lo[i - 1] = reinterpret_cast<float*>(b + f.level_out[i - 1]);
+    }
+    const uint8_t* hard = nullptr;
+    if (effect == MR_EFFECT_SHADOW) {
+        HardArgs a{};
+        a.depth = d->g.depth;
+        a.W = g.W;
+        a.H = g.H;
+        a.f = d->cam.focal_px;
+        a.sm = d->shadow->shadow_map;
+        a.size = d->shadow->sm_size;
+        memcpy(a.M, d->shadow->view_to_light, sizeof(a.M));
+        a.fL = d->shadow->light_focal_px;
+        a.bias = d->shadow->bias;
+        a.hard = b + f.hard;
+        if (launch_hard(a, s) != hipSuccess) return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
+        hard = b + f.hard;
+    }
+    st = do_build_masks(&d->g, g, &d->mp, hard, &m, b + f.scratch, s);
+    if (st) return st;
+    st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s);
+    if (st) return st;
+    const float* clo[kMaxLevels];
+    for (int k = 0; k < kMaxLevels; ++k) clo[k] = lo[k];
+    return do_merge(g, &d->mp, &m, clo, C, d->out, s);
+}
+
+const char* mr_status_string(int status) {
+    switch (status) {
+        case MR_OK: return "MR_OK";
+        case MR_E_NULL: return "MR_E_NULL: a required pointer is NULL";
+        case MR_E_SHAPE: return "MR_E_SHAPE: invalid image or map size";
+        case MR_E_PARAM: return "MR_E_PARAM: parameter out of range or pointer misaligned";
+        case MR_E_WORKSPACE: return "MR_E_WORKSPACE: workspace too small";
+        case MR_E_DTYPE: return "MR_E_DTYPE: unsupported element type";
+        case MR_E_DEVICE: return "MR_E_DEVICE: HIP launch failed";
+        default: return "unknown status";
+    }
+}
+
+const char* mr_last_error(void) { return g_err; }
+
+int mr_version(void) { return MR_VERSION; }
+
+}  // extern "C"

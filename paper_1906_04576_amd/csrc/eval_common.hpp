@@ -1,0 +1,67 @@
+// Shared pieces of the per-level evaluation kernels (Sec. 3.2 / 4.1): the
+// mapping of a flat item index onto (level, texel) over the work lists and
+// the dense coarsest level, and the view-space position of a texel.
+#pragma once
+
+#include "mr_internal.hpp"
+
+namespace mr {
+
+// Item ranges: level j owns items [cum[j], cum[j+1]); list levels take their
+// length from the device counts, dense levels from dense_n.
+struct ItemMap {
+    unsigned cum[kMaxLevels + 1];
+    int nlev;
+};
+
+__device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
+    ItemMap m;
+    m.nlev = c.nlev;
+    m.cum[0] = 0;
+    for (int j = 0; j < c.nlev; ++j) {
+        // a list never holds more entries than its level has texels
+        const unsigned n = c.lv[j].list ? min(c.counts[c.lv[j].count_idx], c.lv[j].dense_n) : c.lv[j].dense_n;
+        m.cum[j + 1] = m.cum[j] + n;
+    }
+    return m;
+}
+
+__device__ __forceinline__ int item_level(const ItemMap& m, unsigned item) {
+    int j = 0;
+    while (j + 1 < m.nlev && item >= m.cum[j + 1]) ++j;
+    return j;
+}
+
+// P = (X z, Y z, -z), X = ((x + 0.5) - cx) / f, Y = (cy - (y + 0.5)) / f
+__device__ __forceinline__ void view_pos(int x, int y, float z, float f, float cx, float cy,
+                                         float& px, float& py, float& pz) {
+    const float X = (((float)x + 0.5f) - cx) / f;
+    const float Y = (cy - ((float)y + 0.5f)) / f;
+    px = X * z;
+    py = Y * z;
+    pz = -z;
+}
+
+// Duff et al. 2017 branch-free orthonormal basis around n
+__device__ __forceinline__ void onb(float nx, float ny, float nz, float& tx, float& ty, float& tz,
+                                    float& bx, float& by, float& bz) {
+    const float sg = copysignf(1.0f, nz);
+    const float a = -1.0f / (sg + nz);
+    const float b = (nx * ny) * a;
+    tx = 1.0f + ((sg * (nx * nx)) * a);
+    ty = sg * b;
+    tz = -(sg * nx);
+    bx = b;
+    by = sg + ((ny * ny) * a);
+    bz = -ny;
+}
+
+// grid for a grid-stride evaluation pass over `total_hint` items at most
+__host__ inline unsigned eval_blocks(unsigned total_hint) {
+    unsigned b = (total_hint + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return b;
+}
+
+}  // namespace mr

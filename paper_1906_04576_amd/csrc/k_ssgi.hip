@@ -1,0 +1,98 @@
+// One-bounce screen-space indirect light (Sec. 2.4, after Ritschel et al.
+// 2009).  The SSAO sampling and occlusion test are reused; every occluding
+// sample adds the directly lit colour of the texel it hit, weighted as a
+// small patch sending light to the receiver:
+//   v = X_t - P, dd = dot(v, v), dist2 = max(dd, (0.1 r)^2),
+//   v_hat = v / sqrt(dd), g = (max(0, n.v_hat) max(0, -n_t.v_hat)) / dist2,
+//   acc += C_t g;  out = acc (r^2 / S).
+#include "eval_common.hpp"
+
+namespace mr {
+
+template <typename NT, typename CT>
+__global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
+    const ItemMap m = make_item_map(a.c);
+    const unsigned total = m.cum[m.nlev];
+    const NT* nrm = static_cast<const NT*>(a.c.normal);
+    const CT* col = static_cast<const CT*>(a.c.color);
+    const long long plane = a.c.plane;
+    const float r = a.r, b = a.b;
+    const int S = a.S;
+    const float rmin = 0.1f * r;
+    const float rmin2 = rmin * rmin;
+    const float scale = (r * r) / (float)S;
+    for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+        const int j = item_level(m, item);
+        const EvalLevel& L = a.c.lv[j];
+        const unsigned local = item - m.cum[j];
+        const unsigned t = L.list ? L.list[local] : local;
+        if (t >= L.dense_n) continue;  // malformed list entry
+        const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
+        const float z = L.z[(long long)y * L.zpy + (long long)x * L.zpx];
+        float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+        if (valid_depth(z)) {
+            const long long g = L.goff + (long long)y * L.gpy + (long long)x * L.gpx;
+            const float nx = ld(nrm, g), ny = ld(nrm, plane + g), nz = ld(nrm, 2 * plane + g);
+            float px, py, pz;
+            view_pos(x, y, z, L.f, L.cx, L.cy, px, py, pz);
+            float tx, ty, tz, bx, by, bz;
+            onb(nx, ny, nz, tx, ty, tz, bx, by, bz);
+            const float rtx = r * tx, rty = r * ty, rtz = r * tz;
+            const float rbx = r * bx, rby = r * by, rbz = r * bz;
+            const float rnx = r * nx, rny = r * ny, rnz = r * nz;
+            const float Wf = (float)L.W, Hf = (float)L.H;
+            for (int s = 0; s < S; ++s) {
+                const float kx = a.kernel[3 * s], ky = a.kernel[3 * s + 1], kz = a.kernel[3 * s + 2];
+                const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
+                const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
+                const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
+                const float d = -qz;
+                if (!(d > 0.0f)) continue;
+                const float inv = 1.0f / d;
+                const float u = L.cx + (qx * inv) * L.f;
+                const float v = L.cy - (qy * inv) * L.f;
+                if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
+                const int sx = (int)floorf(u), sy = (int)floorf(v);
+                const float zs = L.z[(long long)sy * L.zpy + (long long)sx * L.zpx];
+                if (!valid_depth(zs)) continue;
+                if (!(zs < d - (b * d) && fabsf(z - zs) < r)) continue;
+                float hx, hy, hz;
+                view_pos(sx, sy, zs, L.f, L.cx, L.cy, hx, hy, hz);
+                const float vx = hx - px, vy = hy - py, vz = hz - pz;
+                const float dd = ((vx * vx) + (vy * vy)) + (vz * vz);
+                if (!(dd > 0.0f)) continue;
+                const float dist2 = fmaxf(dd, rmin2);
+                const float il = 1.0f / sqrtf(dd);
+                const float vhx = vx * il, vhy = vy * il, vhz = vz * il;
+                const long long gt = L.goff + (long long)sy * L.gpy + (long long)sx * L.gpx;
+                const float mx = ld(nrm, gt), my = ld(nrm, plane + gt), mz = ld(nrm, 2 * plane + gt);
+                const float cr = fmaxf(0.0f, ((nx * vhx) + (ny * vhy)) + (nz * vhz));
+                const float ce = fmaxf(0.0f, -(((mx * vhx) + (my * vhy)) + (mz * vhz)));
+                const float w = (cr * ce) / dist2;
+                acc0 = acc0 + ld(col, gt) * w;
+                acc1 = acc1 + ld(col, plane + gt) * w;
+                acc2 = acc2 + ld(col, 2 * plane + gt) * w;
+            }
+        }
+        const long long o = (long long)y * L.W + x;
+        L.out[o] = acc0 * scale;
+        L.out[L.out_plane + o] = acc1 * scale;
+        L.out[2 * L.out_plane + o] = acc2 * scale;
+    }
+}
+
+hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
+                       hipStream_t s) {
+    const unsigned nb = eval_blocks(total_hint);
+    if (normal_dtype == MR_F16 && color_dtype == MR_F16)
+        hipLaunchKernelGGL((k_ssgi<_Float16, _Float16>), dim3(nb), dim3(256), 0, s, a);
+    else if (normal_dtype == MR_F16)
+        hipLaunchKernelGGL((k_ssgi<_Float16, float>), dim3(nb), dim3(256), 0, s, a);
+    else if (color_dtype == MR_F16)
+        hipLaunchKernelGGL((k_ssgi<float, _Float16>), dim3(nb), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_ssgi<float, float>), dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mr

@@ -1,0 +1,182 @@
+// Internal declarations shared by the host API and the HIP kernels of libmr.
+// Nothing here is part of the public C ABI (include/mr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mr.h"
+
+namespace mr {
+
+constexpr int kMaxLevels = MR_MAX_LEVELS;
+constexpr int kMaxRadius = MR_MAX_RADIUS;
+constexpr int kChunk = 4096;  // texels per compaction chunk (256 threads x 16)
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool valid_depth(float z) {
+    // geometry iff finite and > 0 (inf and NaN fail both tests below)
+    return z > 0.0f && z < __builtin_inff();
+}
+
+template <typename T>
+__device__ __forceinline__ float ld(const T* p, long long i) {
+    return static_cast<float>(p[i]);
+}
+
+// Blocks of a 1-D grid are handed to the 8 XCDs round robin (block b runs on
+// XCD b % 8).  Remap so that every XCD works on one contiguous range of tiles:
+// neighbouring tiles then share that XCD's L2 (halo rows and columns hit).
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned n) {
+    const unsigned q = n >> 3, rem = n & 7u, x = b & 7u, k = b >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
+// ---------------------------------------------------------------------------
+// argument blocks (passed by value to the kernels)
+// ---------------------------------------------------------------------------
+struct EdgeArgs {
+    const float* depth;
+    const void* normal;
+    const uint8_t* hard;  // optional one-sample shadow bits
+    int W, H;
+    float depth_ratio, normal_cos;
+    uint8_t* E;                          // full-res edges
+    uint8_t* Ei[kMaxLevels];             // pooled edges per level (null = not needed)
+    float* zi[kMaxLevels];               // point-sampled level depth (null = not needed)
+    int Wi[kMaxLevels], Hi[kMaxLevels];
+    int num_levels;
+};
+
+struct BlurArgs {
+    const uint8_t* Ei;
+    float* a;
+    uint8_t* S;
+    int W, H, r;
+    float g[2 * kMaxRadius + 1];
+};
+
+struct NestArgs {
+    const uint8_t* Sf;  // finer stencil
+    uint8_t* Sc;        // coarser stencil (updated in place)
+    int Wf, Hf, Wc, Hc, k;
+};
+
+struct LevelMapArgs {
+    const uint8_t* S[kMaxLevels];
+    int Wi[kMaxLevels];
+    int levels[kMaxLevels];  // enabled levels ascending (1-based); last = coarsest
+    int nlev;
+    int W, H;
+    uint8_t* out;
+};
+
+struct CompactArgs {
+    const uint8_t* S[kMaxLevels];
+    uint32_t* list[kMaxLevels];
+    uint32_t n[kMaxLevels];          // texels per compacted level
+    uint32_t chunk_base[kMaxLevels + 1];
+    int count_idx[kMaxLevels];       // index into count[] per compacted level
+    int nlev;                        // compacted levels
+    uint32_t* chunk_count;           // [total chunks]
+    uint32_t* chunk_off;             // [total chunks]
+    uint32_t* count;                 // [MR_MAX_LEVELS]
+};
+
+// One level of an evaluation pass.  Depth of texel (x, y) is
+// z[y * zpy + x * zpx]; normals and colour of texel (x, y) sit at full-res
+// element index goff + y * gpy + x * gpx of their planes.
+struct EvalLevel {
+    const float* z;
+    long long zpy;
+    int zpx;
+    long long goff, gpy;
+    int gpx;
+    int W, H;
+    float f, cx, cy;
+    float* out;
+    long long out_plane;
+    const uint32_t* list;  // null = dense
+    int count_idx;         // list length = counts[count_idx]
+    unsigned dense_n;
+};
+
+struct EvalCommon {
+    EvalLevel lv[kMaxLevels];
+    int nlev;
+    const uint32_t* counts;
+    const void* normal;
+    const void* color;
+    long long plane;  // H * W, full-res plane stride of normal/colour
+};
+
+struct SsaoArgs {
+    EvalCommon c;
+    const float* kernel;
+    int S;
+    float r, b;
+};
+
+struct ShadowArgs {
+    EvalCommon c;
+    const float* sm;
+    int size;
+    float M[12];
+    float fL, lsize, nL, bias;
+    const float* bd;
+    const float* pd;
+    int nb, np;
+};
+
+struct SsgiArgs {
+    EvalCommon c;
+    const float* kernel;
+    int S;
+    float r, b;
+};
+
+struct HardArgs {
+    const float* depth;
+    int W, H;
+    float f;
+    const float* sm;
+    int size;
+    float M[12];
+    float fL, bias;
+    uint8_t* hard;
+};
+
+struct MergeLevel {
+    const float* c;
+    long long c_plane;
+    const float* a;     // null for the coarsest
+    const uint8_t* S;   // null for the coarsest
+    int s, W, H;
+    float w;
+};
+
+struct MergeArgs {
+    MergeLevel lv[kMaxLevels];  // enabled levels ascending; last = coarsest
+    int nlev;
+    int W, H, C;
+    float* out;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (return hipSuccess or the launch error)
+// ---------------------------------------------------------------------------
+hipError_t launch_edges(const EdgeArgs& a, int normal_dtype, hipStream_t s);
+hipError_t launch_blur(const BlurArgs& a, hipStream_t s);
+hipError_t launch_nest(const NestArgs& a, hipStream_t s);
+hipError_t launch_level_map(const LevelMapArgs& a, hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
+hipError_t launch_ssao(const SsaoArgs& a, int normal_dtype, unsigned total_hint, hipStream_t s);
+hipError_t launch_hard(const HardArgs& a, hipStream_t s);
+hipError_t launch_shadow(const ShadowArgs& a, unsigned total_hint, hipStream_t s);
+hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
+                       hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+
+}  // namespace mr

@@ -1,0 +1,447 @@
+"""Python binding of libmr (include/mr.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and takes
+torch tensors that already live on the GPU; each step of the lighting path
+runs in the HIP kernels of libmr.so.  PyTorch supplies device memory and the
+current stream.  If libmr.so is missing or fails to load, every call raises:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmr.so")
+
+MR_MAX_LEVELS = 6
+MR_OK, MR_E_NULL, MR_E_SHAPE, MR_E_PARAM, MR_E_WORKSPACE, MR_E_DTYPE, MR_E_DEVICE = 0, -1, -2, -3, -4, -5, -6
+MR_F32, MR_F16 = 0, 1
+MR_EFFECT_SSAO, MR_EFFECT_SHADOW, MR_EFFECT_SSGI = 0, 1, 2
+MR_WS_MASKS = -1
+EFFECTS = {"ssao": MR_EFFECT_SSAO, "shadow": MR_EFFECT_SHADOW, "ssgi": MR_EFFECT_SSGI}
+
+c_float6 = ctypes.c_float * MR_MAX_LEVELS
+c_int6 = ctypes.c_int * MR_MAX_LEVELS
+c_ptr6 = ctypes.c_void_p * MR_MAX_LEVELS
+
+
+class mr_gbuffer(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("normal_dtype", ctypes.c_int),
+                ("color", ctypes.c_void_p), ("color_dtype", ctypes.c_int)]
+
+
+class mr_camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int), ("focal_px", ctypes.c_float)]
+
+
+class mr_mask_params(ctypes.Structure):
+    _fields_ = [("num_levels", ctypes.c_int), ("level_enable", ctypes.c_uint32),
+                ("depth_ratio", ctypes.c_float), ("normal_cos", ctypes.c_float),
+                ("sigma2", c_float6), ("weight", c_float6), ("radius", c_int6)]
+
+
+class mr_masks(ctypes.Structure):
+    _fields_ = [("edge", ctypes.c_void_p), ("level_map", ctypes.c_void_p), ("alpha", c_ptr6),
+                ("stencil", c_ptr6), ("worklist", c_ptr6), ("level_depth", c_ptr6),
+                ("count", ctypes.c_void_p)]
+
+
+class mr_ssao_params(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_void_p), ("samples", ctypes.c_int), ("radius", ctypes.c_float),
+                ("bias_rel", ctypes.c_float)]
+
+
+mr_ssgi_params = mr_ssao_params
+
+
+class mr_shadow_params(ctypes.Structure):
+    _fields_ = [("shadow_map", ctypes.c_void_p), ("sm_size", ctypes.c_int),
+                ("view_to_light", ctypes.c_float * 12), ("light_focal_px", ctypes.c_float),
+                ("light_size", ctypes.c_float), ("light_near", ctypes.c_float), ("bias", ctypes.c_float),
+                ("blocker_disk", ctypes.c_void_p), ("pcf_disk", ctypes.c_void_p),
+                ("n_blocker", ctypes.c_int), ("n_pcf", ctypes.c_int)]
+
+
+class mr_frame_desc(ctypes.Structure):
+    _fields_ = [("effect", ctypes.c_int), ("multires", ctypes.c_int), ("g", mr_gbuffer),
+                ("cam", mr_camera), ("mp", mr_mask_params),
+                ("ssao", ctypes.POINTER(mr_ssao_params)), ("shadow", ctypes.POINTER(mr_shadow_params)),
+                ("ssgi", ctypes.POINTER(mr_ssgi_params)), ("out", ctypes.c_void_p),
+                ("level_map", ctypes.c_void_p)]
+
+
+# entry points and their ctypes signatures (also used by the export test)
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "mr_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params), ctypes.c_int]),
+    "mr_build_masks": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
+                                      ctypes.POINTER(mr_mask_params), _P, ctypes.POINTER(mr_masks), _P,
+                                      ctypes.c_size_t, _P]),
+    "mr_eval_ssao": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
+                                    ctypes.POINTER(mr_mask_params), ctypes.POINTER(mr_masks),
+                                    ctypes.POINTER(mr_ssao_params), ctypes.POINTER(c_ptr6), _P]),
+    "mr_shadow_hard": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
+                                      ctypes.POINTER(mr_shadow_params), _P, _P]),
+    "mr_eval_shadow": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
+                                      ctypes.POINTER(mr_mask_params), ctypes.POINTER(mr_masks),
+                                      ctypes.POINTER(mr_shadow_params), ctypes.POINTER(c_ptr6), _P]),
+    "mr_eval_ssgi": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
+                                    ctypes.POINTER(mr_mask_params), ctypes.POINTER(mr_masks),
+                                    ctypes.POINTER(mr_ssgi_params), ctypes.POINTER(c_ptr6), _P]),
+    "mr_upsample_merge": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
+                                         ctypes.POINTER(mr_masks), ctypes.POINTER(c_ptr6), ctypes.c_int, _P, _P]),
+    "mr_frame": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P, ctypes.c_size_t, _P]),
+    "mr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mr_last_error": (ctypes.c_char_p, []),
+    "mr_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+class MRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def lib():
+    """The loaded libmr.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libmr.so not built at {LIB_PATH}; run paper_1906_04576_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != MR_OK:
+        raise MRError(status, lib().mr_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# parameter marshalling
+# ---------------------------------------------------------------------------
+@dataclass
+class MaskParams:
+    """Sec. 3.1 / Table 1 mask parameters (see mr_mask_params in mr.h)."""
+    num_levels: int = 4
+    level_enable: int = 0xF
+    depth_ratio: float = 0.05
+    normal_cos: float = math.cos(math.radians(25.0))
+    sigma2: tuple = (0.924, 1.848, 3.696, 0.0)
+    weight: tuple = (100.0, 50.0, 20.0, 1.0)
+    radius: tuple = (-1, -1, -1, -1)
+
+    def levels(self):
+        return [i for i in range(1, self.num_levels + 1) if (self.level_enable >> (i - 1)) & 1]
+
+    def c(self) -> mr_mask_params:
+        p = mr_mask_params()
+        p.num_levels = self.num_levels
+        p.level_enable = self.level_enable
+        p.depth_ratio = self.depth_ratio
+        p.normal_cos = self.normal_cos
+        for i in range(MR_MAX_LEVELS):
+            p.sigma2[i] = self.sigma2[i] if i < len(self.sigma2) else 0.0
+            p.weight[i] = self.weight[i] if i < len(self.weight) else 1.0
+            p.radius[i] = self.radius[i] if i < len(self.radius) else -1
+        return p
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dt(t):
+    if t is None:
+        return MR_F32
+    if t.dtype == torch.float32:
+        return MR_F32
+    if t.dtype == torch.float16:
+        return MR_F16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev(t, what, dtypes=(torch.float32,)):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{what} has dtype {t.dtype}")
+
+
+def gbuffer(depth, normal=None, color=None) -> mr_gbuffer:
+    _dev(depth, "depth")
+    _dev(normal, "normal", (torch.float32, torch.float16))
+    _dev(color, "color", (torch.float32, torch.float16))
+    return mr_gbuffer(_ptr(depth), _ptr(normal), _dt(normal), _ptr(color), _dt(color))
+
+
+def camera(width, height, focal) -> mr_camera:
+    return mr_camera(int(width), int(height), float(focal))
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def level_dims(W, H, i):
+    return W >> (i - 1), H >> (i - 1)
+
+
+@dataclass
+class Masks:
+    """Device tensors of one mask pyramid (see mr_masks in mr.h)."""
+    W: int
+    H: int
+    mp: MaskParams
+    edge: torch.Tensor
+    count: torch.Tensor
+    level_map: torch.Tensor = None
+    alpha: dict = field(default_factory=dict)
+    stencil: dict = field(default_factory=dict)
+    worklist: dict = field(default_factory=dict)
+    level_depth: dict = field(default_factory=dict)
+    workspace: torch.Tensor = None
+
+    def c(self) -> mr_masks:
+        m = mr_masks()
+        m.edge = _ptr(self.edge)
+        m.level_map = _ptr(self.level_map)
+        m.count = _ptr(self.count)
+        for i, t in self.alpha.items():
+            m.alpha[i - 1] = t.data_ptr()
+        for i, t in self.stencil.items():
+            m.stencil[i - 1] = t.data_ptr()
+        for i, t in self.worklist.items():
+            m.worklist[i - 1] = t.data_ptr()
+        for i, t in self.level_depth.items():
+            m.level_depth[i - 1] = t.data_ptr()
+        return m
+
+
+def mr_workspace_bytes(W, H, focal, mp: MaskParams, purpose) -> int:
+    cam = camera(W, H, focal)
+    cmp = mp.c()
+    n = lib().mr_workspace_bytes(ctypes.byref(cam), ctypes.byref(cmp), int(purpose))
+    if n == 0:
+        raise MRError(MR_E_PARAM, lib().mr_last_error().decode())
+    return int(n)
+
+
+def alloc_masks(W, H, focal, mp: MaskParams, device="cuda", level_map=True, level_depth=True) -> Masks:
+    levels = mp.levels()
+    L = levels[-1]
+    u8 = dict(dtype=torch.uint8, device=device)
+    f32 = dict(dtype=torch.float32, device=device)
+    m = Masks(W, H, mp, edge=torch.empty((H, W), **u8), count=torch.zeros(8, dtype=torch.int32, device=device))
+    if level_map:
+        m.level_map = torch.empty((H, W), **u8)
+    for i in levels:
+        Wi, Hi = level_dims(W, H, i)
+        if i != L:
+            m.alpha[i] = torch.empty((Hi, Wi), **f32)
+            m.stencil[i] = torch.empty((Hi, Wi), **u8)
+            m.worklist[i] = torch.empty(Hi * Wi, dtype=torch.int32, device=device)
+        if i >= 2 and level_depth:
+            m.level_depth[i] = torch.empty((Hi, Wi), **f32)
+    nws = mr_workspace_bytes(W, H, focal, mp, MR_WS_MASKS)
+    m.workspace = torch.empty(nws, **u8)
+    return m
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+def mr_build_masks(depth, normal, focal, mp: MaskParams, hard_shadow=None, masks: Masks = None,
+                   level_map=True, level_depth=True, stream=None) -> Masks:
+    H, W = depth.shape
+    if masks is None:
+        masks = alloc_masks(W, H, focal, mp, depth.device, level_map, level_depth)
+    _dev(hard_shadow, "hard_shadow", (torch.uint8,))
+    g = gbuffer(depth, normal)
+    cam = camera(W, H, focal)
+    cmp = mp.c()
+    cm = masks.c()
+    _check(lib().mr_build_masks(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cmp), _ptr(hard_shadow),
+                                ctypes.byref(cm), _ptr(masks.workspace), masks.workspace.numel(),
+                                _stream(stream)))
+    return masks
+
+
+def _level_outputs(W, H, levels, C, device, plain):
+    out = {}
+    for i in ([1] if plain else levels):
+        Wi, Hi = level_dims(W, H, i)
+        shape = (C, Hi, Wi) if C > 1 else (Hi, Wi)
+        out[i] = torch.full(shape, float("nan"), dtype=torch.float32, device=device)
+    return out
+
+
+def _eval(name, g, W, H, focal, mp, masks, params_c, C, out, stream):
+    levels = mp.levels() if masks is not None else [1]
+    if out is None:
+        out = _level_outputs(W, H, levels, C, g_device(g), masks is None)
+    arr = c_ptr6()
+    for i, t in out.items():
+        arr[i - 1] = t.data_ptr()
+    cam = camera(W, H, focal)
+    cmp = mp.c() if mp is not None else None
+    cm = masks.c() if masks is not None else None
+    fn = getattr(lib(), name)
+    _check(fn(ctypes.byref(g[0]), ctypes.byref(cam), ctypes.byref(cmp) if cmp is not None else None,
+              ctypes.byref(cm) if cm is not None else None, ctypes.byref(params_c), ctypes.byref(arr),
+              _stream(stream)))
+    return out
+
+
+def g_device(g):
+    return g[1]
+
+
+def ssao_params(kernel, radius, bias_rel) -> mr_ssao_params:
+    _dev(kernel, "kernel")
+    return mr_ssao_params(_ptr(kernel), int(kernel.shape[0]), float(radius), float(bias_rel))
+
+
+def mr_eval_ssao(depth, normal, focal, kernel, radius, bias_rel, mp: MaskParams = None, masks: Masks = None,
+                 out=None, stream=None):
+    """Per-level SSAO (masks given) or the naive full-resolution pass."""
+    H, W = depth.shape
+    p = ssao_params(kernel, radius, bias_rel)
+    return _eval("mr_eval_ssao", (gbuffer(depth, normal), depth.device), W, H, focal, mp, masks, p, 1, out,
+                 stream)
+
+
+def shadow_params(shadow_map, view_to_light, light_focal, light_size, light_near, bias, blocker_disk,
+                  pcf_disk) -> mr_shadow_params:
+    _dev(shadow_map, "shadow_map")
+    _dev(blocker_disk, "blocker_disk")
+    _dev(pcf_disk, "pcf_disk")
+    p = mr_shadow_params()
+    p.shadow_map = _ptr(shadow_map)
+    p.sm_size = int(shadow_map.shape[0])
+    m = [float(v) for v in list(view_to_light.reshape(-1))]
+    for k in range(12):
+        p.view_to_light[k] = m[k]
+    p.light_focal_px = float(light_focal)
+    p.light_size = float(light_size)
+    p.light_near = float(light_near)
+    p.bias = float(bias)
+    p.blocker_disk = _ptr(blocker_disk)
+    p.pcf_disk = _ptr(pcf_disk)
+    p.n_blocker = int(blocker_disk.shape[0])
+    p.n_pcf = int(pcf_disk.shape[0])
+    return p
+
+
+def mr_shadow_hard(depth, focal, sp: mr_shadow_params, hard=None, stream=None):
+    H, W = depth.shape
+    if hard is None:
+        hard = torch.empty((H, W), dtype=torch.uint8, device=depth.device)
+    g = gbuffer(depth)
+    cam = camera(W, H, focal)
+    _check(lib().mr_shadow_hard(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(sp), _ptr(hard), _stream(stream)))
+    return hard
+
+
+def mr_eval_shadow(depth, focal, sp: mr_shadow_params, mp: MaskParams = None, masks: Masks = None, out=None,
+                   stream=None):
+    H, W = depth.shape
+    return _eval("mr_eval_shadow", (gbuffer(depth), depth.device), W, H, focal, mp, masks, sp, 1, out, stream)
+
+
+def mr_eval_ssgi(depth, normal, color, focal, kernel, radius, bias_rel, mp: MaskParams = None,
+                 masks: Masks = None, out=None, stream=None):
+    H, W = depth.shape
+    p = ssao_params(kernel, radius, bias_rel)
+    return _eval("mr_eval_ssgi", (gbuffer(depth, normal, color), depth.device), W, H, focal, mp, masks, p, 3,
+                 out, stream)
+
+
+def mr_upsample_merge(focal, mp: MaskParams, masks: Masks, level_out: dict, channels=1, out=None, stream=None):
+    W, H = masks.W, masks.H
+    if out is None:
+        shape = (channels, H, W) if channels > 1 else (H, W)
+        out = torch.empty(shape, dtype=torch.float32, device=masks.edge.device)
+    arr = c_ptr6()
+    for i, t in level_out.items():
+        arr[i - 1] = t.data_ptr()
+    cam = camera(W, H, focal)
+    cmp = mp.c()
+    cm = masks.c()
+    _check(lib().mr_upsample_merge(ctypes.byref(cam), ctypes.byref(cmp), ctypes.byref(cm), ctypes.byref(arr),
+                                   int(channels), _ptr(out), _stream(stream)))
+    return out
+
+
+class FrameRunner:
+    """Pre-marshalled mr_frame call: the descriptor and workspace are built
+    once so that repeated calls cost one ctypes call each."""
+
+    def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
+                 out=None, level_map=None):
+        self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
+        H, W = depth.shape
+        C = 3 if self.effect == MR_EFFECT_SSGI else 1
+        self.out = out if out is not None else torch.empty((C, H, W) if C > 1 else (H, W), dtype=torch.float32,
+                                                           device=depth.device)
+        d = mr_frame_desc()
+        d.effect = self.effect
+        d.multires = 1 if multires else 0
+        d.g = gbuffer(depth, normal, color)
+        d.cam = camera(W, H, focal)
+        d.mp = mp.c()
+        self._params = params
+        if self.effect == MR_EFFECT_SSAO:
+            d.ssao = ctypes.pointer(params)
+        elif self.effect == MR_EFFECT_SHADOW:
+            d.shadow = ctypes.pointer(params)
+        else:
+            d.ssgi = ctypes.pointer(params)
+        d.out = _ptr(self.out)
+        d.level_map = _ptr(level_map)
+        self.desc = d
+        self._keep = (depth, normal, color, level_map)
+        nws = mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0
+        self.workspace = torch.empty(max(nws, 256), dtype=torch.uint8, device=depth.device)
+        self._fn = lib().mr_frame
+        self._ws = _ptr(self.workspace)
+        self._nws = self.workspace.numel()
+
+    def __call__(self, stream=None):
+        _check(self._fn(ctypes.byref(self.desc), self._ws, self._nws, _stream(stream)))
+        return self.out
+
+
+def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,
+             level_map=None, stream=None):
+    return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map)(stream)
+
+
+def mr_version() -> int:
+    return lib().mr_version()
+
+
+def mr_status_string(status: int) -> str:
+    return lib().mr_status_string(int(status)).decode()
+
+
+def mr_last_error() -> str:
+    return lib().mr_last_error().decode()
