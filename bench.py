@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Multi-resolution vs naive full-resolution SSAO at 3840x2160 on one MI355X.
+
+Workload: the seeded box/sphere scene generator (200 boxes + 50 spheres on a
+ground plane) at 3840x2160, 4 levels (full, 1/2, 1/4, 1/8) with the SSAO
+column of Table 1, SSAO with 32 samples and radius 1.0, edge thresholds 0.05
+(depth ratio) and 25 degrees (normals).  3 scene seeds x 8 orbit cameras = 24
+configurations stay resident in HBM (3.2 GB, far above the 256 MB
+Infinity Cache) and the timed frames cycle through them.
+
+One step = one multi-resolution frame through mr_frame: edge image + level
+G-buffers, mask blur/stencils, work-list compaction, per-level SSAO and the
+Eq. 1 merge.  The naive full-resolution pass is timed the same way for the
+speedup.  Progress goes to stderr; stdout gets one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x GHz: non-packed FP32 lane-ops/s
+SSAO_OPS_PER_SAMPLE = 41        # algorithmic FP32 operations of one SSAO sample
+SSAO_OPS_PER_TEXEL = 40         # per evaluated texel outside the sample loop
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=240)
+    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--width", type=int, default=3840)
+    ap.add_argument("--height", type=int, default=2160)
+    ap.add_argument("--samples", type=int, default=32)
+    ap.add_argument("--radius", type=float, default=1.0)
+    ap.add_argument("--seeds", type=int, default=3)
+    ap.add_argument("--cameras", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stages", action="store_true")
+    ap.add_argument("--plain", action="store_true", help="profile helper: time only the naive pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profile helper: first run a 256 MiB device-to-device copy (known HBM traffic)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the multi-resolution path is one frame per GPU "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import scenegen
+    from paper_1906_04576_amd import mr
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration copy: 3 x 256 MiB device-to-device")
+    W, H, S = args.width, args.height, args.samples
+    mp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=scenegen.TABLE1["ssao"]["sigma2"],
+                       weight=scenegen.TABLE1["ssao"]["weight"])
+    K = scenegen.ssao_kernel(S)
+    kdev = torch.from_numpy(K).to(dev)
+    sp = mr.ssao_params(kdev, args.radius, 0.02)
+
+    # ---------------- resident inputs ----------------
+    t0 = time.time()
+    frames = []
+    for seed in range(1, args.seeds + 1):
+        scene = scenegen.make_scene(seed, 200, 50)
+        for cam in range(args.cameras):
+            gb = scenegen.render_gbuffer(scene, scenegen.orbit_view(cam), W, H)
+            frames.append(dict(seed=seed, cam=cam, gb=gb, d=torch.from_numpy(gb.depth).to(dev),
+                               n=torch.from_numpy(gb.normal).to(dev)))
+    focal = frames[0]["gb"].focal
+    log(f"[bench] {len(frames)} configurations at {W}x{H} generated and resident in {time.time() - t0:.1f}s")
+
+    ws = torch.empty(mr.mr_workspace_bytes(W, H, focal, mp, mr.MR_EFFECT_SSAO), dtype=torch.uint8, device=dev)
+    multi = [mr.FrameRunner("ssao", f["d"], f["n"], focal, mp, True, params=sp, workspace=ws) for f in frames]
+    plain = [mr.FrameRunner("ssao", f["d"], f["n"], focal, mp, False, params=sp) for f in frames]
+    nf = len(frames)
+
+    def timed(runners, steps, warm):
+        for k in range(warm):
+            runners[k % nf]()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t_start = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record()
+            runners[k % nf]()
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        return wall, lat
+
+    if args.plain:
+        wall, lat = timed(plain, args.steps, args.warmup)
+        log(f"[bench] plain {args.steps} frames {wall * 1e3 / args.steps:.3f} ms/frame")
+        return
+
+    wall_m, lat_m = timed(multi, args.steps, args.warmup)
+    log(f"[bench] multi-res: {wall_m * 1e3 / args.steps:.3f} ms/frame")
+    wall_p, lat_p = timed(plain, args.steps, args.warmup)
+    log(f"[bench] plain:     {wall_p * 1e3 / args.steps:.3f} ms/frame")
+
+    npx = W * H
+    value = npx * args.steps / wall_m / 1e6
+    plain_mpx = npx * args.steps / wall_p / 1e6
+
+    # ---------------- quality: multi-res vs naive on every configuration ----------------
+    mads, rmss, covs = [], [], []
+    lm = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    for k in range(nf):
+        a = multi[k]().clone()
+        b = plain[k]()
+        diff = (a - b).double()
+        mads.append(float(diff.abs().mean()))
+        rmss.append(float(diff.pow(2).mean().sqrt()))
+
+    # ---------------- per-stage timing through the separate entry points ----------------
+    stages = {}
+    roofline = None
+    if not args.no_stages:
+        masks = mr.alloc_masks(W, H, focal, mp, dev, level_map=False)
+        lo = {i: torch.empty((H >> (i - 1), W >> (i - 1)), dtype=torch.float32, device=dev) for i in (1, 2, 3, 4)}
+        lo_plain = {1: torch.empty((H, W), dtype=torch.float32, device=dev)}
+        out = torch.empty((H, W), dtype=torch.float32, device=dev)
+        reps = min(nf, 24)
+        names = ["build_masks", "eval_ssao_multi", "merge", "eval_ssao_plain"]
+        ev = {s: [] for s in names}
+        counts = []
+        calls = []
+        for k in range(reps):
+            f = frames[k]
+            calls.append((mr.prepare_build_masks(f["d"], f["n"], focal, mp, masks),
+                          mr.prepare_eval_ssao(f["d"], f["n"], focal, sp, lo, mp=mp, masks=masks),
+                          mr.prepare_upsample_merge(focal, mp, masks, lo, out),
+                          mr.prepare_eval_ssao(f["d"], f["n"], focal, sp, lo_plain)))
+        # the pre-marshalled calls keep the stream ahead of the host, so the
+        # events bracket back-to-back GPU work of each stage
+        for rep in range(2):
+            plain[0]()
+            for k in range(reps):
+                build, ev_m, merge, ev_p = calls[k]
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                e[0].record()
+                build()
+                e[1].record()
+                ev_m()
+                e[2].record()
+                merge()
+                e[3].record()
+                ev_p()
+                e[4].record()
+                if rep == 1:
+                    ev["build_masks"].append((e[0], e[1]))
+                    ev["eval_ssao_multi"].append((e[1], e[2]))
+                    ev["merge"].append((e[2], e[3]))
+                    ev["eval_ssao_plain"].append((e[3], e[4]))
+                    counts.append(masks.count[:3].clone())
+        torch.cuda.synchronize()
+        for s in names:
+            stages[s] = float(np.median([a.elapsed_time(b) for a, b in ev[s]]))
+        cnt = np.array([c.cpu().numpy().view(np.uint32) for c in counts], np.float64).mean(0)
+        n = [npx >> (2 * (i - 1)) for i in (1, 2, 3, 4)]
+        cov = [cnt[0] / n[0], cnt[1] / n[1], cnt[2] / n[2]]
+        F = cov[0] + cov[1] / 4 + cov[2] / 16 + 1 / 64
+        evaluated = cnt[0] + cnt[1] + cnt[2] + n[3]
+        # algorithmic bytes (per-kernel byte accounting)
+        b_edges = 16 * n[0] + n[0] + n[1] + n[2] + 4 * (n[1] + n[2] + n[3])
+        b_blur = sum(6 * n[i] for i in range(3))
+        b_compact = sum(2 * n[i] + 4 * cnt[i] for i in range(3))
+        b_eval = 20 * evaluated + 4 * (cnt[0] + cnt[1] + cnt[2])
+        b_merge = 5 * n[0] + 4 * cnt[0] + 9 * (n[1] + n[2]) + 4 * n[3] + 4 * n[0]
+        b_frame = b_edges + b_blur + b_compact + b_eval + b_merge
+        gathers = 4.0 * S * evaluated
+        t_frame = wall_m / args.steps
+        ops_multi = evaluated * (SSAO_OPS_PER_SAMPLE * S + SSAO_OPS_PER_TEXEL)
+        ops_plain = n[0] * (SSAO_OPS_PER_SAMPLE * S + SSAO_OPS_PER_TEXEL)
+        t_eval = stages["eval_ssao_multi"] * 1e-3
+        t_plain_eval = stages["eval_ssao_plain"] * 1e-3
+        stages.update({
+            "coverage_f1_f2_f3": [round(c, 5) for c in cov], "F": round(F, 5),
+            "frame_alg_bytes": b_frame, "frame_hbm_frac": b_frame / t_frame / (HBM_PEAK_GBS * 1e9),
+            "frame_hbm_frac_incl_gathers": (b_frame + gathers) / t_frame / (HBM_PEAK_GBS * 1e9),
+            "build_masks_hbm_frac": (b_edges + b_blur + b_compact) / (stages["build_masks"] * 1e-3) / 8e12,
+            "merge_hbm_frac": b_merge / (stages["merge"] * 1e-3) / 8e12,
+            "eval_multi_valu_frac": ops_multi / t_eval / (VALU_PEAK_TOPS * 1e12),
+            "eval_plain_valu_frac": ops_plain / t_plain_eval / (VALU_PEAK_TOPS * 1e12),
+        })
+        # dominant kernel of the multi-resolution frame
+        achieved = ops_multi / t_eval / 1e12
+        roofline = {"kernel": "k_ssao (multi-res, all levels in one launch)", "bound": "alu",
+                    "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None}
+        log(f"[bench] stages (ms): " + ", ".join(f"{s}={stages[s]:.4f}" for s in names))
+
+    # ---------------- CPU oracle on a bounded sample ----------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        omp = oracle.MaskParams(num_levels=4, level_enable=0xF, sigma2=mp.sigma2, weight=mp.weight,
+                                normal_cos=float(np.float32(mp.normal_cos)))
+        op = oracle.SSAOParams(K, args.radius, 0.02)
+        t_c = time.perf_counter()
+        done = 0
+        for k in range(3):
+            gb = frames[k]["gb"]
+            oracle.frame("ssao", gb.depth, gb.normal, gb.focal, omp, op)
+            done += 1
+            if time.perf_counter() - t_c > 25:
+                break
+        dt = time.perf_counter() - t_c
+        cpu = {"value": round(npx * done / dt / 1e6, 4), "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} full multi-resolution SSAO frames at {W}x{H} (configurations 0..{done - 1}), "
+                         f"numpy single thread, {dt:.1f}s"}
+        log(f"[bench] cpu oracle: {cpu['value']} Mpixels/s")
+
+    res = {
+        "metric": "Mpixels/s multi-res vs full-res SSAO at 4K (HBM %); p50/p99 frame latency",
+        "value": round(value, 2),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_m * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ssao_4k: seeded scenes (200 boxes + 50 spheres) at {W}x{H}, 4 levels, "
+                               f"SSAO {S} samples r={args.radius}, {nf} resident configurations",
+                   "width": W, "height": H, "levels": 4, "samples": S, "radius": args.radius,
+                   "configurations": nf, "parallelism": "single GPU"},
+        "plain_mpixels_s": round(plain_mpx, 2),
+        "speedup_vs_plain": round(value / plain_mpx, 3),
+        "p50_ms": round(float(np.percentile(lat_m, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat_m, 99)), 4),
+        "plain_p50_ms": round(float(np.percentile(lat_p, 50)), 4),
+        "plain_p99_ms": round(float(np.percentile(lat_p, 99)), 4),
+        "mad_vs_plain": round(float(np.mean(mads)), 6),
+        "rms_vs_plain": round(float(np.mean(rmss)), 6),
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -302,20 +302,31 @@ int do_build_masks(const mr_gbuffer* gb, const Geo& g, const mr_mask_params* mp,
     }
     if (launch_edges(ea, gb->normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
     int radius[kMaxLevels] = {};
+    BlurArgs ba{};
+    unsigned tiles = 0;
     for (int j = 0; j + 1 < g.nlev; ++j) {
         const int i = g.levels[j];
-        BlurArgs ba{};
+        BlurLevel bl{};
         int r;
-        gauss(mp, i, ba.g, r);
+        gauss(mp, i, bl.g, r);
         radius[i - 1] = r;
-        ba.Ei = Ei[i - 1];
-        ba.a = m->alpha[i - 1];
-        ba.S = m->stencil[i - 1];
-        ba.W = g.Wi[i - 1];
-        ba.H = g.Hi[i - 1];
-        ba.r = r;
-        if (launch_blur(ba, s) != hipSuccess) return fail(MR_E_DEVICE, "blur kernel launch failed");
+        bl.Ei = Ei[i - 1];
+        bl.a = m->alpha[i - 1];
+        bl.S = m->stencil[i - 1];
+        bl.W = g.Wi[i - 1];
+        bl.H = g.Hi[i - 1];
+        bl.r = r;
+        bl.tiles_x = (unsigned)((bl.W + 255) / 256);
+        if (r > kBlurFusedMaxRadius) {
+            if (launch_blur_wide(bl, s) != hipSuccess) return fail(MR_E_DEVICE, "blur kernel launch failed");
+            continue;
+        }
+        bl.tile_base = tiles;
+        tiles += bl.tiles_x * (unsigned)((bl.H + 31) / 32);
+        ba.lv[ba.nlev++] = bl;
     }
+    ba.ntiles = tiles;
+    if (launch_blur(ba, s) != hipSuccess) return fail(MR_E_DEVICE, "blur kernel launch failed");
     // Nesting: S_j |= pool(S_i) for consecutive enabled i < j < L.  When every
     // earlier pair was a no-op, S_i is the Chebyshev dilation of E_i by r_i
     // and the pair is a no-op too if r_j >= ceil(r_i / k); only pairs that can
@@ -391,7 +402,7 @@ unsigned make_eval_common(const mr_gbuffer* gb, const Geo& g, const mr_masks* m,
                 L.zpx = 1;
             } else {
                 L.z = gb->depth + off;
-                L.zpy = (long long)sc * g.W;
+                L.zpy = sc * g.W;
                 L.zpx = sc;
             }
             L.goff = off;
@@ -479,12 +490,22 @@ int do_merge(const Geo& g, const mr_mask_params* mp, const mr_masks* m, const fl
         MergeLevel& L = a.lv[j];
         L.c = lo[i - 1];
         L.c_plane = g.n(i);
-        L.s = 1 << (i - 1);
+        L.sh = i - 1;
+        L.s = 1 << L.sh;
         L.W = g.Wi[i - 1];
         L.H = g.Hi[i - 1];
         L.w = mp->weight[i - 1];
         L.a = i == g.L ? nullptr : m->alpha[i - 1];
         L.S = i == g.L ? nullptr : m->stencil[i - 1];
+        if (L.s >= 2) {
+            // taps of a tile's columns x0 .. x0 + 63 lie in (x0 >> sh) - 1 ..
+            // (x0 >> sh) + ceil(64 / s); rows likewise for 16 rows
+            L.rw = (kMergeTW + L.s - 1) / L.s + 2;
+            L.rh = (kMergeTH + L.s - 1) / L.s + 2;
+            L.roff = a.staged;
+            L.rmagic = (65536u + (unsigned)L.rw - 1) / (unsigned)L.rw;
+            a.staged += L.rw * L.rh;
+        }
     }
     if (launch_merge(a, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
     return MR_OK;

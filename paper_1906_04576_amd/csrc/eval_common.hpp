@@ -18,18 +18,49 @@ __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
     ItemMap m;
     m.nlev = c.nlev;
     m.cum[0] = 0;
-    for (int j = 0; j < c.nlev; ++j) {
-        // a list never holds more entries than its level has texels
-        const unsigned n = c.lv[j].list ? min(c.counts[c.lv[j].count_idx], c.lv[j].dense_n) : c.lv[j].dense_n;
+#pragma unroll
+    for (int j = 0; j < kMaxLevels; ++j) {
+        unsigned n = 0;
+        if (j < c.nlev) {
+            // a list never holds more entries than its level has texels
+            n = c.lv[j].list ? min(c.counts[c.lv[j].count_idx], c.lv[j].dense_n) : c.lv[j].dense_n;
+        }
         m.cum[j + 1] = m.cum[j] + n;
     }
     return m;
 }
 
+// total item count (cum[nlev]; the entries past nlev repeat it)
+__device__ __forceinline__ unsigned item_total(const ItemMap& m) { return m.cum[kMaxLevels]; }
+
+// level of an item: unrolled comparisons (a dynamically indexed prefix
+// array would be demoted to per-thread LDS)
 __device__ __forceinline__ int item_level(const ItemMap& m, unsigned item) {
     int j = 0;
-    while (j + 1 < m.nlev && item >= m.cum[j + 1]) ++j;
+#pragma unroll
+    for (int k = 1; k < kMaxLevels; ++k) j += (k < m.nlev && item >= m.cum[k]) ? 1 : 0;
     return j;
+}
+
+// item index relative to its level's first item
+__device__ __forceinline__ unsigned item_local(const ItemMap& m, unsigned item, int j) {
+    unsigned base = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k)
+        if (k == j) base = m.cum[k];
+    return item - base;
+}
+
+// Sample sets are staged in LDS once per workgroup when they fit; the sample
+// loops then read them with uniform LDS addresses instead of a vector load
+// (and its full wait) per sample.
+constexpr int kLdsSamples = 1024;
+
+__device__ __forceinline__ const float* stage_samples(const float* g, int nfloats, float* lds) {
+    if (nfloats > 3 * kLdsSamples) return g;
+    for (int i = threadIdx.x; i < nfloats; i += blockDim.x) lds[i] = g[i];
+    __syncthreads();
+    return lds;
 }
 
 // P = (X z, Y z, -z), X = ((x + 0.5) - cx) / f, Y = (cy - (y + 0.5)) / f

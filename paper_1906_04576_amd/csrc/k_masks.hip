@@ -8,141 +8,440 @@ namespace mr {
 
 // ---------------------------------------------------------------------------
 // edge image + pooling.  One workgroup = 64 x 32 pixel tile (aligned to every
-// pooling block up to s = 32), 256 threads, 8 pixels per thread.
+// pooling block up to s = 32), 256 threads.  The tile and a one-pixel halo of
+// depth and normals (and shadow bits) are staged in LDS with 16-byte loads,
+// then every thread classifies a 4 x 2 pixel block, ORs it to the level-2
+// texels in registers and the coarser levels through LDS.
 // ---------------------------------------------------------------------------
 constexpr int kEdgeTW = 64, kEdgeTH = 32;
 
-template <typename NT>
-__device__ __forceinline__ float ndot(const NT* n, long long plane, long long p, long long q) {
-    // ((nx_p nx_q) + (ny_p ny_q)) + (nz_p nz_q)
-    float a = ld(n, p) * ld(n, q);
-    float b = ld(n, plane + p) * ld(n, plane + q);
-    float c = ld(n, 2 * plane + p) * ld(n, 2 * plane + q);
-    return (a + b) + c;
-}
+template <typename T>
+__device__ __forceinline__ void row4(const T* p, unsigned off, bool vec, int n, float* o);
 
-template <typename NT>
-__device__ uint8_t edge_at(const EdgeArgs& a, int x, int y) {
-    const int W = a.W, H = a.H;
-    const long long p = (long long)y * W + x;
-    const float z = a.depth[p];
-    if (!valid_depth(z)) return 0;
-    const bool hl = x > 0, hr = x < W - 1, hu = y > 0, hd = y < H - 1;
-    const float zl = hl ? a.depth[p - 1] : 0.0f;
-    const float zr = hr ? a.depth[p + 1] : 0.0f;
-    const float zu = hu ? a.depth[p - W] : 0.0f;
-    const float zd = hd ? a.depth[p + W] : 0.0f;
-    // geometry next to background is an edge
-    if ((hl && !valid_depth(zl)) || (hr && !valid_depth(zr)) || (hu && !valid_depth(zu)) ||
-        (hd && !valid_depth(zd)))
-        return 1;
-    // depth: relative second difference per axis, skipped at the border
-    const float thr = a.depth_ratio * z;
-    const float two_z = 2.0f * z;
-    if (hl && hr && fabsf((zl + zr) - two_z) > thr) return 1;
-    if (hu && hd && fabsf((zu + zd) - two_z) > thr) return 1;
-    // normal: first difference as an angle test against the 4-neighbours
-    const NT* n = static_cast<const NT*>(a.normal);
-    const long long plane = (long long)W * H;
-    const float cn = a.normal_cos;
-    if (hl && ndot(n, plane, p, p - 1) < cn) return 1;
-    if (hr && ndot(n, plane, p, p + 1) < cn) return 1;
-    if (hu && ndot(n, plane, p, p - W) < cn) return 1;
-    if (hd && ndot(n, plane, p, p + W) < cn) return 1;
-    // shadow edges (soft shadows): the one-sample shadow bit changes
-    if (a.hard) {
-        const uint8_t h = a.hard[p];
-        if ((hl && a.hard[p - 1] != h) || (hr && a.hard[p + 1] != h) ||
-            (hu && a.hard[p - W] != h) || (hd && a.hard[p + W] != h))
-            return 1;
+template <>
+__device__ __forceinline__ void row4<float>(const float* p, unsigned off, bool vec, int n, float* o) {
+    if (vec) {
+        const float4 v = *reinterpret_cast<const float4*>(p + off);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    } else {
+        for (int k = 0; k < 4; ++k) o[k] = k < n ? p[off + k] : 0.0f;
     }
-    return 0;
 }
 
-template <typename NT>
-__global__ __launch_bounds__(256) void k_edges(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
-    __shared__ uint8_t t1[kEdgeTH][kEdgeTW];
-    __shared__ uint8_t t2[kEdgeTH / 2][kEdgeTW / 2];
-    __shared__ uint8_t t3[kEdgeTH / 4][kEdgeTW / 4];
-    __shared__ uint8_t t4[kEdgeTH / 8][kEdgeTW / 8];
-    __shared__ uint8_t t5[kEdgeTH / 16][kEdgeTW / 16];
-    __shared__ uint8_t t6[kEdgeTH / 32][kEdgeTW / 32];
+template <>
+__device__ __forceinline__ void row4<_Float16>(const _Float16* p, unsigned off, bool vec, int n, float* o) {
+    if (vec) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 v = *reinterpret_cast<const h4*>(p + off);
+        o[0] = (float)v.x;
+        o[1] = (float)v.y;
+        o[2] = (float)v.z;
+        o[3] = (float)v.w;
+    } else {
+        for (int k = 0; k < 4; ++k) o[k] = k < n ? (float)p[off + k] : 0.0f;
+    }
+}
 
+__device__ __forceinline__ bool ndot_lt(const float* a, const float* b, float cn) {
+    // ((nx nx') + (ny ny')) + (nz nz') < c_n
+    return ((a[0] * b[0]) + (a[1] * b[1])) + (a[2] * b[2]) < cn;
+}
+
+// One workgroup = 64 x 32 pixel tile (aligned to every pooling block up to
+// s = 32), 256 threads; a thread owns a 4 x 2 pixel block and loads it with a
+// one-pixel ring straight from memory (rows above and below and the side
+// columns are shared with neighbouring threads through L1/L2), so no LDS
+// staging limits occupancy.  Each normal pair is tested once.  Level 2 is
+// ORed in registers, levels 3 and 4 with lane shuffles, 5 and 6 through LDS.
+template <typename NT>
+__global__ __launch_bounds__(256) void k_edges_generic(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
+    __shared__ uint8_t p4[4][8];
     const unsigned tile = xcd_remap(blockIdx.x, ntiles);
     const int x0 = (int)(tile % tiles_x) * kEdgeTW;
     const int y0 = (int)(tile / tiles_x) * kEdgeTH;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int W = a.W, H = a.H;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int cg = lane & 15, rp = lane >> 4;
+    const int xb = x0 + 4 * cg, yb = y0 + 8 * wave + 2 * rp;
+    const unsigned plane = (unsigned)W * (unsigned)H;
+    const NT* nrm = static_cast<const NT*>(a.normal);
+    const bool has_hard = a.hard != nullptr;
+    const bool any = xb < W && yb < H;
+    const int ncol = min(4, W - xb);
+    const bool vec = ((W & 3) == 0) && ncol == 4;
+
+    // ---- loads: rows yb-1 .. yb+2 (index 0..3), columns xb .. xb+3, and the
+    // side columns xb-1 / xb+4 of rows yb, yb+1 ----
+    float z[4][4], n[4][4][3];
+    float zs[2][2], ns[2][2][3];  // [row][left/right]
+    uint8_t h[4][4], hs[2][2];
 #pragma unroll
-    for (int k = 0; k < kEdgeTH / 4; ++k) {
-        const int ly = ty + 4 * k;
-        const int x = x0 + tx, y = y0 + ly;
-        uint8_t e = 0;
-        if (x < W && y < H) {
-            e = edge_at<NT>(a, x, y);
-            a.E[(long long)y * W + x] = e;
-            // point-sampled level depth: z_i(X, Y) = z(s X + s/2, s Y + s/2)
-            for (int i = 2; i <= a.num_levels; ++i) {
-                float* zi = a.zi[i - 1];
-                const int s = 1 << (i - 1), h = s >> 1;
-                if (zi && (x & (s - 1)) == h && (y & (s - 1)) == h)
-                    zi[(long long)(y >> (i - 1)) * a.Wi[i - 1] + (x >> (i - 1))] =
-                        a.depth[(long long)y * W + x];
+    for (int r = 0; r < 4; ++r) {
+        const int y = yb - 1 + r;
+        const bool rok = any && y >= 0 && y < H;
+        float tz[4] = {0, 0, 0, 0}, t0[4] = {0, 0, 0, 0}, t1[4] = {0, 0, 0, 0}, t2[4] = {0, 0, 0, 0};
+        uint8_t th[4] = {0, 0, 0, 0};
+        if (rok) {
+            const unsigned off = (unsigned)y * (unsigned)W + (unsigned)xb;
+            row4<float>(a.depth, off, vec, ncol, tz);
+            row4<NT>(nrm, off, vec, ncol, t0);
+            row4<NT>(nrm + plane, off, vec, ncol, t1);
+            row4<NT>(nrm + 2 * plane, off, vec, ncol, t2);
+            if (has_hard) {
+                if (vec) {
+                    const uchar4 v = *reinterpret_cast<const uchar4*>(a.hard + off);
+                    th[0] = v.x;
+                    th[1] = v.y;
+                    th[2] = v.z;
+                    th[3] = v.w;
+                } else {
+                    for (int k = 0; k < ncol; ++k) th[k] = a.hard[off + k];
+                }
             }
         }
-        t1[ly][tx] = e;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            z[r][k] = tz[k];
+            n[r][k][0] = t0[k];
+            n[r][k][1] = t1[k];
+            n[r][k][2] = t2[k];
+            h[r][k] = th[k];
+        }
     }
-    __syncthreads();
-    // hierarchical OR: level i texel = OR of its four level-(i-1) children
-    const int t = threadIdx.x;
-    for (int idx = t; idx < (kEdgeTH / 2) * (kEdgeTW / 2); idx += 256) {
-        const int yy = idx / (kEdgeTW / 2), xx = idx % (kEdgeTW / 2);
-        t2[yy][xx] = t1[2 * yy][2 * xx] | t1[2 * yy][2 * xx + 1] | t1[2 * yy + 1][2 * xx] |
-                     t1[2 * yy + 1][2 * xx + 1];
-    }
-    __syncthreads();
-    if (t < (kEdgeTH / 4) * (kEdgeTW / 4)) {
-        const int yy = t / (kEdgeTW / 4), xx = t % (kEdgeTW / 4);
-        t3[yy][xx] = t2[2 * yy][2 * xx] | t2[2 * yy][2 * xx + 1] | t2[2 * yy + 1][2 * xx] |
-                     t2[2 * yy + 1][2 * xx + 1];
-    }
-    __syncthreads();
-    if (t < (kEdgeTH / 8) * (kEdgeTW / 8)) {
-        const int yy = t / (kEdgeTW / 8), xx = t % (kEdgeTW / 8);
-        t4[yy][xx] = t3[2 * yy][2 * xx] | t3[2 * yy][2 * xx + 1] | t3[2 * yy + 1][2 * xx] |
-                     t3[2 * yy + 1][2 * xx + 1];
-    }
-    __syncthreads();
-    if (t < (kEdgeTH / 16) * (kEdgeTW / 16)) {
-        const int yy = t / (kEdgeTW / 16), xx = t % (kEdgeTW / 16);
-        t5[yy][xx] = t4[2 * yy][2 * xx] | t4[2 * yy][2 * xx + 1] | t4[2 * yy + 1][2 * xx] |
-                     t4[2 * yy + 1][2 * xx + 1];
-    }
-    __syncthreads();
-    if (t < (kEdgeTH / 32) * (kEdgeTW / 32)) {
-        const int xx = t;
-        t6[0][xx] = t5[0][2 * xx] | t5[0][2 * xx + 1] | t5[1][2 * xx] | t5[1][2 * xx + 1];
-    }
-    __syncthreads();
-    // write the pooled levels that the blur needs
-    for (int i = 2; i <= a.num_levels; ++i) {
-        uint8_t* Ei = a.Ei[i - 1];
-        if (!Ei) continue;
-        const int sh = i - 1;
-        const int tw = kEdgeTW >> sh, th = kEdgeTH >> sh;
-        for (int idx = t; idx < tw * th; idx += 256) {
-            const int yy = idx / tw, xx = idx % tw;
-            const int X = (x0 >> sh) + xx, Y = (y0 >> sh) + yy;
-            if (X >= a.Wi[i - 1] || Y >= a.Hi[i - 1]) continue;
-            uint8_t v;
-            switch (i) {
-                case 2: v = t2[yy][xx]; break;
-                case 3: v = t3[yy][xx]; break;
-                case 4: v = t4[yy][xx]; break;
-                case 5: v = t5[yy][xx]; break;
-                default: v = t6[yy][xx]; break;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int y = yb + r;
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const int x = sd ? xb + 4 : xb - 1;
+            zs[r][sd] = 0.0f;
+            ns[r][sd][0] = ns[r][sd][1] = ns[r][sd][2] = 0.0f;
+            hs[r][sd] = 0;
+            if (any && y < H && x >= 0 && x < W) {
+                const unsigned off = (unsigned)y * (unsigned)W + (unsigned)x;
+                zs[r][sd] = a.depth[off];
+                ns[r][sd][0] = ld(nrm, off);
+                ns[r][sd][1] = ld(nrm, plane + off);
+                ns[r][sd][2] = ld(nrm, 2 * plane + off);
+                if (has_hard) hs[r][sd] = a.hard[off];
             }
-            Ei[(long long)Y * a.Wi[i - 1] + X] = v;
+        }
+    }
+
+    // ---- normal pair tests, each pair once ----
+    const float cn = a.normal_cos, td = a.depth_ratio;
+    bool hp[2][5];  // row r: pair (c-1, c), c = 0..4
+    bool vp[3][4];  // column c: pair (row k, row k+1)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        hp[r][0] = ndot_lt(ns[r][0], n[r + 1][0], cn);
+#pragma unroll
+        for (int c = 1; c < 4; ++c) hp[r][c] = ndot_lt(n[r + 1][c - 1], n[r + 1][c], cn);
+        hp[r][4] = ndot_lt(n[r + 1][3], ns[r][1], cn);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vp[k][c] = ndot_lt(n[k][c], n[k + 1][c], cn);
+
+    // ---- classify the 8 pixels ----
+    uint8_t e[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int y = yb + r;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int x = xb + c;
+            const float zc = z[r + 1][c];
+            const float zl = c > 0 ? z[r + 1][c - 1] : zs[r][0];
+            const float zr = c < 3 ? z[r + 1][c + 1] : zs[r][1];
+            const float zu = z[r][c], zd = z[r + 2][c];
+            const bool hl = x > 0, hr = x < W - 1, hu = y > 0, hd = y < H - 1;
+            bool ed = (hl && !valid_depth(zl)) || (hr && !valid_depth(zr)) || (hu && !valid_depth(zu)) ||
+                      (hd && !valid_depth(zd));
+            const float thr = td * zc;
+            const float two_z = 2.0f * zc;
+            ed = ed || (hl && hr && fabsf((zl + zr) - two_z) > thr);
+            ed = ed || (hu && hd && fabsf((zu + zd) - two_z) > thr);
+            ed = ed || (hl && hp[r][c]) || (hr && hp[r][c + 1]) || (hu && vp[r][c]) || (hd && vp[r + 1][c]);
+            if (has_hard) {
+                const uint8_t hc = h[r + 1][c];
+                const uint8_t hl_ = c > 0 ? h[r + 1][c - 1] : hs[r][0];
+                const uint8_t hr_ = c < 3 ? h[r + 1][c + 1] : hs[r][1];
+                ed = ed || (hl && hl_ != hc) || (hr && hr_ != hc) || (hu && h[r][c] != hc) ||
+                     (hd && h[r + 2][c] != hc);
+            }
+            e[r][c] = (any && x < W && y < H && valid_depth(zc) && ed) ? 1 : 0;
+        }
+    }
+    if (any) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int y = yb + r;
+            if (y >= H) continue;
+            const unsigned off = (unsigned)y * (unsigned)W + (unsigned)xb;
+            if (vec)
+                *reinterpret_cast<uchar4*>(a.E + off) = make_uchar4(e[r][0], e[r][1], e[r][2], e[r][3]);
+            else
+                for (int k = 0; k < ncol; ++k) a.E[off + k] = e[r][k];
+        }
+        // point-sampled level depth: z_i(X, Y) = z(s X + s/2, s Y + s/2)
+        for (int i = 2; i <= a.num_levels; ++i) {
+            float* zi = a.zi[i - 1];
+            if (!zi) continue;
+            const int sh = i - 1, s = 1 << sh, hf = s >> 1;
+            const unsigned wi = (unsigned)a.Wi[i - 1];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int x = xb + c, y = yb + r;
+                    if (x < W && y < H && (x & (s - 1)) == hf && (y & (s - 1)) == hf)
+                        zi[(unsigned)(y >> sh) * wi + (unsigned)(x >> sh)] = z[r + 1][c];
+                }
+        }
+    }
+    // ---- pooled edges ----
+    // level 2: texels (xb/2 + j, yb/2), in registers
+    if (any && a.Ei[1]) {
+        const unsigned off = (unsigned)(yb >> 1) * (unsigned)a.Wi[1] + (unsigned)(xb >> 1);
+        a.Ei[1][off] = e[0][0] | e[0][1] | e[1][0] | e[1][1];
+        if (ncol > 2) a.Ei[1][off + 1] = e[0][2] | e[0][3] | e[1][2] | e[1][3];
+    }
+    // level 3: 4 x 4 = this thread and the one below (lane + 16)
+    int v = e[0][0] | e[0][1] | e[0][2] | e[0][3] | e[1][0] | e[1][1] | e[1][2] | e[1][3];
+    v |= __shfl_xor(v, 16, 64);
+    if (any && a.Ei[2] && (rp & 1) == 0)
+        a.Ei[2][(unsigned)(yb >> 2) * (unsigned)a.Wi[2] + (unsigned)(xb >> 2)] = (uint8_t)v;
+    // level 4: 8 x 8 = pairs of column groups and the other row pair
+    v |= __shfl_xor(v, 1, 64);
+    v |= __shfl_xor(v, 32, 64);
+    if (any && a.Ei[3] && (cg & 1) == 0 && rp == 0)
+        a.Ei[3][(unsigned)(yb >> 3) * (unsigned)a.Wi[3] + (unsigned)(xb >> 3)] = (uint8_t)v;
+    if (a.num_levels >= 5) {
+        // levels 5 and 6 combine the waves' 8 x 8 blocks through LDS
+        if (rp == 0 && (cg & 1) == 0) p4[wave][cg >> 1] = (uint8_t)v;
+        __syncthreads();
+        if (a.Ei[4] && t < 8) {
+            const int w = (t >> 2) * 2, j = t & 3;
+            const int X = (x0 >> 4) + j, Y = (y0 >> 4) + (w >> 1);
+            if (X < a.Wi[4] && Y < a.Hi[4])
+                a.Ei[4][(unsigned)Y * (unsigned)a.Wi[4] + (unsigned)X] =
+                    p4[w][2 * j] | p4[w][2 * j + 1] | p4[w + 1][2 * j] | p4[w + 1][2 * j + 1];
+        }
+        if (a.num_levels >= 6 && a.Ei[5] && t < 2) {
+            const int X = (x0 >> 5) + t, Y = y0 >> 5;
+            uint8_t o = 0;
+            for (int w = 0; w < 4; ++w)
+                for (int j = 0; j < 4; ++j) o |= p4[w][4 * t + j];
+            if (X < a.Wi[5] && Y < a.Hi[5]) a.Ei[5][(unsigned)Y * (unsigned)a.Wi[5] + (unsigned)X] = o;
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Fast path for W divisible by 4 (every image with N >= 3 levels): the same
+// classification, branch-free, with buffer loads (descriptor + 32-bit offset)
+// of clamped rows and columns.  Rows or columns outside the image are loaded
+// from a clamped position and only ever used behind the border flags.
+// ---------------------------------------------------------------------------
+template <typename NT>
+struct NormalRow;
+
+template <>
+struct NormalRow<float> {
+    static constexpr unsigned kSize = 4;
+    __device__ static void load4(__amdgpu_buffer_rsrc_t r, unsigned e, float* o) {
+        const float4 v = buf_f4(r, e * 4u);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+    __device__ static float load1(__amdgpu_buffer_rsrc_t r, unsigned e) { return buf_f1(r, e * 4u); }
+};
+
+template <>
+struct NormalRow<_Float16> {
+    static constexpr unsigned kSize = 2;
+    __device__ static void load4(__amdgpu_buffer_rsrc_t r, unsigned e, float* o) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 v = __builtin_bit_cast(h4, __builtin_amdgcn_raw_buffer_load_b64(r, e * 2u, 0, 0));
+        o[0] = (float)v.x;
+        o[1] = (float)v.y;
+        o[2] = (float)v.z;
+        o[3] = (float)v.w;
+    }
+    __device__ static float load1(__amdgpu_buffer_rsrc_t r, unsigned e) {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, e * 2u, 0, 0));
+    }
+};
+
+template <typename NT, bool HARD>
+__global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
+    __shared__ uint8_t p4[4][8];
+    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
+    const int x0 = (int)(tile % tiles_x) * kEdgeTW;
+    const int y0 = (int)(tile / tiles_x) * kEdgeTH;
+    const int W = a.W, H = a.H;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int cg = lane & 15, rp = lane >> 4;
+    const int xb = x0 + 4 * cg, yb = y0 + 8 * wave + 2 * rp;
+    const bool any = xb < W && yb < H;
+    const unsigned plane = (unsigned)W * (unsigned)H;
+    const __amdgpu_buffer_rsrc_t rz = buf_rsrc(a.depth, plane * 4u);
+    const NT* nrm = static_cast<const NT*>(a.normal);
+    const unsigned nb = plane * NormalRow<NT>::kSize;
+    const __amdgpu_buffer_rsrc_t rn0 = buf_rsrc(nrm, nb), rn1 = buf_rsrc(nrm + plane, nb),
+                                 rn2 = buf_rsrc(nrm + 2 * plane, nb);
+    const __amdgpu_buffer_rsrc_t rh = buf_rsrc(a.hard, HARD ? plane : 0u);
+    // clamped element offsets of rows yb-1 .. yb+2 and the side columns
+    const int xc = min(xb, W - 4);
+    unsigned ro[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ro[r] = (unsigned)min(max(yb - 1 + r, 0), H - 1) * (unsigned)W;
+    const unsigned xl = (unsigned)max(xb - 1, 0), xr = (unsigned)min(xb + 4, W - 1);
+
+    float z[4][4], n[4][4][3];
+    float zs[2][2], ns[2][2][3];
+    unsigned hrow[4] = {0, 0, 0, 0}, hside[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned e = ro[r] + (unsigned)xc;
+        const float4 zv = buf_f4(rz, e * 4u);
+        z[r][0] = zv.x;
+        z[r][1] = zv.y;
+        z[r][2] = zv.z;
+        z[r][3] = zv.w;
+        float t0[4], t1[4], t2[4];
+        NormalRow<NT>::load4(rn0, e, t0);
+        NormalRow<NT>::load4(rn1, e, t1);
+        NormalRow<NT>::load4(rn2, e, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            n[r][k][0] = t0[k];
+            n[r][k][1] = t1[k];
+            n[r][k][2] = t2[k];
+        }
+        if (HARD) hrow[r] = __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const unsigned e = ro[r + 1] + (sd ? xr : xl);
+            zs[r][sd] = buf_f1(rz, e * 4u);
+            ns[r][sd][0] = NormalRow<NT>::load1(rn0, e);
+            ns[r][sd][1] = NormalRow<NT>::load1(rn1, e);
+            ns[r][sd][2] = NormalRow<NT>::load1(rn2, e);
+            if (HARD) hside[r][sd] = __builtin_amdgcn_raw_buffer_load_b8(rh, e, 0, 0);
+        }
+    }
+    // normal pair tests, each pair once
+    const float cn = a.normal_cos, td = a.depth_ratio;
+    bool hp[2][5], vp[3][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        hp[r][0] = ndot_lt(ns[r][0], n[r + 1][0], cn);
+#pragma unroll
+        for (int c = 1; c < 4; ++c) hp[r][c] = ndot_lt(n[r + 1][c - 1], n[r + 1][c], cn);
+        hp[r][4] = ndot_lt(n[r + 1][3], ns[r][1], cn);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vp[k][c] = ndot_lt(n[k][c], n[k + 1][c], cn);
+    // classify, branch-free (non-short-circuit logic)
+    uint8_t e[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int y = yb + r;
+        const bool hu = y > 0, hd = y < H - 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int x = xb + c;
+            const bool hl = x > 0, hr = x < W - 1;
+            const float zc = z[r + 1][c];
+            const float zl = c > 0 ? z[r + 1][c - 1] : zs[r][0];
+            const float zr = c < 3 ? z[r + 1][c + 1] : zs[r][1];
+            const float zu = z[r][c], zd = z[r + 2][c];
+            bool ed = (hl & !valid_depth(zl)) | (hr & !valid_depth(zr)) | (hu & !valid_depth(zu)) |
+                      (hd & !valid_depth(zd));
+            const float thr = td * zc;
+            const float two_z = 2.0f * zc;
+            ed |= hl & hr & (fabsf((zl + zr) - two_z) > thr);
+            ed |= hu & hd & (fabsf((zu + zd) - two_z) > thr);
+            ed |= (hl & hp[r][c]) | (hr & hp[r][c + 1]) | (hu & vp[r][c]) | (hd & vp[r + 1][c]);
+            if (HARD) {
+                const unsigned sh = 8u * (unsigned)c;
+                const unsigned hc = (hrow[r + 1] >> sh) & 0xFFu;
+                const unsigned hl_ = c > 0 ? (hrow[r + 1] >> (sh - 8u)) & 0xFFu : hside[r][0];
+                const unsigned hr_ = c < 3 ? (hrow[r + 1] >> (sh + 8u)) & 0xFFu : hside[r][1];
+                const unsigned hu_ = (hrow[r] >> sh) & 0xFFu, hd_ = (hrow[r + 2] >> sh) & 0xFFu;
+                ed |= (hl & (hl_ != hc)) | (hr & (hr_ != hc)) | (hu & (hu_ != hc)) | (hd & (hd_ != hc));
+            }
+            e[r][c] = (any & (y < H) & valid_depth(zc) & ed) ? 1 : 0;
+        }
+    }
+    if (any) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int y = yb + r;
+            if (y < H)
+                *reinterpret_cast<uchar4*>(a.E + (unsigned)y * (unsigned)W + (unsigned)xb) =
+                    make_uchar4(e[r][0], e[r][1], e[r][2], e[r][3]);
+        }
+        // point-sampled level depth: z_i(X, Y) = z(s X + s/2, s Y + s/2).  For
+        // s = 2 that is columns xb+1, xb+3 of row yb+1; for s >= 4 at most one
+        // pixel of the block qualifies: column 2 (s = 4) or 0 (s >= 8) of row yb.
+        if (a.zi[1]) {
+            float* z2 = a.zi[1] + (unsigned)(yb >> 1) * (unsigned)a.Wi[1] + (unsigned)(xb >> 1);
+            z2[0] = z[2][1];
+            z2[1] = z[2][3];
+        }
+        for (int i = 3; i <= a.num_levels; ++i) {
+            float* zi = a.zi[i - 1];
+            if (!zi) continue;
+            const int sh = i - 1, s = 1 << sh, hf = s >> 1;
+            const int cs = s == 4 ? 2 : 0;
+            if ((xb & (s - 1)) == hf - cs && (yb & (s - 1)) == hf)
+                zi[(unsigned)(yb >> sh) * (unsigned)a.Wi[i - 1] + (unsigned)((xb + cs) >> sh)] =
+                    s == 4 ? z[1][2] : z[1][0];
+        }
+        if (a.Ei[1]) {
+            uint8_t* e2 = a.Ei[1] + (unsigned)(yb >> 1) * (unsigned)a.Wi[1] + (unsigned)(xb >> 1);
+            e2[0] = e[0][0] | e[0][1] | e[1][0] | e[1][1];
+            e2[1] = e[0][2] | e[0][3] | e[1][2] | e[1][3];
+        }
+    }
+    int v = e[0][0] | e[0][1] | e[0][2] | e[0][3] | e[1][0] | e[1][1] | e[1][2] | e[1][3];
+    v |= __shfl_xor(v, 16, 64);
+    if (any && a.Ei[2] && (rp & 1) == 0)
+        a.Ei[2][(unsigned)(yb >> 2) * (unsigned)a.Wi[2] + (unsigned)(xb >> 2)] = (uint8_t)v;
+    v |= __shfl_xor(v, 1, 64);
+    v |= __shfl_xor(v, 32, 64);
+    if (any && a.Ei[3] && (cg & 1) == 0 && rp == 0)
+        a.Ei[3][(unsigned)(yb >> 3) * (unsigned)a.Wi[3] + (unsigned)(xb >> 3)] = (uint8_t)v;
+    if (a.num_levels >= 5) {
+        if (rp == 0 && (cg & 1) == 0) p4[wave][cg >> 1] = (uint8_t)v;
+        __syncthreads();
+        if (a.Ei[4] && t < 8) {
+            const int w = (t >> 2) * 2, j = t & 3;
+            const int X = (x0 >> 4) + j, Y = (y0 >> 4) + (w >> 1);
+            if (X < a.Wi[4] && Y < a.Hi[4])
+                a.Ei[4][(unsigned)Y * (unsigned)a.Wi[4] + (unsigned)X] =
+                    p4[w][2 * j] | p4[w][2 * j + 1] | p4[w + 1][2 * j] | p4[w + 1][2 * j + 1];
+        }
+        if (a.num_levels >= 6 && a.Ei[5] && t < 2) {
+            const int X = (x0 >> 5) + t, Y = y0 >> 5;
+            uint8_t o = 0;
+            for (int w = 0; w < 4; ++w)
+                for (int j = 0; j < 4; ++j) o |= p4[w][4 * t + j];
+            if (X < a.Wi[5] && Y < a.Hi[5]) a.Ei[5][(unsigned)Y * (unsigned)a.Wi[5] + (unsigned)X] = o;
         }
     }
 }
@@ -150,58 +449,188 @@ __global__ __launch_bounds__(256) void k_edges(EdgeArgs a, unsigned tiles_x, uns
 hipError_t launch_edges(const EdgeArgs& a, int normal_dtype, hipStream_t s) {
     const unsigned tx = (a.W + kEdgeTW - 1) / kEdgeTW, ty = (a.H + kEdgeTH - 1) / kEdgeTH;
     const unsigned n = tx * ty;
-    if (normal_dtype == MR_F16)
-        hipLaunchKernelGGL(k_edges<_Float16>, dim3(n), dim3(256), 0, s, a, tx, n);
-    else
-        hipLaunchKernelGGL(k_edges<float>, dim3(n), dim3(256), 0, s, a, tx, n);
+    const bool f16 = normal_dtype == MR_F16, hard = a.hard != nullptr;
+    if ((a.W & 3) == 0 && a.W >= 4) {
+        if (f16 && hard)
+            hipLaunchKernelGGL((k_edges_vec<_Float16, true>), dim3(n), dim3(256), 0, s, a, tx, n);
+        else if (f16)
+            hipLaunchKernelGGL((k_edges_vec<_Float16, false>), dim3(n), dim3(256), 0, s, a, tx, n);
+        else if (hard)
+            hipLaunchKernelGGL((k_edges_vec<float, true>), dim3(n), dim3(256), 0, s, a, tx, n);
+        else
+            hipLaunchKernelGGL((k_edges_vec<float, false>), dim3(n), dim3(256), 0, s, a, tx, n);
+    } else if (f16) {
+        hipLaunchKernelGGL(k_edges_generic<_Float16>, dim3(n), dim3(256), 0, s, a, tx, n);
+    } else {
+        hipLaunchKernelGGL(k_edges_generic<float>, dim3(n), dim3(256), 0, s, a, tx, n);
+    }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// separable blur of one level: tile of 64 x 16 output texels, 256 threads.
+// separable blur of every level below the coarsest in one launch.  A
+// workgroup owns 256 columns x 32 rows of one level: the edge bytes of the
+// tile plus its halo are staged in LDS in one batch, then each thread walks
+// down its column keeping the last 2r+1 horizontal sums in a register shift
+// ring, so every output needs one new horizontal sum.
 // h(x, y) = sum_k g[k] E(x + k, y) then a(x, y) = sum_k g[k] h(x, y + k), taps
-// in ascending k, accumulators from +0, zero outside the image.
+// in ascending k, accumulators from +0, zero outside the image; S = a > 0.
+// Terms with E = 0 contribute g * 0 = +0, so h adds g[k] exactly for the set
+// taps.
 // ---------------------------------------------------------------------------
-constexpr int kBlurTW = 64, kBlurTH = 16;
+constexpr int kBlurTW = 256, kBlurTH = 32;
+constexpr int kBlurLW = kBlurTW + 2 * kMaxRadius;  // staged row stride (bytes)
 
-__global__ __launch_bounds__(256) void k_blur(BlurArgs a, unsigned tiles_x, unsigned ntiles) {
-    __shared__ float es[kBlurTH + 2 * kMaxRadius][kBlurTW + 2 * kMaxRadius];
-    __shared__ float hs[kBlurTH + 2 * kMaxRadius][kBlurTW];
-    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
-    const int x0 = (int)(tile % tiles_x) * kBlurTW;
-    const int y0 = (int)(tile / tiles_x) * kBlurTH;
-    const int r = a.r, W = a.W, H = a.H;
-    const int ew = kBlurTW + 2 * r, eh = kBlurTH + 2 * r;
-    for (int idx = threadIdx.x; idx < ew * eh; idx += 256) {
-        const int yy = idx / ew, xx = idx % ew;
-        const int X = x0 - r + xx, Y = y0 - r + yy;
-        float v = 0.0f;
-        if (X >= 0 && X < W && Y >= 0 && Y < H) v = a.Ei[(long long)Y * W + X] ? 1.0f : 0.0f;
-        es[yy][xx] = v;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kBlurTW * eh; idx += 256) {
-        const int yy = idx / kBlurTW, xx = idx % kBlurTW;
+template <int R>
+__device__ __forceinline__ float hsum(const uint8_t* row, const float* g) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) acc = acc + g[k] * (row[k] ? 1.0f : 0.0f);
+    return acc;
+}
+
+template <int R>
+__device__ __forceinline__ void blur_columns(const BlurLevel& a, const uint8_t* es, int x0, int y0) {
+    const int t = threadIdx.x;
+    const int X = x0 + t;
+    const int W = a.W, H = a.H;
+    float g[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) g[k] = a.g[k];
+    // staged row yy holds image row y0 - R + yy, column t + k holds x0 - R + t + k
+    float ring[2 * R + 1];
+    ring[0] = 0.0f;
+#pragma unroll
+    for (int yy = 0; yy < 2 * R; ++yy) ring[yy + 1] = hsum<R>(es + yy * kBlurLW + t, g);
+    const bool colok = X < W;
+    const int rows = min(kBlurTH, H - y0);
+    for (int oy = 0; oy < rows; ++oy) {
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) ring[k] = ring[k + 1];
+        ring[2 * R] = hsum<R>(es + (oy + 2 * R) * kBlurLW + t, g);
         float acc = 0.0f;
-        for (int k = 0; k <= 2 * r; ++k) acc = acc + a.g[k] * es[yy][xx + k];
-        hs[yy][xx] = acc;
-    }
-    __syncthreads();
-    const int xx = threadIdx.x & 63;
-    for (int yy = threadIdx.x >> 6; yy < kBlurTH; yy += 4) {
-        const int X = x0 + xx, Y = y0 + yy;
-        if (X >= W || Y >= H) continue;
-        float acc = 0.0f;
-        for (int k = 0; k <= 2 * r; ++k) acc = acc + a.g[k] * hs[yy + k][xx];
-        const long long p = (long long)Y * W + X;
-        a.a[p] = acc;
-        a.S[p] = acc > 0.0f ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * R; ++k) acc = acc + g[k] * ring[k];
+        if (colok) {
+            const long long p = (long long)(y0 + oy) * W + X;
+            a.a[p] = acc;
+            a.S[p] = acc > 0.0f ? 1 : 0;
+        }
     }
 }
 
+// Stage the tile's edge bytes (rows y0 - r .. y0 + 31 + r, columns
+// x0 - r .. x0 + 255 + r) into LDS with all global loads issued first.
+__device__ __forceinline__ void blur_stage(const BlurLevel& a, uint8_t* es, int x0, int y0) {
+    const int r = a.r, W = a.W, H = a.H, t = threadIdx.x;
+    const int eh = kBlurTH + 2 * r;
+    const bool vec = (W & 3) == 0;
+    constexpr int kWords = kBlurTW / 4;
+    constexpr int kMaxSlots = ((kBlurTH + 2 * kMaxRadius) * kWords + 255) / 256;
+    uchar4 v[kMaxSlots];
+#pragma unroll
+    for (int j = 0; j < kMaxSlots; ++j) {
+        const int idx = t + 256 * j;
+        const int yy = idx / kWords, q = idx % kWords;
+        const int Y = y0 - r + yy, X = x0 + 4 * q;
+        v[j] = make_uchar4(0, 0, 0, 0);
+        if (yy < eh && Y >= 0 && Y < H && X < W) {
+            const long long p = (long long)Y * W + X;
+            if (vec) {
+                v[j] = *reinterpret_cast<const uchar4*>(a.Ei + p);
+            } else {
+                uint8_t e4[4] = {0, 0, 0, 0};
+                for (int k = 0; k < 4 && X + k < W; ++k) e4[k] = a.Ei[p + k];
+                v[j] = make_uchar4(e4[0], e4[1], e4[2], e4[3]);
+            }
+        }
+    }
+    // side halos: r columns on each side, at most (32 + 2*16) * 2*16 = 2048 bytes
+    constexpr int kHaloSlots = (kBlurTH + 2 * kMaxRadius) * 2 * kMaxRadius / 256;
+    uint8_t hb[kHaloSlots];
+#pragma unroll
+    for (int j = 0; j < kHaloSlots; ++j) {
+        hb[j] = 0;
+        const int idx = t + 256 * j;
+        if (idx >= eh * 2 * r) continue;
+        const int yy = idx / (2 * r), jj = idx % (2 * r);
+        const int xx = jj < r ? jj : kBlurTW + jj;
+        const int X = x0 - r + xx, Y = y0 - r + yy;
+        if (X >= 0 && X < W && Y >= 0 && Y < H) hb[j] = a.Ei[(long long)Y * W + X];
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxSlots; ++j) {
+        const int idx = t + 256 * j;
+        const int yy = idx / kWords, q = idx % kWords;
+        if (yy >= eh) continue;
+        uint8_t* d = es + yy * kBlurLW + r + 4 * q;
+        d[0] = v[j].x;
+        d[1] = v[j].y;
+        d[2] = v[j].z;
+        d[3] = v[j].w;
+    }
+#pragma unroll
+    for (int j = 0; j < kHaloSlots; ++j) {
+        const int idx = t + 256 * j;
+        if (idx >= eh * 2 * r) continue;
+        const int yy = idx / (2 * r), jj = idx % (2 * r);
+        const int xx = jj < r ? jj : kBlurTW + jj;
+        es[yy * kBlurLW + xx] = hb[j];
+    }
+    __syncthreads();
+}
+
+// radius <= 8: every such level of the frame in one launch.  Tiles of all
+// levels share one index range; the plain block order spreads the costlier
+// coarse-level tiles over all XCDs.
+__global__ __launch_bounds__(256) void k_blur(BlurArgs A) {
+    __shared__ uint8_t es[(kBlurTH + 2 * kMaxRadius) * kBlurLW];
+    const unsigned b = blockIdx.x;
+    int l = 0;
+    while (l + 1 < A.nlev && b >= A.lv[l + 1].tile_base) ++l;
+    const BlurLevel& a = A.lv[l];
+    const unsigned tile = b - a.tile_base;
+    const int x0 = (int)(tile % a.tiles_x) * kBlurTW;
+    const int y0 = (int)(tile / a.tiles_x) * kBlurTH;
+    blur_stage(a, es, x0, y0);
+    const int r = a.r;
+    switch (r) {
+#define MR_BLUR_CASE(R) \
+    case R: blur_columns<R>(a, es, x0, y0); break;
+        MR_BLUR_CASE(0) MR_BLUR_CASE(1) MR_BLUR_CASE(2) MR_BLUR_CASE(3) MR_BLUR_CASE(4) MR_BLUR_CASE(5)
+        MR_BLUR_CASE(6) MR_BLUR_CASE(7) MR_BLUR_CASE(8)
+#undef MR_BLUR_CASE
+        default: break;
+    }
+}
+
+// radius 9..16: one launch per level, radius fixed at compile time
+template <int R>
+__global__ __launch_bounds__(256) void k_blur_wide(BlurLevel a) {
+    __shared__ uint8_t es[(kBlurTH + 2 * kMaxRadius) * kBlurLW];
+    const unsigned tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int x0 = (int)(tile % a.tiles_x) * kBlurTW;
+    const int y0 = (int)(tile / a.tiles_x) * kBlurTH;
+    blur_stage(a, es, x0, y0);
+    blur_columns<R>(a, es, x0, y0);
+}
+
+hipError_t launch_blur_wide(const BlurLevel& a, hipStream_t s) {
+    const unsigned n = a.tiles_x * (unsigned)((a.H + kBlurTH - 1) / kBlurTH);
+    switch (a.r) {
+#define MR_BLUR_WIDE(R) \
+    case R: hipLaunchKernelGGL(k_blur_wide<R>, dim3(n), dim3(256), 0, s, a); break;
+        MR_BLUR_WIDE(9) MR_BLUR_WIDE(10) MR_BLUR_WIDE(11) MR_BLUR_WIDE(12) MR_BLUR_WIDE(13) MR_BLUR_WIDE(14)
+        MR_BLUR_WIDE(15) MR_BLUR_WIDE(16)
+#undef MR_BLUR_WIDE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_blur(const BlurArgs& a, hipStream_t s) {
-    const unsigned tx = (a.W + kBlurTW - 1) / kBlurTW, ty = (a.H + kBlurTH - 1) / kBlurTH;
-    hipLaunchKernelGGL(k_blur, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    if (a.nlev == 0 || a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_blur, dim3(a.ntiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -16,101 +16,250 @@
 namespace mr {
 
 struct Taps {
-    long long i00, i01, i10, i11;
+    int i00, i01, i10, i11;  // LDS indices of the four taps
     float b0, b1, b2, b3;
 };
 
-__device__ __forceinline__ Taps make_taps(int X, int Y, const MergeLevel& L) {
-    const float inv_s = 1.0f / (float)L.s;  // exact: s is a power of two
-    const float u = ((float)X + 0.5f) * inv_s - 0.5f;
-    const float v = ((float)Y + 0.5f) * inv_s - 0.5f;
-    const float x0f = floorf(u), y0f = floorf(v);
-    const float fx = u - x0f, fy = v - y0f;
-    const int x0 = (int)x0f, y0 = (int)y0f;
-    const int xa = min(max(x0, 0), L.W - 1), xb = min(max(x0 + 1, 0), L.W - 1);
-    const int ya = min(max(y0, 0), L.H - 1), yb = min(max(y0 + 1, 0), L.H - 1);
-    Taps t;
-    t.i00 = (long long)ya * L.W + xa;
-    t.i01 = (long long)ya * L.W + xb;
-    t.i10 = (long long)yb * L.W + xa;
-    t.i11 = (long long)yb * L.W + xb;
-    const float gx = 1.0f - fx, gy = 1.0f - fy;
-    t.b0 = gx * gy;
-    t.b1 = fx * gy;
-    t.b2 = gx * fy;
-    t.b3 = fx * fy;
-    return t;
+// One axis of the bilinear taps at full-res coordinate X for scale s = 2^sh:
+// u = (X + 0.5) / s - 0.5 is the exact dyadic (m + 0.5) / s with m = X - s/2,
+// so floor(u) = m >> sh (floor division) and u - floor(u) = ((m mod s) + 0.5) / s;
+// both are computed exactly here with integers.  Taps are clamped to the
+// level and returned relative to the staged region's origin `lo`.
+__device__ __forceinline__ void axis_taps(int X, int sh, int n, int lo, int& ia, int& ib, float& f) {
+    const int s = 1 << sh;
+    const int m = X - (s >> 1);
+    const int x0 = m >> sh;
+    f = ((float)(m & (s - 1)) + 0.5f) * (1.0f / (float)s);
+    ia = min(max(x0, 0), n - 1) - lo;
+    ib = min(max(x0 + 1, 0), n - 1) - lo;
 }
 
 template <int C>
 __global__ __launch_bounds__(256) void k_merge(MergeArgs a, unsigned tiles_x, unsigned ntiles) {
+    __shared__ float la[kMergeLDS];
+    __shared__ uint8_t ls[kMergeLDS];
+    __shared__ float lc[C][kMergeLDS];
     const unsigned tile = xcd_remap(blockIdx.x, ntiles);
-    const int X = (int)(tile % tiles_x) * 64 + (threadIdx.x & 63);
-    const int Y = (int)(tile / tiles_x) * 4 + (threadIdx.x >> 6);
-    if (X >= a.W || Y >= a.H) return;
-    const int nl = a.nlev;
-    float out[C];
-    // coarsest level: plain bilinear (its stencil covers everything)
+    const int x0 = (int)(tile % tiles_x) * kMergeTW;
+    const int y0 = (int)(tile / tiles_x) * kMergeTH;
+    const int nl = a.nlev, t = threadIdx.x;
+    const bool fine1 = a.lv[0].s == 1 && nl > 1;  // level 1 is read per pixel from memory
+    // ---- issue every load of the tile before the first LDS store ----
+    constexpr int kSlots = (kMergeLDS + 255) / 256;
+    uint8_t sv[kSlots];
+    float av[kSlots], cv[kSlots][C];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int idx = t + 256 * j;
+        sv[j] = 0;
+        av[j] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) cv[j][c] = 0.0f;
+        if (idx >= a.staged) continue;
+        const uint8_t* Sp = nullptr;
+        const float* ap = nullptr;
+        const float* cp = nullptr;
+        long long cpl = 0, p = 0;
+        bool coarsest = false;
+#pragma unroll
+        for (int q = 0; q < kMaxLevels; ++q) {
+            const MergeLevel& L = a.lv[q];
+            if (q < nl && L.s != 1 && idx >= L.roff && idx < L.roff + L.rw * L.rh) {
+                const int k = idx - L.roff;
+                const int yy = (int)(((unsigned)k * L.rmagic) >> 16), xx = k - yy * L.rw;
+                const int Xl = min(max((x0 >> L.sh) - 1 + xx, 0), L.W - 1);
+                const int Yl = min(max((y0 >> L.sh) - 1 + yy, 0), L.H - 1);
+                p = (long long)Yl * L.W + Xl;
+                Sp = L.S;
+                ap = L.a;
+                cp = L.c;
+                cpl = L.c_plane;
+                coarsest = q == nl - 1;
+            }
+        }
+        sv[j] = coarsest ? 1 : Sp[p];
+        av[j] = coarsest ? 0.0f : ap[p];
+#pragma unroll
+        for (int c = 0; c < C; ++c) cv[j][c] = cp[c * cpl + p];
+    }
+    const int q = t & 15, row = t >> 4;
+    const int Y = y0 + row;
+    const int XQ = x0 + 4 * q;
+    const bool active = Y < a.H && XQ < a.W;
+    uint8_t s1[4] = {0, 0, 0, 0};
+    float a1[4] = {0, 0, 0, 0}, c1[C][4];
+#pragma unroll
+    for (int c = 0; c < C; ++c) c1[c][0] = c1[c][1] = c1[c][2] = c1[c][3] = 0.0f;
+    const bool vec = (a.W & 3) == 0;
+    if (fine1 && active) {
+        const MergeLevel& L = a.lv[0];
+        const long long p = (long long)Y * L.W + XQ;
+        if (vec) {
+            const uchar4 s4 = *reinterpret_cast<const uchar4*>(L.S + p);
+            s1[0] = s4.x;
+            s1[1] = s4.y;
+            s1[2] = s4.z;
+            s1[3] = s4.w;
+            const float4 a4 = *reinterpret_cast<const float4*>(L.a + p);
+            a1[0] = a4.x;
+            a1[1] = a4.y;
+            a1[2] = a4.z;
+            a1[3] = a4.w;
+            if (s1[0] | s1[1] | s1[2] | s1[3]) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float4 c4 = *reinterpret_cast<const float4*>(L.c + c * L.c_plane + p);
+                    c1[c][0] = c4.x;
+                    c1[c][1] = c4.y;
+                    c1[c][2] = c4.z;
+                    c1[c][3] = c4.w;
+                }
+            }
+        } else {
+            for (int k = 0; k < 4; ++k) {
+                const bool in = XQ + k < a.W;
+                s1[k] = in ? L.S[p + k] : 0;
+                a1[k] = in ? L.a[p + k] : 0.0f;
+                for (int c = 0; c < C; ++c) c1[c][k] = (in && s1[k]) ? L.c[c * L.c_plane + p + k] : 0.0f;
+            }
+        }
+    }
+    // ---- stage the coarse levels ----
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int idx = t + 256 * j;
+        if (idx >= a.staged) continue;
+        ls[idx] = sv[j];
+        la[idx] = av[j];
+#pragma unroll
+        for (int c = 0; c < C; ++c) lc[c][idx] = sv[j] ? cv[j][c] : 0.0f;
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // ---- blend: levels outer (coarse to fine), the thread's 4 pixels inner ----
+    float out[C][4];
     {
+        // coarsest level: plain bilinear (its stencil covers everything, so
+        // the normalising sum of the weights is exactly 1 and num / 1 = num)
         const MergeLevel& L = a.lv[nl - 1];
         if (L.s == 1) {
-            const long long p = (long long)Y * L.W + X;
-            for (int c = 0; c < C; ++c) out[c] = L.c[c * L.c_plane + p];
+            const long long p = (long long)Y * L.W + XQ;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < C; ++c) out[c][k] = XQ + k < a.W ? L.c[c * L.c_plane + p + k] : 0.0f;
         } else {
-            const Taps t = make_taps(X, Y, L);
-            for (int c = 0; c < C; ++c) {
-                const float* cc = L.c + c * L.c_plane;
-                float num = t.b0 * cc[t.i00];
-                num = num + t.b1 * cc[t.i01];
-                num = num + t.b2 * cc[t.i10];
-                num = num + t.b3 * cc[t.i11];
-                // den = b0 + b1 + b2 + b3 = 1 exactly
-                out[c] = num / (((t.b0 + t.b1) + t.b2) + t.b3);
+            int ya, yb;
+            float fy;
+            axis_taps(Y, L.sh, L.H, (y0 >> L.sh) - 1, ya, yb, fy);
+            const float gy = 1.0f - fy;
+            const int r0 = L.roff + ya * L.rw, r1 = L.roff + yb * L.rw;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int xa, xb;
+                float fx;
+                axis_taps(XQ + k, L.sh, L.W, (x0 >> L.sh) - 1, xa, xb, fx);
+                const float gx = 1.0f - fx;
+                const float b0 = gx * gy, b1 = fx * gy, b2 = gx * fy, b3 = fx * fy;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    float num = b0 * lc[c][r0 + xa];
+                    num = num + b1 * lc[c][r0 + xb];
+                    num = num + b2 * lc[c][r1 + xa];
+                    num = num + b3 * lc[c][r1 + xb];
+                    out[c][k] = num;
+                }
             }
         }
     }
+    // finer levels.  alpha = 0 leaves the composite unchanged bit for bit
+    // (C * 0 + c' * 1 = c' for the finite C >= 0 of every level), so a level
+    // with A = 0 at all four pixels is skipped; otherwise the four pixels are
+    // blended branch-free with alpha = 0 where A = 0 or no tap is in the
+    // stencil.  A full stencil has den = 1 and num / 1 = num.
     for (int j = nl - 2; j >= 0; --j) {
         const MergeLevel& L = a.lv[j];
-        float Ci[C];
-        float alpha;
-        if (L.s == 1) {
-            const long long p = (long long)Y * L.W + X;
-            const bool in = L.S[p] != 0;
-            for (int c = 0; c < C; ++c) Ci[c] = in ? L.c[c * L.c_plane + p] : 0.0f;
-            alpha = in ? fminf(L.a[p] * L.w, 1.0f) : 0.0f;
-        } else {
-            const Taps t = make_taps(X, Y, L);
-            const bool s0 = L.S[t.i00] != 0, s1 = L.S[t.i01] != 0;
-            const bool s2 = L.S[t.i10] != 0, s3 = L.S[t.i11] != 0;
-            float den = s0 ? t.b0 : 0.0f;
-            den = den + (s1 ? t.b1 : 0.0f);
-            den = den + (s2 ? t.b2 : 0.0f);
-            den = den + (s3 ? t.b3 : 0.0f);
-            float A = t.b0 * L.a[t.i00];
-            A = A + t.b1 * L.a[t.i01];
-            A = A + t.b2 * L.a[t.i10];
-            A = A + t.b3 * L.a[t.i11];
-            const bool any = den > 0.0f;
-            alpha = any ? fminf(A * L.w, 1.0f) : 0.0f;
+        if (j == 0 && fine1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool in = s1[k] != 0;
+                const float alpha = in ? fminf(a1[k] * L.w, 1.0f) : 0.0f;
+                const float om = 1.0f - alpha;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float Ci = in ? c1[c][k] : 0.0f;
+                    out[c][k] = Ci * alpha + out[c][k] * om;
+                }
+            }
+            continue;
+        }
+        int ya, yb;
+        float fy;
+        axis_taps(Y, L.sh, L.H, (y0 >> L.sh) - 1, ya, yb, fy);
+        const float gy = 1.0f - fy;
+        const int r0 = L.roff + ya * L.rw, r1 = L.roff + yb * L.rw;
+        float A[4], b[4][4];
+        int ix[4][2];
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int xa, xb;
+            float fx;
+            axis_taps(XQ + k, L.sh, L.W, (x0 >> L.sh) - 1, xa, xb, fx);
+            const float gx = 1.0f - fx;
+            b[k][0] = gx * gy;
+            b[k][1] = fx * gy;
+            b[k][2] = gx * fy;
+            b[k][3] = fx * fy;
+            ix[k][0] = xa;
+            ix[k][1] = xb;
+            float s_ = b[k][0] * la[r0 + xa];
+            s_ = s_ + b[k][1] * la[r0 + xb];
+            s_ = s_ + b[k][2] * la[r1 + xa];
+            s_ = s_ + b[k][3] * la[r1 + xb];
+            A[k] = s_;
+            nz |= s_ != 0.0f;
+        }
+        if (!nz) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i00 = r0 + ix[k][0], i01 = r0 + ix[k][1], i10 = r1 + ix[k][0], i11 = r1 + ix[k][1];
+            const bool e0 = ls[i00] != 0, e1 = ls[i01] != 0, e2 = ls[i10] != 0, e3 = ls[i11] != 0;
+            float den = e0 ? b[k][0] : 0.0f;
+            den = den + (e1 ? b[k][1] : 0.0f);
+            den = den + (e2 ? b[k][2] : 0.0f);
+            den = den + (e3 ? b[k][3] : 0.0f);
+            const bool use = A[k] != 0.0f && den > 0.0f;
+            const float alpha = use ? fminf(A[k] * L.w, 1.0f) : 0.0f;
+            const float om = 1.0f - alpha;
+            const float dd = use ? den : 1.0f;
+#pragma unroll
             for (int c = 0; c < C; ++c) {
-                const float* cc = L.c + c * L.c_plane;
-                float num = s0 ? t.b0 * cc[t.i00] : 0.0f;
-                num = num + (s1 ? t.b1 * cc[t.i01] : 0.0f);
-                num = num + (s2 ? t.b2 * cc[t.i10] : 0.0f);
-                num = num + (s3 ? t.b3 * cc[t.i11] : 0.0f);
-                Ci[c] = any ? num / den : 0.0f;
+                float num = e0 ? b[k][0] * lc[c][i00] : 0.0f;
+                num = num + (e1 ? b[k][1] * lc[c][i01] : 0.0f);
+                num = num + (e2 ? b[k][2] * lc[c][i10] : 0.0f);
+                num = num + (e3 ? b[k][3] * lc[c][i11] : 0.0f);
+                const float Ci = use ? (dd == 1.0f ? num : num / dd) : 0.0f;
+                out[c][k] = Ci * alpha + out[c][k] * om;
             }
         }
-        const float om = 1.0f - alpha;
-        for (int c = 0; c < C; ++c) out[c] = Ci[c] * alpha + out[c] * om;
     }
-    const long long p = (long long)Y * a.W + X;
+    // ---- store ----
+    const long long p = (long long)Y * a.W + XQ;
     const long long plane = (long long)a.W * a.H;
-    for (int c = 0; c < C; ++c) a.out[c * plane + p] = out[c];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (vec) {
+            *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
+        } else {
+            for (int k = 0; k < 4 && XQ + k < a.W; ++k) a.out[c * plane + p + k] = out[c][k];
+        }
+    }
 }
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
-    const unsigned tx = (a.W + 63) / 64, ty = (a.H + 3) / 4;
+    const unsigned tx = (a.W + kMergeTW - 1) / kMergeTW, ty = (a.H + kMergeTH - 1) / kMergeTH;
     if (a.C == 3)
         hipLaunchKernelGGL(k_merge<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
     else

@@ -67,17 +67,23 @@ hipError_t launch_hard(const HardArgs& a, hipStream_t s) {
 }
 
 __global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
+    __shared__ float bds[2 * kLdsSamples], pds[2 * kLdsSamples];
+    const float* bd = 2 * a.nb <= 2 * kLdsSamples ? bds : a.bd;
+    const float* pd = 2 * a.np <= 2 * kLdsSamples ? pds : a.pd;
+    for (int i = threadIdx.x; i < 2 * a.nb && bd == bds; i += blockDim.x) bds[i] = a.bd[i];
+    for (int i = threadIdx.x; i < 2 * a.np && pd == pds; i += blockDim.x) pds[i] = a.pd[i];
+    __syncthreads();
     const ItemMap m = make_item_map(a.c);
-    const unsigned total = m.cum[m.nlev];
+    const unsigned total = item_total(m);
     const float lsz = a.fL * (0.5f * a.lsize);
     for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
-        const unsigned local = item - m.cum[j];
+        const unsigned local = item_local(m, item, j);
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
-        const float z = L.z[(long long)y * L.zpy + (long long)x * L.zpx];
+        const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float vis = 1.0f;
         if (valid_depth(z)) {
             float px, py, pz;
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
                 float bsum = 0.0f;
                 int bcnt = 0;
                 for (int k = 0; k < a.nb; ++k) {
-                    const float s = sm_tap(a.sm, a.size, c.su, c.sv, Rs, a.bd[2 * k], a.bd[2 * k + 1]);
+                    const float s = sm_tap(a.sm, a.size, c.su, c.sv, Rs, bd[2 * k], bd[2 * k + 1]);
                     if (s < thr) {
                         bsum = bsum + s;
                         ++bcnt;
@@ -101,7 +107,7 @@ __global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
                     int lit = 0;
                     for (int k = 0; k < a.np; ++k) {
                         const float s =
-                            sm_tap(a.sm, a.size, c.su, c.sv, Rf, a.pd[2 * k], a.pd[2 * k + 1]);
+                            sm_tap(a.sm, a.size, c.su, c.sv, Rf, pd[2 * k], pd[2 * k + 1]);
                         if (!(s < thr)) ++lit;
                     }
                     vis = (float)lit / (float)a.np;

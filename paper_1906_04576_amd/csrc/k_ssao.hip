@@ -7,54 +7,81 @@
 
 namespace mr {
 
-template <typename NT>
-__global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
-    const ItemMap m = make_item_map(a.c);
-    const unsigned total = m.cum[m.nlev];
-    const NT* nrm = static_cast<const NT*>(a.c.normal);
-    const long long plane = a.c.plane;
+// occlusion of one texel; K points to LDS (staged samples) or global memory
+template <typename NT, typename KP>
+__device__ __forceinline__ float ssao_texel(const SsaoArgs& a, const EvalLevel& L, const NT* nrm, unsigned plane,
+                                            KP K, int x, int y, float z) {
     const float r = a.r, b = a.b;
     const int S = a.S;
+    const float* zb = L.z;
+    const int zpy = L.zpy, zpx = L.zpx;
+    const unsigned g = (unsigned)L.goff + (unsigned)y * (unsigned)L.gpy + (unsigned)x * (unsigned)L.gpx;
+    const float nx = ld(nrm, g), ny = ld(nrm, plane + g), nz = ld(nrm, 2 * plane + g);
+    float px, py, pz;
+    view_pos(x, y, z, L.f, L.cx, L.cy, px, py, pz);
+    float tx, ty, tz, bx, by, bz;
+    onb(nx, ny, nz, tx, ty, tz, bx, by, bz);
+    const float rtx = r * tx, rty = r * ty, rtz = r * tz;
+    const float rbx = r * bx, rby = r * by, rbz = r * bz;
+    const float rnx = r * nx, rny = r * ny, rnz = r * nz;
+    const float Wf = (float)L.W, Hf = (float)L.H;
+    const float f = L.f, cx = L.cx, cy = L.cy;
+    int occ = 0;
+    for (int s = 0; s < S; ++s) {
+        const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
+        const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
+        const float d = -qz;
+        if (!(d > 0.0f)) continue;
+        const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
+        const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
+        const float inv = 1.0f / d;
+        const float u = cx + (qx * inv) * f;
+        const float v = cy - (qy * inv) * f;
+        if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
+        // u, v >= 0 here, so truncation is floor
+        const int sx = (int)u, sy = (int)v;
+        const float zs = zb[(unsigned)sy * zpy + (unsigned)sx * zpx];
+        // z_s <= 0 must not count; +inf and NaN fail the first test below
+        if (!(zs > 0.0f)) continue;
+        if (zs < d - (b * d) && fabsf(z - zs) < r) ++occ;
+    }
+    return (float)occ / (float)S;
+}
+
+template <typename NT, bool KLDS>
+__device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks) {
+    const ItemMap m = make_item_map(a.c);
+    const unsigned total = item_total(m);
+    const NT* nrm = static_cast<const NT*>(a.c.normal);
+    const unsigned plane = (unsigned)a.c.plane;
     for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
-        const unsigned local = item - m.cum[j];
+        const unsigned local = item_local(m, item, j);
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
-        const float z = L.z[(long long)y * L.zpy + (long long)x * L.zpx];
+        const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float res = 0.0f;
         if (valid_depth(z)) {
-            const long long g = L.goff + (long long)y * L.gpy + (long long)x * L.gpx;
-            const float nx = ld(nrm, g), ny = ld(nrm, plane + g), nz = ld(nrm, 2 * plane + g);
-            float px, py, pz;
-            view_pos(x, y, z, L.f, L.cx, L.cy, px, py, pz);
-            float tx, ty, tz, bx, by, bz;
-            onb(nx, ny, nz, tx, ty, tz, bx, by, bz);
-            const float rtx = r * tx, rty = r * ty, rtz = r * tz;
-            const float rbx = r * bx, rby = r * by, rbz = r * bz;
-            const float rnx = r * nx, rny = r * ny, rnz = r * nz;
-            const float Wf = (float)L.W, Hf = (float)L.H;
-            int occ = 0;
-            for (int s = 0; s < S; ++s) {
-                const float kx = a.kernel[3 * s], ky = a.kernel[3 * s + 1], kz = a.kernel[3 * s + 2];
-                const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
-                const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
-                const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
-                const float d = -qz;
-                if (!(d > 0.0f)) continue;
-                const float inv = 1.0f / d;
-                const float u = L.cx + (qx * inv) * L.f;
-                const float v = L.cy - (qy * inv) * L.f;
-                if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
-                const int sx = (int)floorf(u), sy = (int)floorf(v);
-                const float zs = L.z[(long long)sy * L.zpy + (long long)sx * L.zpx];
-                if (!valid_depth(zs)) continue;
-                if (zs < d - (b * d) && fabsf(z - zs) < r) ++occ;
-            }
-            res = (float)occ / (float)S;
+            if (KLDS)
+                res = ssao_texel<NT>(a, L, nrm, plane, ks, x, y, z);
+            else
+                res = ssao_texel<NT>(a, L, nrm, plane, a.kernel, x, y, z);
         }
-        L.out[(long long)y * L.W + x] = res;
+        L.out[(unsigned)y * (unsigned)L.W + (unsigned)x] = res;
+    }
+}
+
+template <typename NT>
+__global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
+    __shared__ float ks[3 * kLdsSamples];
+    if (a.S <= kLdsSamples) {
+        for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
+        __syncthreads();
+        ssao_items<NT, true>(a, ks);
+    } else {
+        ssao_items<NT, false>(a, ks);
     }
 }
 

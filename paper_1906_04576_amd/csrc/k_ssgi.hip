@@ -11,8 +11,10 @@ namespace mr {
 
 template <typename NT, typename CT>
 __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
+    __shared__ float ks[3 * kLdsSamples];
+    const float* K = stage_samples(a.kernel, 3 * a.S, ks);
     const ItemMap m = make_item_map(a.c);
-    const unsigned total = m.cum[m.nlev];
+    const unsigned total = item_total(m);
     const NT* nrm = static_cast<const NT*>(a.c.normal);
     const CT* col = static_cast<const CT*>(a.c.color);
     const long long plane = a.c.plane;
@@ -24,11 +26,11 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
     for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
-        const unsigned local = item - m.cum[j];
+        const unsigned local = item_local(m, item, j);
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
-        const float z = L.z[(long long)y * L.zpy + (long long)x * L.zpx];
+        const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
         if (valid_depth(z)) {
             const long long g = L.goff + (long long)y * L.gpy + (long long)x * L.gpx;
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
             const float rnx = r * nx, rny = r * ny, rnz = r * nz;
             const float Wf = (float)L.W, Hf = (float)L.H;
             for (int s = 0; s < S; ++s) {
-                const float kx = a.kernel[3 * s], ky = a.kernel[3 * s + 1], kz = a.kernel[3 * s + 2];
+                const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
                 const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
                 const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
                 const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
                 const float v = L.cy - (qy * inv) * L.f;
                 if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
                 const int sx = (int)floorf(u), sy = (int)floorf(v);
-                const float zs = L.z[(long long)sy * L.zpy + (long long)sx * L.zpx];
+                const float zs = L.z[(unsigned)sy * L.zpy + (unsigned)sx * L.zpx];
                 if (!valid_depth(zs)) continue;
                 if (!(zs < d - (b * d) && fabsf(z - zs) < r)) continue;
                 float hx, hy, hz;

@@ -26,6 +26,21 @@ __device__ __forceinline__ float ld(const T* p, long long i) {
     return static_cast<float>(p[i]);
 }
 
+// Raw buffer resource over `bytes` bytes at `p` (gfx9 family: dword 3 =
+// 0x00020000).  Every load issued through these below is kept in range by
+// clamping its offset; the hardware range check is never relied on.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0));
+}
+
+__device__ __forceinline__ float buf_f1(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
 // Blocks of a 1-D grid are handed to the 8 XCDs round robin (block b runs on
 // XCD b % 8).  Remap so that every XCD works on one contiguous range of tiles:
 // neighbouring tiles then share that XCD's L2 (halo rows and columns hit).
@@ -50,12 +65,19 @@ struct EdgeArgs {
     int num_levels;
 };
 
-struct BlurArgs {
+struct BlurLevel {
     const uint8_t* Ei;
     float* a;
     uint8_t* S;
     int W, H, r;
+    unsigned tiles_x, tile_base;
     float g[2 * kMaxRadius + 1];
+};
+
+struct BlurArgs {
+    BlurLevel lv[kMaxLevels - 1];  // every enabled level below the coarsest
+    int nlev;
+    unsigned ntiles;
 };
 
 struct NestArgs {
@@ -90,8 +112,7 @@ struct CompactArgs {
 // element index goff + y * gpy + x * gpx of their planes.
 struct EvalLevel {
     const float* z;
-    long long zpy;
-    int zpx;
+    int zpy, zpx;  // element strides of the depth view (32-bit: images are at most 16384^2)
     long long goff, gpy;
     int gpx;
     int W, H;
@@ -153,22 +174,33 @@ struct MergeLevel {
     long long c_plane;
     const float* a;     // null for the coarsest
     const uint8_t* S;   // null for the coarsest
-    int s, W, H;
+    int s, sh, W, H;    // scale s = 2^sh and level size
     float w;
+    // levels with s >= 2: texels a 64 x 16 pixel tile's bilinear taps can
+    // touch, rw x rh starting at ((x0 >> sh) - 1, (y0 >> sh) - 1), staged at
+    // LDS offset roff; rmagic = ceil(65536 / rw) divides the staging index
+    int rw, rh, roff;
+    unsigned rmagic;
 };
 
 struct MergeArgs {
     MergeLevel lv[kMaxLevels];  // enabled levels ascending; last = coarsest
     int nlev;
     int W, H, C;
+    int staged;  // total staged texels
     float* out;
 };
+
+constexpr int kMergeTW = 64, kMergeTH = 16;
+constexpr int kMergeLDS = 640;  // >= sum of rw * rh over levels 2..6 (518)
 
 // ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 // ---------------------------------------------------------------------------
 hipError_t launch_edges(const EdgeArgs& a, int normal_dtype, hipStream_t s);
-hipError_t launch_blur(const BlurArgs& a, hipStream_t s);
+hipError_t launch_blur(const BlurArgs& a, hipStream_t s);       // levels with radius <= 8
+hipError_t launch_blur_wide(const BlurLevel& a, hipStream_t s);  // one level, radius 9..16
+constexpr int kBlurFusedMaxRadius = 8;
 hipError_t launch_nest(const NestArgs& a, hipStream_t s);
 hipError_t launch_level_map(const LevelMapArgs& a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s);

@@ -396,7 +396,7 @@ class FrameRunner:
     once so that repeated calls cost one ctypes call each."""
 
     def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
-                 out=None, level_map=None):
+                 out=None, level_map=None, workspace=None):
         self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         H, W = depth.shape
         C = 3 if self.effect == MR_EFFECT_SSGI else 1
@@ -420,7 +420,10 @@ class FrameRunner:
         self.desc = d
         self._keep = (depth, normal, color, level_map)
         nws = mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0
-        self.workspace = torch.empty(max(nws, 256), dtype=torch.uint8, device=depth.device)
+        if workspace is not None and workspace.numel() >= nws:
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(max(nws, 256), dtype=torch.uint8, device=depth.device)
         self._fn = lib().mr_frame
         self._ws = _ptr(self.workspace)
         self._nws = self.workspace.numel()
@@ -433,6 +436,52 @@ class FrameRunner:
 def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,
              level_map=None, stream=None):
     return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map)(stream)
+
+
+class Prepared:
+    """One C entry point with its ctypes arguments built once; calling it
+    costs a single foreign call (used where Python overhead would otherwise
+    leave the GPU idle between short launches)."""
+
+    def __init__(self, name, args, keep=()):
+        self._fn = getattr(lib(), name)
+        self._args = args
+        self._keep = keep
+
+    def __call__(self):
+        _check(self._fn(*self._args))
+
+
+def prepare_build_masks(depth, normal, focal, mp: MaskParams, masks: Masks, hard_shadow=None, stream=None):
+    H, W = depth.shape
+    g, cam, cmp, cm = gbuffer(depth, normal), camera(W, H, focal), mp.c(), masks.c()
+    args = (ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cmp), _ptr(hard_shadow), ctypes.byref(cm),
+            _ptr(masks.workspace), masks.workspace.numel(), _stream(stream))
+    return Prepared("mr_build_masks", args, (g, cam, cmp, cm, masks, depth, normal, hard_shadow))
+
+
+def prepare_eval_ssao(depth, normal, focal, params: mr_ssao_params, out: dict, mp: MaskParams = None,
+                      masks: Masks = None, stream=None):
+    H, W = depth.shape
+    g, cam = gbuffer(depth, normal), camera(W, H, focal)
+    cmp = mp.c() if mp is not None else None
+    cm = masks.c() if masks is not None else None
+    arr = c_ptr6()
+    for i, t in out.items():
+        arr[i - 1] = t.data_ptr()
+    args = (ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cmp) if cmp is not None else None,
+            ctypes.byref(cm) if cm is not None else None, ctypes.byref(params), ctypes.byref(arr), _stream(stream))
+    return Prepared("mr_eval_ssao", args, (g, cam, cmp, cm, arr, params, out, masks, depth, normal))
+
+
+def prepare_upsample_merge(focal, mp: MaskParams, masks: Masks, level_out: dict, out, channels=1, stream=None):
+    cam, cmp, cm = camera(masks.W, masks.H, focal), mp.c(), masks.c()
+    arr = c_ptr6()
+    for i, t in level_out.items():
+        arr[i - 1] = t.data_ptr()
+    args = (ctypes.byref(cam), ctypes.byref(cmp), ctypes.byref(cm), ctypes.byref(arr), int(channels), _ptr(out),
+            _stream(stream))
+    return Prepared("mr_upsample_merge", args, (cam, cmp, cm, arr, masks, level_out, out))
 
 
 def mr_version() -> int:

@@ -42,6 +42,8 @@ CASES = {
                     (-1, -1, -1, -1)),
     "nest_r0": (192, 128, 30, 8, 6, 2, 4, 0b1111, (0.924, 0.0, 0.0, 0), (100, 50, 20, 1), 16, 1.0,
                 (-1, 0, 0, -1)),
+    "wide_radius": (256, 192, 30, 8, 7, 5, 4, 0b1111, (9.0, 1.848, 12.0, 0), (100, 50, 20, 1), 16, 1.0,
+                    (-1, 11, 16, -1)),
     "1080p": (1920, 1080, 200, 50, 1, 0, 4, 0b1111, (0.924, 1.848, 3.696, 0), (100, 50, 20, 1), 32, 1.0,
               (-1, -1, -1, -1)),
 }
