@@ -24,7 +24,7 @@ SOURCES = ["api.cpp", "k_masks.hip", "k_compact.hip", "k_ssao.hip", "k_shadow.hi
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
+         "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-Wno-bitwise-instead-of-logical", "-I", INCLUDE, "-I", CSRC]
 
 
 def _compile(src: str) -> str:

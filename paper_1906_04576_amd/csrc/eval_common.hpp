@@ -51,17 +51,10 @@ __device__ __forceinline__ unsigned item_local(const ItemMap& m, unsigned item, 
     return item - base;
 }
 
-// Sample sets are staged in LDS once per workgroup when they fit; the sample
-// loops then read them with uniform LDS addresses instead of a vector load
-// (and its full wait) per sample.
+// Sample sets of at most this many entries are staged in LDS once per
+// workgroup; the sample loops then read them with uniform LDS addresses
+// instead of a vector load (and its full wait) per sample.
 constexpr int kLdsSamples = 1024;
-
-__device__ __forceinline__ const float* stage_samples(const float* g, int nfloats, float* lds) {
-    if (nfloats > 3 * kLdsSamples) return g;
-    for (int i = threadIdx.x; i < nfloats; i += blockDim.x) lds[i] = g[i];
-    __syncthreads();
-    return lds;
-}
 
 // P = (X z, Y z, -z), X = ((x + 0.5) - cx) / f, Y = (cy - (y + 0.5)) / f
 __device__ __forceinline__ void view_pos(int x, int y, float z, float f, float cx, float cy,

@@ -66,16 +66,41 @@ hipError_t launch_hard(const HardArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
-    __shared__ float bds[2 * kLdsSamples], pds[2 * kLdsSamples];
-    const float* bd = 2 * a.nb <= 2 * kLdsSamples ? bds : a.bd;
-    const float* pd = 2 * a.np <= 2 * kLdsSamples ? pds : a.pd;
-    for (int i = threadIdx.x; i < 2 * a.nb && bd == bds; i += blockDim.x) bds[i] = a.bd[i];
-    for (int i = threadIdx.x; i < 2 * a.np && pd == pds; i += blockDim.x) pds[i] = a.pd[i];
-    __syncthreads();
+// visibility of one texel; BD / PD point to LDS (staged disks) or global memory
+template <typename DP>
+__device__ __forceinline__ float pcss_texel(const ShadowArgs& a, const EvalLevel& L, DP bd, DP pd, int x, int y,
+                                            float z) {
+    float px, py, pz;
+    view_pos(x, y, z, L.f, L.cx, L.cy, px, py, pz);
+    const LightCoord c = to_light(a.M, a.size, a.fL, px, py, pz);
+    if (!c.inside) return 1.0f;
+    const float lsz = a.fL * (0.5f * a.lsize);
+    const float thr = c.dr - a.bias;
+    const float Rs = (lsz * (c.dr - a.nL)) / (c.dr * a.nL);
+    float bsum = 0.0f;
+    int bcnt = 0;
+    for (int k = 0; k < a.nb; ++k) {
+        const float s = sm_tap(a.sm, a.size, c.su, c.sv, Rs, bd[2 * k], bd[2 * k + 1]);
+        if (s < thr) {
+            bsum = bsum + s;
+            ++bcnt;
+        }
+    }
+    if (bcnt == 0) return 1.0f;
+    const float db = bsum / (float)bcnt;
+    const float Rf = (lsz * (c.dr - db)) / (db * c.dr);
+    int lit = 0;
+    for (int k = 0; k < a.np; ++k) {
+        const float s = sm_tap(a.sm, a.size, c.su, c.sv, Rf, pd[2 * k], pd[2 * k + 1]);
+        if (!(s < thr)) ++lit;
+    }
+    return (float)lit / (float)a.np;
+}
+
+template <bool LDS>
+__device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds, const float* pds) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
-    const float lsz = a.fL * (0.5f * a.lsize);
     for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
@@ -86,35 +111,25 @@ __global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
         const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float vis = 1.0f;
         if (valid_depth(z)) {
-            float px, py, pz;
-            view_pos(x, y, z, L.f, L.cx, L.cy, px, py, pz);
-            const LightCoord c = to_light(a.M, a.size, a.fL, px, py, pz);
-            if (c.inside) {
-                const float thr = c.dr - a.bias;
-                const float Rs = (lsz * (c.dr - a.nL)) / (c.dr * a.nL);
-                float bsum = 0.0f;
-                int bcnt = 0;
-                for (int k = 0; k < a.nb; ++k) {
-                    const float s = sm_tap(a.sm, a.size, c.su, c.sv, Rs, bd[2 * k], bd[2 * k + 1]);
-                    if (s < thr) {
-                        bsum = bsum + s;
-                        ++bcnt;
-                    }
-                }
-                if (bcnt > 0) {
-                    const float db = bsum / (float)bcnt;
-                    const float Rf = (lsz * (c.dr - db)) / (db * c.dr);
-                    int lit = 0;
-                    for (int k = 0; k < a.np; ++k) {
-                        const float s =
-                            sm_tap(a.sm, a.size, c.su, c.sv, Rf, pd[2 * k], pd[2 * k + 1]);
-                        if (!(s < thr)) ++lit;
-                    }
-                    vis = (float)lit / (float)a.np;
-                }
-            }
+            if (LDS)
+                vis = pcss_texel(a, L, bds, pds, x, y, z);
+            else
+                vis = pcss_texel(a, L, a.bd, a.pd, x, y, z);
         }
-        L.out[(long long)y * L.W + x] = vis;
+        L.out[(unsigned)y * (unsigned)L.W + (unsigned)x] = vis;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
+    __shared__ float bds[2 * kLdsSamples], pds[2 * kLdsSamples];
+    const bool staged = a.nb <= kLdsSamples && a.np <= kLdsSamples;  // uniform
+    if (staged) {
+        for (int i = threadIdx.x; i < 2 * a.nb; i += 256) bds[i] = a.bd[i];
+        for (int i = threadIdx.x; i < 2 * a.np; i += 256) pds[i] = a.pd[i];
+        __syncthreads();
+        pcss_items<true>(a, bds, pds);
+    } else {
+        pcss_items<false>(a, bds, pds);
     }
 }
 

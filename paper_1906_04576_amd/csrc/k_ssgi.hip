@@ -9,10 +9,8 @@
 
 namespace mr {
 
-template <typename NT, typename CT>
-__global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
-    __shared__ float ks[3 * kLdsSamples];
-    const float* K = stage_samples(a.kernel, 3 * a.S, ks);
+template <typename NT, typename CT, typename KP>
+__device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
     const NT* nrm = static_cast<const NT*>(a.c.normal);
@@ -80,6 +78,18 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
         L.out[o] = acc0 * scale;
         L.out[L.out_plane + o] = acc1 * scale;
         L.out[2 * L.out_plane + o] = acc2 * scale;
+    }
+}
+
+template <typename NT, typename CT>
+__global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
+    __shared__ float ks[3 * kLdsSamples];
+    if (a.S <= kLdsSamples) {  // uniform
+        for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
+        __syncthreads();
+        ssgi_items<NT, CT>(a, (const float*)ks);
+    } else {
+        ssgi_items<NT, CT>(a, a.kernel);
     }
 }
 

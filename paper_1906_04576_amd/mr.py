@@ -316,8 +316,12 @@ def g_device(g):
 
 
 def ssao_params(kernel, radius, bias_rel) -> mr_ssao_params:
+    """SSAO / SSGI sampling parameters.  The returned struct holds a reference
+    to `kernel`, so the device memory it points to lives as long as it does."""
     _dev(kernel, "kernel")
-    return mr_ssao_params(_ptr(kernel), int(kernel.shape[0]), float(radius), float(bias_rel))
+    p = mr_ssao_params(_ptr(kernel), int(kernel.shape[0]), float(radius), float(bias_rel))
+    p._tensors = (kernel,)
+    return p
 
 
 def mr_eval_ssao(depth, normal, focal, kernel, radius, bias_rel, mp: MaskParams = None, masks: Masks = None,
@@ -348,6 +352,8 @@ def shadow_params(shadow_map, view_to_light, light_focal, light_size, light_near
     p.pcf_disk = _ptr(pcf_disk)
     p.n_blocker = int(blocker_disk.shape[0])
     p.n_pcf = int(pcf_disk.shape[0])
+    # keep the device arrays alive as long as the struct that points to them
+    p._tensors = (shadow_map, blocker_disk, pcf_disk)
     return p
 
 
