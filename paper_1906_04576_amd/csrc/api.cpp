@@ -272,6 +272,80 @@ FrameLayout frame_layout(const Geo& g, int effect) {
 }
 
 // ---------------------------------------------------------------------------
+// lean frame path eligibility and layout
+// ---------------------------------------------------------------------------
+// The lean path stores the stencils as bits and a_i / sub-image values only at
+// stencil texels.  It needs: the coarsest enabled level L <= 4 (bit outputs
+// exist for levels 1..3), W divisible by 128 (whole bit words per row at
+// levels 1..3), and for every enabled level below L a radius <= 8 whose
+// Gaussian taps are all positive with no product of two taps underflowing
+// (then a_i > 0 exactly on the Chebyshev dilation of the pooled edges), and
+// radii for which the nesting step changes nothing (r_j >= ceil(r_i / k)).
+bool lean_ok(const Geo& g, const mr_mask_params* mp) {
+    if (g.L > 4 || g.nlev < 2 || g.W % 128 != 0) return false;
+    int radius[kMaxLevels] = {};
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        float taps[2 * kMaxRadius + 1];
+        int r;
+        if (gauss(mp, i, taps, r)) return false;
+        if (r > kBlurFusedMaxRadius) return false;
+        float gmin = 1.0f;
+        for (int k = 0; k <= 2 * r; ++k) gmin = taps[k] < gmin ? taps[k] : gmin;
+        // smallest positive binary32 (denormal) is 2^-149
+        if (!(gmin > 0.0f) || (double)gmin * (double)gmin < ldexp(1.0, -149)) return false;
+        radius[i - 1] = r;
+    }
+    for (int j = 0; j + 2 < g.nlev; ++j) {
+        const int fi = g.levels[j], ci = g.levels[j + 1];
+        const int k = 1 << (ci - fi);
+        if (radius[ci - 1] < (radius[fi - 1] + k - 1) / k) return false;
+    }
+    return true;
+}
+
+struct LeanLayout {
+    size_t count = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, ac[3] = {}, cc[3] = {};
+    size_t zi[kMaxLevels] = {}, cL = 0, blk_sum = 0, blk_off = 0, hard = 0;
+    unsigned nblk = 0;
+    size_t bytes = 0;
+};
+
+LeanLayout lean_layout(const Geo& g, int effect) {
+    LeanLayout f;
+    const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        size_t o = off;
+        off += align256(n);
+        return o;
+    };
+    f.count = take(4 * kMaxLevels);
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        const size_t n = (size_t)g.n(i);
+        const size_t words = (size_t)(g.Wi[i - 1] / 32) * g.Hi[i - 1];
+        f.Eb[i - 1] = take(4 * words);
+        f.Sb[i - 1] = take(4 * words);
+        f.woff[i - 1] = take(4 * words);
+        f.list[i - 1] = take(4 * n);
+        f.ac[i - 1] = take(4 * n);
+        f.cc[i - 1] = take(4 * n * C);
+        f.nblk += (unsigned)((words + 255) / 256);
+    }
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i >= 2) f.zi[i - 1] = take(4 * (size_t)g.n(i));
+    }
+    f.cL = take(4 * (size_t)g.n(g.L) * C);
+    f.blk_sum = take(4 * (size_t)f.nblk + 4);
+    f.blk_off = take(4 * (size_t)f.nblk + 4);
+    if (effect == MR_EFFECT_SHADOW) f.hard = take((size_t)g.W * g.H);
+    f.bytes = off;
+    return f;
+}
+
+// ---------------------------------------------------------------------------
 // pipeline pieces (arguments already validated)
 // ---------------------------------------------------------------------------
 int do_build_masks(const mr_gbuffer* gb, const Geo& g, const mr_mask_params* mp, const uint8_t* hard,
@@ -431,8 +505,27 @@ void set_level_cameras(const mr_camera* cam, const Geo& g, EvalCommon& c, bool p
     }
 }
 
+// compact: list levels write their results at the list position; lean (with
+// compact) also has the evaluators write a_i at the list position
 int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g, const mr_masks* m,
-            const void* params, float* const out[kMaxLevels], hipStream_t s) {
+            const void* params, float* const out[kMaxLevels], hipStream_t s, bool compact = false,
+            const LeanArgs* lean = nullptr) {
+    auto set_compact = [&](EvalCommon& c) {
+        if (!compact) return;
+        for (int j = 0; j < c.nlev; ++j) {
+            EvalLevel& L = c.lv[j];
+            if (!L.list) continue;
+            L.compact = 1;
+            if (lean) {
+                const LeanLevel& A = lean->lv[j];
+                L.ac = A.ac;
+                L.Eb = A.Eb;
+                L.Ewpr = A.wpr;
+                L.Er = A.r;
+                for (int k = 0; k <= 2 * A.r; ++k) L.Eg[k] = A.g[k];
+            }
+        }
+    };
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
     hipError_t e;
     if (effect == MR_EFFECT_SSAO) {
@@ -440,6 +533,7 @@ int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g
         SsaoArgs a{};
         const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
         set_level_cameras(cam, g, a.c, !m);
+        set_compact(a.c);
         a.kernel = p->kernel;
         a.S = p->samples;
         a.r = p->radius;
@@ -450,6 +544,7 @@ int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g
         ShadowArgs a{};
         const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
         set_level_cameras(cam, g, a.c, !m);
+        set_compact(a.c);
         a.sm = p->shadow_map;
         a.size = p->sm_size;
         memcpy(a.M, p->view_to_light, sizeof(a.M));
@@ -467,6 +562,7 @@ int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g
         SsgiArgs a{};
         const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
         set_level_cameras(cam, g, a.c, !m);
+        set_compact(a.c);
         a.kernel = p->kernel;
         a.S = p->samples;
         a.r = p->radius;
@@ -524,6 +620,144 @@ int check_effect_params(int effect, const mr_ssao_params* ssao, const mr_shadow_
     return fail(MR_E_PARAM, "unknown effect %d", effect);
 }
 
+int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, hipStream_t s) {
+    const int effect = d->effect;
+    const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    const LeanLayout f = lean_layout(g, effect);
+    uint32_t* count = reinterpret_cast<uint32_t*>(b + f.count);
+    const uint8_t* hard = nullptr;
+    if (effect == MR_EFFECT_SHADOW) {
+        HardArgs ha{};
+        ha.depth = d->g.depth;
+        ha.W = g.W;
+        ha.H = g.H;
+        ha.f = d->cam.focal_px;
+        ha.sm = d->shadow->shadow_map;
+        ha.size = d->shadow->sm_size;
+        memcpy(ha.M, d->shadow->view_to_light, sizeof(ha.M));
+        ha.fL = d->shadow->light_focal_px;
+        ha.bias = d->shadow->bias;
+        ha.hard = b + f.hard;
+        if (launch_hard(ha, s) != hipSuccess) return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
+        hard = b + f.hard;
+    }
+    // edges as bits, point-sampled level depth
+    EdgeArgs ea{};
+    ea.depth = d->g.depth;
+    ea.normal = d->g.normal;
+    ea.hard = hard;
+    ea.W = g.W;
+    ea.H = g.H;
+    ea.depth_ratio = d->mp.depth_ratio;
+    ea.normal_cos = d->mp.normal_cos;
+    ea.num_levels = g.N;
+    for (int i = 1; i <= g.N; ++i) {
+        ea.Wi[i - 1] = g.Wi[i - 1];
+        ea.Hi[i - 1] = g.Hi[i - 1];
+    }
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i >= 2) ea.zi[i - 1] = reinterpret_cast<float*>(b + f.zi[i - 1]);
+        if (i < g.L) {
+            ea.Eb[i - 1] = reinterpret_cast<uint32_t*>(b + f.Eb[i - 1]);
+            ea.wpr[i - 1] = g.Wi[i - 1] / 32;
+        }
+    }
+    if (launch_edges(ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
+    // stencils, ranks, lists, a_i at listed texels
+    LeanArgs la{};
+    la.nlev = g.nlev - 1;
+    la.count = count;
+    la.blk_sum = reinterpret_cast<uint32_t*>(b + f.blk_sum);
+    la.blk_off = reinterpret_cast<uint32_t*>(b + f.blk_off);
+    unsigned blk = 0;
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        LeanLevel& L = la.lv[j];
+        L.Eb = reinterpret_cast<uint32_t*>(b + f.Eb[i - 1]);
+        L.Sb = reinterpret_cast<uint32_t*>(b + f.Sb[i - 1]);
+        L.woff = reinterpret_cast<uint32_t*>(b + f.woff[i - 1]);
+        L.list = reinterpret_cast<uint32_t*>(b + f.list[i - 1]);
+        L.ac = reinterpret_cast<float*>(b + f.ac[i - 1]);
+        L.W = g.Wi[i - 1];
+        L.H = g.Hi[i - 1];
+        L.wpr = L.W / 32;
+        gauss(&d->mp, i, L.g, L.r);
+        L.nwords = (unsigned)L.wpr * (unsigned)L.H;
+        L.blk_base = blk;
+        L.count_idx = i - 1;
+        blk += (L.nwords + 255) / 256;
+    }
+    la.nblk = blk;
+    // a_i is written by the evaluation kernel (alpha_blocks = 0)
+    if (launch_lean_masks(la, 0, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "lean mask kernels launch failed");
+    if (d->level_map) {
+        LeanMapArgs lm{};
+        lm.nlev = g.nlev - 1;
+        for (int j = 0; j + 1 < g.nlev; ++j) {
+            lm.Sb[j] = la.lv[j].Sb;
+            lm.wpr[j] = la.lv[j].wpr;
+            lm.level[j] = g.levels[j];
+        }
+        lm.coarsest = g.L;
+        lm.W = g.W;
+        lm.H = g.H;
+        lm.out = d->level_map;
+        if (launch_lean_level_map(lm, s) != hipSuccess) return fail(MR_E_DEVICE, "level map kernel launch failed");
+    }
+    // per-level evaluation, list levels written by rank
+    mr_masks m{};
+    m.count = count;
+    float* lo[kMaxLevels] = {};
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        if (i >= 2) m.level_depth[i - 1] = reinterpret_cast<float*>(b + f.zi[i - 1]);
+        if (i < g.L) {
+            m.worklist[i - 1] = reinterpret_cast<uint32_t*>(b + f.list[i - 1]);
+            lo[i - 1] = reinterpret_cast<float*>(b + f.cc[i - 1]);
+        } else {
+            lo[i - 1] = reinterpret_cast<float*>(b + f.cL);
+        }
+    }
+    int st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s, /*compact=*/true, &la);
+    if (st) return st;
+    // merge by rank
+    LeanMergeArgs ma{};
+    ma.nlev = g.nlev;
+    ma.W = g.W;
+    ma.H = g.H;
+    ma.C = C;
+    ma.out = d->out;
+    ma.fine1 = true;
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        LeanMergeLevel& L = ma.lv[j];
+        L.sh = i - 1;
+        L.s = 1 << L.sh;
+        L.W = g.Wi[i - 1];
+        L.H = g.Hi[i - 1];
+        L.w = d->mp.weight[i - 1];
+        L.c = lo[i - 1];
+        L.c_plane = g.n(i);
+        if (i < g.L) {
+            L.Sb = la.lv[j].Sb;
+            L.woff = la.lv[j].woff;
+            L.ac = la.lv[j].ac;
+            L.wpr = la.lv[j].wpr;
+        }
+        if (L.s >= 2) {
+            L.rw = (kMergeTW + L.s - 1) / L.s + 2;
+            L.rh = (kMergeTH + L.s - 1) / L.s + 2;
+            L.roff = ma.staged;
+            L.rmagic = (65536u + (unsigned)L.rw - 1) / (unsigned)L.rw;
+            ma.staged += L.rw * L.rh;
+        }
+    }
+    if (launch_lean_merge(ma, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
+    return MR_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -543,7 +777,8 @@ size_t mr_workspace_bytes(const mr_camera* cam, const mr_mask_params* mp, int pu
         fail(MR_E_PARAM, "unknown workspace purpose %d", purpose);
         return 0;
     }
-    return frame_layout(g, purpose).bytes;
+    const size_t dense = frame_layout(g, purpose).bytes, lean = lean_layout(g, purpose).bytes;
+    return dense > lean ? dense : lean;
 }
 
 int mr_build_masks(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp, const uint8_t* hard,
@@ -672,8 +907,11 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if (st) return st;
     if (d->level_map && misaligned(d->level_map)) return fail(MR_E_PARAM, "level_map is not 16-byte aligned");
     const FrameLayout f = frame_layout(g, effect);
-    if (!ws || ws_bytes < f.bytes) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, f.bytes);
+    const size_t lean_bytes = lean_layout(g, effect).bytes;
+    const size_t need = f.bytes > lean_bytes ? f.bytes : lean_bytes;
+    if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
+    if (lean_ok(g, &d->mp)) return do_frame_lean(d, g, params, static_cast<uint8_t*>(ws), s);
     uint8_t* b = static_cast<uint8_t*>(ws);
     mr_masks m{};
     m.edge = b + f.edge;

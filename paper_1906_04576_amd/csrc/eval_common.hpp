@@ -56,6 +56,62 @@ __device__ __forceinline__ unsigned item_local(const ItemMap& m, unsigned item, 
 // instead of a vector load (and its full wait) per sample.
 constexpr int kLdsSamples = 1024;
 
+// a_i at every listed texel: the separable blur of the dense path with the
+// zero terms left out (g * 0 = +0 and acc + 0 = acc, so the sums are equal).
+// The radius is a template parameter so that all 2R+1 rows' words are loaded
+// in one batch.
+template <int R>
+__device__ __forceinline__ float alpha_at(const uint32_t* Eb, int wpr, int H, const float* g, int x, int y) {
+    constexpr int N = 2 * R + 1;
+    const int x0 = x - R;
+    const int w0 = x0 >> 5, sh = x0 & 31;
+    const bool lo_ok = w0 >= 0 && w0 < wpr, hi_ok = w0 + 1 >= 0 && w0 + 1 < wpr;
+    unsigned lo[N], hi[N];
+#pragma unroll
+    for (int ky = 0; ky < N; ++ky) {
+        const int yy = y - R + ky;
+        const bool rok = yy >= 0 && yy < H;
+        const uint32_t* row = Eb + (unsigned)(rok ? yy : 0) * (unsigned)wpr;
+        lo[ky] = (rok && lo_ok) ? row[w0] : 0u;
+        hi[ky] = (rok && hi_ok) ? row[w0 + 1] : 0u;
+    }
+    float a = 0.0f;
+#pragma unroll
+    for (int ky = 0; ky < N; ++ky) {
+        unsigned m = sh ? (lo[ky] >> sh) | (hi[ky] << (32 - sh)) : lo[ky];
+        m &= (1u << N) - 1u;
+        if (!m) continue;
+        float h = 0.0f;
+        while (m) {
+            const int k = __builtin_ctz(m);
+            m &= m - 1;
+            h = h + g[k];
+        }
+        a = a + g[ky] * h;
+    }
+    return a;
+}
+
+// blur taps of every level in LDS (the caller synchronises before use)
+constexpr int kEgStride = 2 * kBlurFusedMaxRadiusC + 1;
+__device__ __forceinline__ void stage_taps(const EvalCommon& c, float* eg) {
+    for (int i = threadIdx.x; i < kMaxLevels * kEgStride; i += blockDim.x) {
+        const int j = i / kEgStride, k = i - j * kEgStride;
+        eg[i] = c.lv[j].Eg[k];
+    }
+}
+
+// a_i of a listed texel for the evaluators (radius <= 8, else 0)
+__device__ __forceinline__ float alpha_dispatch(const EvalLevel& L, const float* g, int x, int y) {
+    switch (L.Er) {
+#define MR_ALPHA(R) \
+    case R: return alpha_at<R>(L.Eb, L.Ewpr, L.H, g, x, y);
+        MR_ALPHA(0) MR_ALPHA(1) MR_ALPHA(2) MR_ALPHA(3) MR_ALPHA(4) MR_ALPHA(5) MR_ALPHA(6) MR_ALPHA(7) MR_ALPHA(8)
+#undef MR_ALPHA
+        default: return 0.0f;
+    }
+}
+
 // P = (X z, Y z, -z), X = ((x + 0.5) - cx) / f, Y = (cy - (y + 0.5)) / f
 __device__ __forceinline__ void view_pos(int x, int y, float z, float f, float cx, float cy,
                                          float& px, float& py, float& pz) {
@@ -78,6 +134,14 @@ __device__ __forceinline__ void onb(float nx, float ny, float nz, float& tx, flo
     bx = b;
     by = sg + ((ny * ny) * a);
     bz = -ny;
+}
+
+// whether any level has the evaluator write a_i (selects the kernel instance
+// that carries the blur code, so that the others keep their register budget)
+__host__ inline bool fused_alpha(const EvalCommon& c) {
+    for (int j = 0; j < c.nlev; ++j)
+        if (c.lv[j].ac) return true;
+    return false;
 }
 
 // grid for a grid-stride evaluation pass over `total_hint` items at most

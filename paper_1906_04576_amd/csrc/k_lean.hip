@@ -1,0 +1,430 @@
+// Lean frame path: the mask pyramid kept as bits and compact arrays.
+//
+// The blurred mask a_i (Sec. 3.1, Table 1) is positive exactly on the
+// Chebyshev dilation of the pooled edges by the blur radius when every
+// Gaussian tap is positive and no product of two taps underflows (the host
+// checks both), and the nesting step of the inclusive decomposition is then a
+// no-op (the host checks the radius condition).  So the stencil of Sec. 4.1
+// is computed here as an integer dilation of bit-packed edges, its texels are
+// ranked (per-word prefix counts), and a_i and the sub-image values are
+// stored only at the stencil texels, indexed by rank.  The merge (Sec. 4.2,
+// Eq. 1) finds a texel's value through its rank.  All floating-point results
+// are the same operations, in the same order, as the dense path.
+#include "eval_common.hpp"
+
+namespace mr {
+
+// horizontal dilation by r (< 32) of word c with neighbours p (left), n (right);
+// bit x % 32 of word x / 32 holds texel x
+__device__ __forceinline__ unsigned hdilate(unsigned p, unsigned c, unsigned n, int r) {
+    unsigned d = c;
+    for (int s = 1; s <= r; ++s) d |= (c << s) | (p >> (32 - s)) | (c >> s) | (n << (32 - s));
+    return d;
+}
+
+__device__ __forceinline__ int lean_level(const LeanArgs& A, unsigned b) {
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < 3; ++k) l += (k < A.nlev && b >= A.lv[k].blk_base) ? 1 : 0;
+    return l;
+}
+
+// S words (dilated edge bits) and per-256-word popcount sums; the radius is
+// a template parameter so that all rows' words are loaded in one batch
+template <int R>
+__device__ __forceinline__ unsigned stencil_word(const LeanLevel& L, int y, int xw) {
+    unsigned c[2 * R + 1], p[2 * R + 1], n[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) {
+        const int yy = y - R + k;
+        const bool ok = yy >= 0 && yy < L.H;
+        const uint32_t* row = L.Eb + (unsigned)(ok ? yy : 0) * (unsigned)L.wpr;
+        c[k] = ok ? row[xw] : 0u;
+        p[k] = (ok && xw > 0) ? row[xw - 1] : 0u;
+        n[k] = (ok && xw + 1 < L.wpr) ? row[xw + 1] : 0u;
+    }
+    unsigned acc = 0;
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) acc |= hdilate(p[k], c[k], n[k], R);
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void k_lean_stencil(LeanArgs A) {
+    __shared__ unsigned wsum[4];
+    const unsigned b = blockIdx.x;
+    const int l = lean_level(A, b);
+    const LeanLevel& L = A.lv[l];
+    const unsigned w = (b - L.blk_base) * 256 + threadIdx.x;
+    unsigned cnt = 0;
+    if (w < L.nwords) {
+        const int y = (int)(w / (unsigned)L.wpr), xw = (int)(w - (unsigned)y * (unsigned)L.wpr);
+        unsigned acc = 0;
+        switch (L.r) {
+#define MR_STENCIL(R) \
+    case R: acc = stencil_word<R>(L, y, xw); break;
+            MR_STENCIL(0) MR_STENCIL(1) MR_STENCIL(2) MR_STENCIL(3) MR_STENCIL(4) MR_STENCIL(5) MR_STENCIL(6)
+            MR_STENCIL(7) MR_STENCIL(8)
+#undef MR_STENCIL
+            default: break;
+        }
+        L.Sb[w] = acc;
+        cnt = __popc(acc);
+    }
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    if (__lane_id() == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) A.blk_sum[b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// exclusive scan of the block sums per level; level totals into count[]
+__global__ __launch_bounds__(1024) void k_lean_scan(LeanArgs A) {
+    __shared__ unsigned wtot[16];
+    const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
+    if (t < kMaxLevels) A.count[t] = 0;
+    __syncthreads();
+    for (int l = 0; l < A.nlev; ++l) {
+        const unsigned b0 = A.lv[l].blk_base;
+        const unsigned b1 = l + 1 < A.nlev ? A.lv[l + 1].blk_base : A.nblk;
+        unsigned carry = 0;
+        for (unsigned base = b0; base < b1; base += 1024) {
+            const unsigned c = base + t;
+            const unsigned v = c < b1 ? A.blk_sum[c] : 0u;
+            const unsigned inc = wave_scan_incl(v);
+            if (lane == 63) wtot[wv] = inc;
+            __syncthreads();
+            unsigned before = 0, all = 0;
+            for (int w = 0; w < 16; ++w) {
+                if (w < wv) before += wtot[w];
+                all += wtot[w];
+            }
+            if (c < b1) A.blk_off[c] = carry + before + inc - v;
+            carry += all;
+            __syncthreads();
+        }
+        if (t == 0) A.count[A.lv[l].count_idx] = carry;
+    }
+}
+
+// per-word ranks and the row-major lists of stencil texels
+__global__ __launch_bounds__(256) void k_lean_scatter(LeanArgs A) {
+    __shared__ unsigned wtot[4];
+    const unsigned b = blockIdx.x;
+    const int l = lean_level(A, b);
+    const LeanLevel& L = A.lv[l];
+    const unsigned w = (b - L.blk_base) * 256 + threadIdx.x;
+    const unsigned s = w < L.nwords ? L.Sb[w] : 0u;
+    const unsigned cnt = __popc(s);
+    const unsigned inc = wave_scan_incl(cnt);
+    const int wv = threadIdx.x >> 6;
+    if (__lane_id() == 63) wtot[wv] = inc;
+    __syncthreads();
+    unsigned before = 0;
+    for (int k = 0; k < wv; ++k) before += wtot[k];
+    if (w >= L.nwords) return;
+    unsigned pos = A.blk_off[b] + before + inc - cnt;
+    L.woff[w] = pos;
+    if (!s) return;
+    const int y = (int)(w / (unsigned)L.wpr), xw = (int)(w - (unsigned)y * (unsigned)L.wpr);
+    const unsigned base = (unsigned)y * (unsigned)L.W + (unsigned)xw * 32u;
+    unsigned m = s;
+    while (m) {
+        const int bit = __builtin_ctz(m);
+        m &= m - 1;
+        L.list[pos++] = base + (unsigned)bit;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lean_alpha(LeanArgs A) {
+    unsigned cum[4];
+    cum[0] = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        unsigned n = 0;
+        if (l < A.nlev) n = min(A.count[A.lv[l].count_idx], A.lv[l].nwords * 32u);
+        cum[l + 1] = cum[l] + n;
+    }
+    const unsigned total = cum[3];
+    for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+        const int l = (item >= cum[1] ? 1 : 0) + (item >= cum[2] ? 1 : 0);
+        const LeanLevel& L = A.lv[l];
+        const unsigned local = item - (l == 0 ? 0u : (l == 1 ? cum[1] : cum[2]));
+        const unsigned t = L.list[local];
+        const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
+        float a = 0.0f;
+        switch (L.r) {
+#define MR_ALPHA(R) \
+    case R: a = alpha_at<R>(L.Eb, L.wpr, L.H, L.g, x, y); break;
+            MR_ALPHA(0) MR_ALPHA(1) MR_ALPHA(2) MR_ALPHA(3) MR_ALPHA(4) MR_ALPHA(5) MR_ALPHA(6) MR_ALPHA(7)
+            MR_ALPHA(8)
+#undef MR_ALPHA
+            default: break;
+        }
+        L.ac[local] = a;
+    }
+}
+
+// alpha_blocks = 0: a_i is computed by the evaluation kernel instead
+hipError_t launch_lean_masks(const LeanArgs& a, unsigned alpha_blocks, hipStream_t s) {
+    if (a.nblk) hipLaunchKernelGGL(k_lean_stencil, dim3(a.nblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lean_scan, dim3(1), dim3(1024), 0, s, a);
+    if (a.nblk) {
+        hipLaunchKernelGGL(k_lean_scatter, dim3(a.nblk), dim3(256), 0, s, a);
+        if (alpha_blocks) hipLaunchKernelGGL(k_lean_alpha, dim3(alpha_blocks), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// owner-level map from the stencil bits
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lean_level_map(LeanMapArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.W || y >= a.H) return;
+    uint8_t lvl = (uint8_t)a.coarsest;
+    for (int j = a.nlev - 1; j >= 0; --j) {
+        const int sh = a.level[j] - 1;
+        const int X = x >> sh, Y = y >> sh;
+        if ((a.Sb[j][(unsigned)Y * (unsigned)a.wpr[j] + (unsigned)(X >> 5)] >> (X & 31)) & 1u)
+            lvl = (uint8_t)a.level[j];
+    }
+    a.out[(unsigned)y * (unsigned)a.W + (unsigned)x] = lvl;
+}
+
+hipError_t launch_lean_level_map(const LeanMapArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_lean_level_map, dim3((a.W + 63) / 64, (a.H + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// merge with rank lookups (same arithmetic as the dense merge)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void axis_taps_l(int X, int sh, int n, int lo, int& ia, int& ib, float& f) {
+    const int s = 1 << sh;
+    const int m = X - (s >> 1);
+    const int x0 = m >> sh;
+    f = ((float)(m & (s - 1)) + 0.5f) * (1.0f / (float)s);
+    ia = min(max(x0, 0), n - 1) - lo;
+    ib = min(max(x0 + 1, 0), n - 1) - lo;
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
+    __shared__ float la[kMergeLDS];
+    __shared__ uint8_t ls[kMergeLDS];
+    __shared__ float lc[C][kMergeLDS];
+    __shared__ int lvl_any[kMaxLevels];  // some staged a > 0 in the level's region
+    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
+    const int x0 = (int)(tile % tiles_x) * kMergeTW;
+    const int y0 = (int)(tile / tiles_x) * kMergeTH;
+    const int nl = a.nlev, t = threadIdx.x;
+    if (t < kMaxLevels) lvl_any[t] = 0;
+    __syncthreads();
+    // ---- stage the coarse levels' tap regions (all loads issued first) ----
+    constexpr int kSlots = (kMergeLDS + 255) / 256;
+    uint8_t sv[kSlots];
+    float av[kSlots], cv[kSlots][C];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int idx = t + 256 * j;
+        sv[j] = 0;
+        av[j] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) cv[j][c] = 0.0f;
+        if (idx >= a.staged) continue;
+        int q = 0;
+#pragma unroll
+        for (int k = 1; k < kMaxLevels; ++k) q += (k < nl && idx >= a.lv[k].roff) ? 1 : 0;
+        const LeanMergeLevel& L = a.lv[q];
+        const int k = idx - L.roff;
+        const int yy = (int)(((unsigned)k * L.rmagic) >> 16), xx = k - yy * L.rw;
+        const int Xl = min(max((x0 >> L.sh) - 1 + xx, 0), L.W - 1);
+        const int Yl = min(max((y0 >> L.sh) - 1 + yy, 0), L.H - 1);
+        if (q == nl - 1) {
+            sv[j] = 1;
+            const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
+#pragma unroll
+            for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + p];
+        } else {
+            const unsigned wi = (unsigned)Yl * (unsigned)L.wpr + (unsigned)(Xl >> 5);
+            const unsigned word = L.Sb[wi];
+            const unsigned bit = (unsigned)Xl & 31u;
+            if ((word >> bit) & 1u) {
+                const unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
+                sv[j] = 1;
+                av[j] = L.ac[rank];
+#pragma unroll
+                for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + rank];
+            }
+        }
+    }
+    const int q = t & 15, row = t >> 4;
+    const int Y = y0 + row;
+    const int XQ = x0 + 4 * q;
+    const bool active = Y < a.H && XQ < a.W;
+    // ---- level 1: four pixels per thread, values by rank ----
+    uint8_t s1[4] = {0, 0, 0, 0};
+    float a1[4] = {0, 0, 0, 0}, c1[C][4];
+#pragma unroll
+    for (int c = 0; c < C; ++c) c1[c][0] = c1[c][1] = c1[c][2] = c1[c][3] = 0.0f;
+    const bool fine1 = a.fine1;
+    if (fine1 && active) {
+        const LeanMergeLevel& L = a.lv[0];
+        const unsigned wi = (unsigned)Y * (unsigned)L.wpr + (unsigned)(XQ >> 5);
+        const unsigned word = L.Sb[wi];
+        const unsigned bit = (unsigned)XQ & 31u;
+        const unsigned nib = (word >> bit) & 0xFu;
+        if (nib) {
+            unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((nib >> k) & 1u) {
+                    s1[k] = 1;
+                    a1[k] = L.ac[rank];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) c1[c][k] = L.c[c * L.c_plane + rank];
+                    ++rank;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int idx = t + 256 * j;
+        if (idx >= a.staged) continue;
+        ls[idx] = sv[j];
+        la[idx] = av[j];
+#pragma unroll
+        for (int c = 0; c < C; ++c) lc[c][idx] = cv[j][c];
+        if (av[j] != 0.0f) {
+            int q = 0;
+#pragma unroll
+            for (int k = 1; k < kMaxLevels; ++k) q += (k < nl && idx >= a.lv[k].roff) ? 1 : 0;
+            lvl_any[q] = 1;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    float out[C][4];
+    {
+        // coarsest level: plain bilinear, normalising sum exactly 1
+        const LeanMergeLevel& L = a.lv[nl - 1];
+        int ya, yb;
+        float fy;
+        axis_taps_l(Y, L.sh, L.H, (y0 >> L.sh) - 1, ya, yb, fy);
+        const float gy = 1.0f - fy;
+        const int r0 = L.roff + ya * L.rw, r1 = L.roff + yb * L.rw;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int xa, xb;
+            float fx;
+            axis_taps_l(XQ + k, L.sh, L.W, (x0 >> L.sh) - 1, xa, xb, fx);
+            const float gx = 1.0f - fx;
+            const float b0 = gx * gy, b1 = fx * gy, b2 = gx * fy, b3 = fx * fy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float num = b0 * lc[c][r0 + xa];
+                num = num + b1 * lc[c][r0 + xb];
+                num = num + b2 * lc[c][r1 + xa];
+                num = num + b3 * lc[c][r1 + xb];
+                out[c][k] = num;
+            }
+        }
+    }
+    for (int j = nl - 2; j >= 0; --j) {
+        const LeanMergeLevel& L = a.lv[j];
+        if (j == 0 && fine1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool in = s1[k] != 0;
+                const float alpha = in ? fminf(a1[k] * L.w, 1.0f) : 0.0f;
+                const float om = 1.0f - alpha;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float Ci = in ? c1[c][k] : 0.0f;
+                    out[c][k] = Ci * alpha + out[c][k] * om;
+                }
+            }
+            continue;
+        }
+        // every staged a of this level is 0: A = 0 at all pixels, alpha = 0
+        if (!lvl_any[j]) continue;
+        int ya, yb;
+        float fy;
+        axis_taps_l(Y, L.sh, L.H, (y0 >> L.sh) - 1, ya, yb, fy);
+        const float gy = 1.0f - fy;
+        const int r0 = L.roff + ya * L.rw, r1 = L.roff + yb * L.rw;
+        float A[4], b[4][4];
+        int ix[4][2];
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int xa, xb;
+            float fx;
+            axis_taps_l(XQ + k, L.sh, L.W, (x0 >> L.sh) - 1, xa, xb, fx);
+            const float gx = 1.0f - fx;
+            b[k][0] = gx * gy;
+            b[k][1] = fx * gy;
+            b[k][2] = gx * fy;
+            b[k][3] = fx * fy;
+            ix[k][0] = xa;
+            ix[k][1] = xb;
+            float s_ = b[k][0] * la[r0 + xa];
+            s_ = s_ + b[k][1] * la[r0 + xb];
+            s_ = s_ + b[k][2] * la[r1 + xa];
+            s_ = s_ + b[k][3] * la[r1 + xb];
+            A[k] = s_;
+            nz |= s_ != 0.0f;
+        }
+        if (!nz) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i00 = r0 + ix[k][0], i01 = r0 + ix[k][1], i10 = r1 + ix[k][0], i11 = r1 + ix[k][1];
+            const bool e0 = ls[i00] != 0, e1 = ls[i01] != 0, e2 = ls[i10] != 0, e3 = ls[i11] != 0;
+            float den = e0 ? b[k][0] : 0.0f;
+            den = den + (e1 ? b[k][1] : 0.0f);
+            den = den + (e2 ? b[k][2] : 0.0f);
+            den = den + (e3 ? b[k][3] : 0.0f);
+            const bool use = A[k] != 0.0f && den > 0.0f;
+            const float alpha = use ? fminf(A[k] * L.w, 1.0f) : 0.0f;
+            const float om = 1.0f - alpha;
+            const float dd = use ? den : 1.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float num = e0 ? b[k][0] * lc[c][i00] : 0.0f;
+                num = num + (e1 ? b[k][1] * lc[c][i01] : 0.0f);
+                num = num + (e2 ? b[k][2] * lc[c][i10] : 0.0f);
+                num = num + (e3 ? b[k][3] * lc[c][i11] : 0.0f);
+                const float Ci = use ? (dd == 1.0f ? num : num / dd) : 0.0f;
+                out[c][k] = Ci * alpha + out[c][k] * om;
+            }
+        }
+    }
+    const unsigned p = (unsigned)Y * (unsigned)a.W + (unsigned)XQ;
+    const unsigned plane = (unsigned)a.W * (unsigned)a.H;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
+}
+
+hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s) {
+    const unsigned tx = (a.W + kMergeTW - 1) / kMergeTW, ty = (a.H + kMergeTH - 1) / kMergeTH;
+    if (a.C == 3)
+        hipLaunchKernelGGL(k_lean_merge<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    else
+        hipLaunchKernelGGL(k_lean_merge<1>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    return hipGetLastError();
+}
+
+}  // namespace mr

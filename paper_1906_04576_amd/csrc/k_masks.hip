@@ -281,7 +281,7 @@ struct NormalRow<_Float16> {
     }
 };
 
-template <typename NT, bool HARD>
+template <typename NT, bool HARD, bool BITS>
 __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
     __shared__ uint8_t p4[4][8];
     const unsigned tile = xcd_remap(blockIdx.x, ntiles);
@@ -387,7 +387,30 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
             e[r][c] = (any & (y < H) & valid_depth(zc) & ed) ? 1 : 0;
         }
     }
-    if (any) {
+    if (BITS) {
+        // bit-packed level 1: a tile row of 64 pixels is 2 words; the 8 lanes
+        // of a word OR their shifted nibbles together (shuffles run on all lanes)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            unsigned v1 = (unsigned)(e[r][0] | (e[r][1] << 1) | (e[r][2] << 2) | (e[r][3] << 3)) << (4 * (cg & 7));
+            v1 |= __shfl_xor(v1, 1, 64);
+            v1 |= __shfl_xor(v1, 2, 64);
+            v1 |= __shfl_xor(v1, 4, 64);
+            if (any && (cg & 7) == 0 && yb + r < H)
+                a.Eb[0][(unsigned)(yb + r) * (unsigned)a.wpr[0] + (unsigned)((xb >> 5))] = v1;
+        }
+        // level 2: 32 texels per tile row = one word
+        unsigned v2 = ((unsigned)(e[0][0] | e[0][1] | e[1][0] | e[1][1]) |
+                       ((unsigned)(e[0][2] | e[0][3] | e[1][2] | e[1][3]) << 1))
+                      << (2 * cg);
+        v2 |= __shfl_xor(v2, 1, 64);
+        v2 |= __shfl_xor(v2, 2, 64);
+        v2 |= __shfl_xor(v2, 4, 64);
+        v2 |= __shfl_xor(v2, 8, 64);
+        if (any && cg == 0 && a.Eb[1])
+            a.Eb[1][(unsigned)(yb >> 1) * (unsigned)a.wpr[1] + (unsigned)(x0 >> 6)] = v2;
+    }
+    if (any && !BITS) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int y = yb + r;
@@ -395,6 +418,8 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
                 *reinterpret_cast<uchar4*>(a.E + (unsigned)y * (unsigned)W + (unsigned)xb) =
                     make_uchar4(e[r][0], e[r][1], e[r][2], e[r][3]);
         }
+    }
+    if (any) {
         // point-sampled level depth: z_i(X, Y) = z(s X + s/2, s Y + s/2).  For
         // s = 2 that is columns xb+1, xb+3 of row yb+1; for s >= 4 at most one
         // pixel of the block qualifies: column 2 (s = 4) or 0 (s >= 8) of row yb.
@@ -412,7 +437,7 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
                 zi[(unsigned)(yb >> sh) * (unsigned)a.Wi[i - 1] + (unsigned)((xb + cs) >> sh)] =
                     s == 4 ? z[1][2] : z[1][0];
         }
-        if (a.Ei[1]) {
+        if (!BITS && a.Ei[1]) {
             uint8_t* e2 = a.Ei[1] + (unsigned)(yb >> 1) * (unsigned)a.Wi[1] + (unsigned)(xb >> 1);
             e2[0] = e[0][0] | e[0][1] | e[1][0] | e[1][1];
             e2[1] = e[0][2] | e[0][3] | e[1][2] | e[1][3];
@@ -420,8 +445,19 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
     }
     int v = e[0][0] | e[0][1] | e[0][2] | e[0][3] | e[1][0] | e[1][1] | e[1][2] | e[1][3];
     v |= __shfl_xor(v, 16, 64);
-    if (any && a.Ei[2] && (rp & 1) == 0)
+    if (BITS) {
+        // level 3: 16 texels per tile row = half a word (ushort store)
+        unsigned v3 = (unsigned)v << cg;
+        v3 |= __shfl_xor(v3, 1, 64);
+        v3 |= __shfl_xor(v3, 2, 64);
+        v3 |= __shfl_xor(v3, 4, 64);
+        v3 |= __shfl_xor(v3, 8, 64);
+        if (any && cg == 0 && (rp & 1) == 0 && a.Eb[2])
+            reinterpret_cast<uint16_t*>(a.Eb[2])[(unsigned)(yb >> 2) * (unsigned)(2 * a.wpr[2]) +
+                                                 (unsigned)(x0 >> 6)] = (uint16_t)v3;
+    } else if (any && a.Ei[2] && (rp & 1) == 0) {
         a.Ei[2][(unsigned)(yb >> 2) * (unsigned)a.Wi[2] + (unsigned)(xb >> 2)] = (uint8_t)v;
+    }
     v |= __shfl_xor(v, 1, 64);
     v |= __shfl_xor(v, 32, 64);
     if (any && a.Ei[3] && (cg & 1) == 0 && rp == 0)
@@ -449,16 +485,21 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
 hipError_t launch_edges(const EdgeArgs& a, int normal_dtype, hipStream_t s) {
     const unsigned tx = (a.W + kEdgeTW - 1) / kEdgeTW, ty = (a.H + kEdgeTH - 1) / kEdgeTH;
     const unsigned n = tx * ty;
-    const bool f16 = normal_dtype == MR_F16, hard = a.hard != nullptr;
+    const bool f16 = normal_dtype == MR_F16, hard = a.hard != nullptr, bits = a.Eb[0] != nullptr;
     if ((a.W & 3) == 0 && a.W >= 4) {
-        if (f16 && hard)
-            hipLaunchKernelGGL((k_edges_vec<_Float16, true>), dim3(n), dim3(256), 0, s, a, tx, n);
-        else if (f16)
-            hipLaunchKernelGGL((k_edges_vec<_Float16, false>), dim3(n), dim3(256), 0, s, a, tx, n);
-        else if (hard)
-            hipLaunchKernelGGL((k_edges_vec<float, true>), dim3(n), dim3(256), 0, s, a, tx, n);
-        else
-            hipLaunchKernelGGL((k_edges_vec<float, false>), dim3(n), dim3(256), 0, s, a, tx, n);
+#define MR_EDGES(NT, HD, BT) hipLaunchKernelGGL((k_edges_vec<NT, HD, BT>), dim3(n), dim3(256), 0, s, a, tx, n)
+        if (bits) {
+            if (f16 && hard) MR_EDGES(_Float16, true, true);
+            else if (f16) MR_EDGES(_Float16, false, true);
+            else if (hard) MR_EDGES(float, true, true);
+            else MR_EDGES(float, false, true);
+        } else {
+            if (f16 && hard) MR_EDGES(_Float16, true, false);
+            else if (f16) MR_EDGES(_Float16, false, false);
+            else if (hard) MR_EDGES(float, true, false);
+            else MR_EDGES(float, false, false);
+        }
+#undef MR_EDGES
     } else if (f16) {
         hipLaunchKernelGGL(k_edges_generic<_Float16>, dim3(n), dim3(256), 0, s, a, tx, n);
     } else {

@@ -97,8 +97,8 @@ __device__ __forceinline__ float pcss_texel(const ShadowArgs& a, const EvalLevel
     return (float)lit / (float)a.np;
 }
 
-template <bool LDS>
-__device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds, const float* pds) {
+template <bool LDS, bool AL>
+__device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds, const float* pds, const float* eg) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
     for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
@@ -108,6 +108,7 @@ __device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
+        if (AL && L.ac) L.ac[local] = alpha_dispatch(L, eg + j * kEgStride, x, y);
         const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float vis = 1.0f;
         if (valid_depth(z)) {
@@ -116,25 +117,32 @@ __device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds
             else
                 vis = pcss_texel(a, L, a.bd, a.pd, x, y, z);
         }
-        L.out[(unsigned)y * (unsigned)L.W + (unsigned)x] = vis;
+        L.out[L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x] = vis;
     }
 }
 
+template <bool AL>
 __global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
     __shared__ float bds[2 * kLdsSamples], pds[2 * kLdsSamples];
+    __shared__ float eg[kMaxLevels * kEgStride];
+    if (AL) stage_taps(a.c, eg);
     const bool staged = a.nb <= kLdsSamples && a.np <= kLdsSamples;  // uniform
     if (staged) {
         for (int i = threadIdx.x; i < 2 * a.nb; i += 256) bds[i] = a.bd[i];
         for (int i = threadIdx.x; i < 2 * a.np; i += 256) pds[i] = a.pd[i];
         __syncthreads();
-        pcss_items<true>(a, bds, pds);
+        pcss_items<true, AL>(a, bds, pds, eg);
     } else {
-        pcss_items<false>(a, bds, pds);
+        __syncthreads();
+        pcss_items<false, AL>(a, bds, pds, eg);
     }
 }
 
 hipError_t launch_shadow(const ShadowArgs& a, unsigned total_hint, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcss, dim3(eval_blocks(total_hint)), dim3(256), 0, s, a);
+    if (fused_alpha(a.c))
+        hipLaunchKernelGGL(k_pcss<true>, dim3(eval_blocks(total_hint)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_pcss<false>, dim3(eval_blocks(total_hint)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

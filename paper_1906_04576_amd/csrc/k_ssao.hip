@@ -48,8 +48,8 @@ __device__ __forceinline__ float ssao_texel(const SsaoArgs& a, const EvalLevel& 
     return (float)occ / (float)S;
 }
 
-template <typename NT, bool KLDS>
-__device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks) {
+template <typename NT, bool KLDS, bool AL>
+__device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, const float* eg) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
     const NT* nrm = static_cast<const NT*>(a.c.normal);
@@ -61,6 +61,7 @@ __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks) {
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
+        if (AL && L.ac) L.ac[local] = alpha_dispatch(L, eg + j * kEgStride, x, y);
         const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float res = 0.0f;
         if (valid_depth(z)) {
@@ -69,28 +70,39 @@ __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks) {
             else
                 res = ssao_texel<NT>(a, L, nrm, plane, a.kernel, x, y, z);
         }
-        L.out[(unsigned)y * (unsigned)L.W + (unsigned)x] = res;
+        L.out[L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x] = res;
     }
 }
 
-template <typename NT>
+template <typename NT, bool AL>
 __global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
     __shared__ float ks[3 * kLdsSamples];
+    __shared__ float eg[kMaxLevels * kEgStride];
+    if (AL) stage_taps(a.c, eg);
     if (a.S <= kLdsSamples) {
         for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
         __syncthreads();
-        ssao_items<NT, true>(a, ks);
+        ssao_items<NT, true, AL>(a, ks, eg);
     } else {
-        ssao_items<NT, false>(a, ks);
+        __syncthreads();
+        ssao_items<NT, false, AL>(a, ks, eg);
     }
 }
 
 hipError_t launch_ssao(const SsaoArgs& a, int normal_dtype, unsigned total_hint, hipStream_t s) {
     const unsigned nb = eval_blocks(total_hint);
-    if (normal_dtype == MR_F16)
-        hipLaunchKernelGGL(k_ssao<_Float16>, dim3(nb), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_ssao<float>, dim3(nb), dim3(256), 0, s, a);
+    const bool al = fused_alpha(a.c);
+    if (normal_dtype == MR_F16) {
+        if (al)
+            hipLaunchKernelGGL((k_ssao<_Float16, true>), dim3(nb), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_ssao<_Float16, false>), dim3(nb), dim3(256), 0, s, a);
+    } else {
+        if (al)
+            hipLaunchKernelGGL((k_ssao<float, true>), dim3(nb), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_ssao<float, false>), dim3(nb), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

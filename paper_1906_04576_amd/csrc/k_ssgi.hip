@@ -9,8 +9,8 @@
 
 namespace mr {
 
-template <typename NT, typename CT, typename KP>
-__device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K) {
+template <typename NT, typename CT, bool AL, typename KP>
+__device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float* eg) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
     const NT* nrm = static_cast<const NT*>(a.c.normal);
@@ -28,6 +28,7 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K) {
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
+        if (AL && L.ac) L.ac[local] = alpha_dispatch(L, eg + j * kEgStride, x, y);
         const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
         float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
         if (valid_depth(z)) {
@@ -74,36 +75,48 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K) {
                 acc2 = acc2 + ld(col, 2 * plane + gt) * w;
             }
         }
-        const long long o = (long long)y * L.W + x;
+        const long long o = L.compact ? (long long)local : (long long)y * L.W + x;
         L.out[o] = acc0 * scale;
         L.out[L.out_plane + o] = acc1 * scale;
         L.out[2 * L.out_plane + o] = acc2 * scale;
     }
 }
 
-template <typename NT, typename CT>
+template <typename NT, typename CT, bool AL>
 __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
     __shared__ float ks[3 * kLdsSamples];
+    __shared__ float eg[kMaxLevels * kEgStride];
+    if (AL) stage_taps(a.c, eg);
     if (a.S <= kLdsSamples) {  // uniform
         for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
         __syncthreads();
-        ssgi_items<NT, CT>(a, (const float*)ks);
+        ssgi_items<NT, CT, AL>(a, (const float*)ks, (const float*)eg);
     } else {
-        ssgi_items<NT, CT>(a, a.kernel);
+        __syncthreads();
+        ssgi_items<NT, CT, AL>(a, a.kernel, (const float*)eg);
     }
 }
 
 hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
                        hipStream_t s) {
     const unsigned nb = eval_blocks(total_hint);
+    const bool al = fused_alpha(a.c);
+#define MR_SSGI(NT, CT)                                                                  \
+    do {                                                                                 \
+        if (al)                                                                          \
+            hipLaunchKernelGGL((k_ssgi<NT, CT, true>), dim3(nb), dim3(256), 0, s, a);  \
+        else                                                                             \
+            hipLaunchKernelGGL((k_ssgi<NT, CT, false>), dim3(nb), dim3(256), 0, s, a); \
+    } while (0)
     if (normal_dtype == MR_F16 && color_dtype == MR_F16)
-        hipLaunchKernelGGL((k_ssgi<_Float16, _Float16>), dim3(nb), dim3(256), 0, s, a);
+        MR_SSGI(_Float16, _Float16);
     else if (normal_dtype == MR_F16)
-        hipLaunchKernelGGL((k_ssgi<_Float16, float>), dim3(nb), dim3(256), 0, s, a);
+        MR_SSGI(_Float16, float);
     else if (color_dtype == MR_F16)
-        hipLaunchKernelGGL((k_ssgi<float, _Float16>), dim3(nb), dim3(256), 0, s, a);
+        MR_SSGI(float, _Float16);
     else
-        hipLaunchKernelGGL((k_ssgi<float, float>), dim3(nb), dim3(256), 0, s, a);
+        MR_SSGI(float, float);
+#undef MR_SSGI
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 namespace mr {
 
 constexpr int kMaxLevels = MR_MAX_LEVELS;
+constexpr int kBlurFusedMaxRadiusC = 8;  // largest radius of the single-launch blur and the lean path
 constexpr int kMaxRadius = MR_MAX_RADIUS;
 constexpr int kChunk = 4096;  // texels per compaction chunk (256 threads x 16)
 
@@ -63,6 +64,10 @@ struct EdgeArgs {
     float* zi[kMaxLevels];               // point-sampled level depth (null = not needed)
     int Wi[kMaxLevels], Hi[kMaxLevels];
     int num_levels;
+    // bit-packed edges (lean frame path): levels 1..3, 32 texels per word,
+    // bit x % 32 of word x / 32, rows of wpr words; null = not written
+    uint32_t* Eb[3];
+    int wpr[3];
 };
 
 struct BlurLevel {
@@ -122,6 +127,13 @@ struct EvalLevel {
     const uint32_t* list;  // null = dense
     int count_idx;         // list length = counts[count_idx]
     unsigned dense_n;
+    int compact;           // list levels: output at the list position instead of the texel
+    // lean frame path: also write a_i at the list position (ac != null),
+    // computed from the edge bits Eb (Ewpr words per row) with radius Er
+    float* ac;
+    const uint32_t* Eb;
+    int Ewpr, Er;
+    float Eg[2 * kBlurFusedMaxRadiusC + 1];
 };
 
 struct EvalCommon {
@@ -195,12 +207,67 @@ constexpr int kMergeTW = 64, kMergeTH = 16;
 constexpr int kMergeLDS = 640;  // >= sum of rw * rh over levels 2..6 (518)
 
 // ---------------------------------------------------------------------------
+// lean frame path (bit-packed stencils, values stored by rank)
+// ---------------------------------------------------------------------------
+struct LeanLevel {
+    const uint32_t* Eb;  // edge bits
+    uint32_t* Sb;        // stencil bits
+    uint32_t* woff;      // per word: number of stencil texels before it (its rank base)
+    uint32_t* list;      // stencil texels, row-major
+    float* ac;           // a_i by rank
+    int W, H, wpr, r;
+    unsigned nwords, blk_base;
+    int count_idx;
+    float g[2 * kMaxRadius + 1];
+};
+
+struct LeanArgs {
+    LeanLevel lv[3];  // enabled levels below the coarsest (levels 1..3)
+    int nlev;
+    unsigned nblk;    // 256-word blocks over all levels
+    uint32_t* blk_sum;
+    uint32_t* blk_off;
+    uint32_t* count;
+};
+
+struct LeanMapArgs {
+    const uint32_t* Sb[3];
+    int wpr[3];
+    int level[3];
+    int nlev;
+    int coarsest;
+    int W, H;
+    uint8_t* out;
+};
+
+struct LeanMergeLevel {
+    const float* c;      // by rank (levels below the coarsest) or dense (coarsest)
+    long long c_plane;
+    const uint32_t* Sb;  // null for the coarsest
+    const uint32_t* woff;
+    const float* ac;
+    int s, sh, W, H, wpr;
+    float w;
+    int rw, rh, roff;
+    unsigned rmagic;
+};
+
+struct LeanMergeArgs {
+    LeanMergeLevel lv[kMaxLevels];
+    int nlev;
+    int W, H, C;
+    int staged;
+    bool fine1;
+    float* out;
+};
+
+// ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 // ---------------------------------------------------------------------------
 hipError_t launch_edges(const EdgeArgs& a, int normal_dtype, hipStream_t s);
 hipError_t launch_blur(const BlurArgs& a, hipStream_t s);       // levels with radius <= 8
 hipError_t launch_blur_wide(const BlurLevel& a, hipStream_t s);  // one level, radius 9..16
-constexpr int kBlurFusedMaxRadius = 8;
+constexpr int kBlurFusedMaxRadius = kBlurFusedMaxRadiusC;
 hipError_t launch_nest(const NestArgs& a, hipStream_t s);
 hipError_t launch_level_map(const LevelMapArgs& a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
@@ -210,5 +277,8 @@ hipError_t launch_shadow(const ShadowArgs& a, unsigned total_hint, hipStream_t s
 hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
                        hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_lean_masks(const LeanArgs& a, unsigned alpha_blocks, hipStream_t s);
+hipError_t launch_lean_level_map(const LeanMapArgs& a, hipStream_t s);
+hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s);
 
 }  // namespace mr

@@ -40,7 +40,8 @@ def masks_params(effect, levels=4, enable=None):
     return m, o
 
 
-@pytest.mark.parametrize("W,H,sm", [(320, 184, 512), (960, 544, 2048)])
+# widths divisible by 128 take mr_frame's bit-packed path, the others the dense one
+@pytest.mark.parametrize("W,H,sm", [(320, 184, 512), (384, 256, 512), (960, 544, 2048)])
 def test_pcss_parity(W, H, sm):
     log(f"[gpu] pcss {W}x{H} map {sm}")
     s, gb = scene(W, H)
@@ -90,10 +91,10 @@ def test_pcss_parity(W, H, sm):
     assert ((rp > 0) & (rp < 1)).any(), "no penumbra in the test scene"
 
 
-@pytest.mark.parametrize("enable", [0b1101, 0b1111])
-def test_ssgi_parity(enable):
-    log(f"[gpu] ssgi levels {enable:04b}")
-    W, H = 320, 184
+@pytest.mark.parametrize("enable,W,H", [(0b1101, 320, 184), (0b1111, 320, 184), (0b1101, 384, 256),
+                                        (0b1111, 384, 256)])
+def test_ssgi_parity(enable, W, H):
+    log(f"[gpu] ssgi levels {enable:04b} {W}x{H}")
     s, gb = scene(W, H, seed=3, cam=4)
     col = scenegen.lambert_color(s, gb)
     K = scenegen.ssao_kernel(24, seed=77)

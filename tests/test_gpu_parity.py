@@ -142,7 +142,9 @@ def test_ssao_levels_and_merge(name):
     assert np.array_equal(o, oref), "merge not bit-exact"
 
 
-@pytest.mark.parametrize("name", ["256_3lv", "ragged_200x120", "1080p"])
+# 256_3lv, skip_level2 (width 320 -> dense), wide_radius (radius > 8 -> dense), 1080p:
+# mr_frame takes the bit-packed path where it is eligible and the dense one elsewhere
+@pytest.mark.parametrize("name", ["256_3lv", "ragged_200x120", "skip_level2", "wide_radius", "1080p"])
 def test_plain_and_frame(name):
     log(f"[gpu] plain + frame {name}")
     c = case(name)
