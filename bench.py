@@ -26,8 +26,17 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x GHz: non-packed FP32 lane-ops/s
-SSAO_OPS_PER_SAMPLE = 41        # algorithmic FP32 operations of one SSAO sample
+# algorithmic FP32 operations of one SSAO sample: the sample point (3 x 3
+# multiplies + 3 x 3 adds), the reciprocal of its depth, the projection (2 x
+# (2 multiplies + 1 add)), 4 bounds tests, 2 floor conversions, the validity
+# test, the biased depth (multiply + subtract) and its test, the range test
+# (subtract, test) and the count
+SSAO_OPS_PER_SAMPLE = 41
 SSAO_OPS_PER_TEXEL = 40         # per evaluated texel outside the sample loop
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
+# WRITE_SIZE counters (profiles/), scaled by the copy-kernel calibration;
+# None until measured for the current kernel
+TRAFFIC_BYTES = {"k_ssao_multi": 213443683}
 
 
 def log(*a):
@@ -47,6 +56,7 @@ def parse():
     ap.add_argument("--cameras", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true")
+    ap.add_argument("--no-quality", action="store_true", help="profile helper: skip the multi vs naive comparison")
     ap.add_argument("--plain", action="store_true", help="profile helper: time only the naive pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profile helper: first run a 256 MiB device-to-device copy (known HBM traffic)")
@@ -58,7 +68,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the multi-resolution path is one frame per GPU "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+              "and every frame fits one GPU; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -100,18 +110,26 @@ def main():
     nf = len(frames)
 
     def timed(runners, steps, warm):
+        """Throughput: `steps` frames back to back, bracketed by device
+        synchronisations and nothing else on the stream.  Latency: the same
+        frames again, each between two timing events (device-scope release);
+        each event adds a few microseconds of its own to the stream."""
         for k in range(warm):
             runners[k % nf]()
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t_start = time.perf_counter()
         for k in range(steps):
-            ev[k][0].record()
             runners[k % nf]()
-            ev[k][1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
-        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        ev = [(mr.DeviceEvent(), mr.DeviceEvent()) for _ in range(steps)]
+        stream = torch.cuda.current_stream()
+        for k in range(steps):
+            mr.record(ev[k][0], stream)
+            runners[k % nf]()
+            mr.record(ev[k][1], stream)
+        torch.cuda.synchronize()
+        lat = np.array([a.elapsed_ms(b) for a, b in ev])
         return wall, lat
 
     if args.plain:
@@ -129,92 +147,102 @@ def main():
     plain_mpx = npx * args.steps / wall_p / 1e6
 
     # ---------------- quality: multi-res vs naive on every configuration ----------------
-    mads, rmss, covs = [], [], []
-    lm = torch.empty((H, W), dtype=torch.uint8, device=dev)
-    for k in range(nf):
+    mads, rmss = [], []
+    for k in range(0 if args.no_quality else nf):
         a = multi[k]().clone()
         b = plain[k]()
         diff = (a - b).double()
         mads.append(float(diff.abs().mean()))
         rmss.append(float(diff.pow(2).mean().sqrt()))
 
-    # ---------------- per-stage timing through the separate entry points ----------------
+    # ---------------- per-stage GPU time of the same frames ----------------
+    # mr_frame records the caller's events (device-scope release) at its
+    # stage boundaries: [0] start, [1] masks and work lists done, [2]
+    # per-level evaluation done (one kernel launch), [3] merge done.  Each
+    # stage time is the event difference minus the stream time of one event.
+    # A long naive frame is queued first so that the stream runs ahead of
+    # the host and the events bracket back-to-back GPU work.
     stages = {}
     roofline = None
     if not args.no_stages:
-        masks = mr.alloc_masks(W, H, focal, mp, dev, level_map=False)
-        lo = {i: torch.empty((H >> (i - 1), W >> (i - 1)), dtype=torch.float32, device=dev) for i in (1, 2, 3, 4)}
-        lo_plain = {1: torch.empty((H, W), dtype=torch.float32, device=dev)}
-        out = torch.empty((H, W), dtype=torch.float32, device=dev)
-        reps = min(nf, 24)
-        names = ["build_masks", "eval_ssao_multi", "merge", "eval_ssao_plain"]
-        ev = {s: [] for s in names}
-        counts = []
-        calls = []
-        for k in range(reps):
-            f = frames[k]
-            calls.append((mr.prepare_build_masks(f["d"], f["n"], focal, mp, masks),
-                          mr.prepare_eval_ssao(f["d"], f["n"], focal, sp, lo, mp=mp, masks=masks),
-                          mr.prepare_upsample_merge(focal, mp, masks, lo, out),
-                          mr.prepare_eval_ssao(f["d"], f["n"], focal, sp, lo_plain)))
-        # the pre-marshalled calls keep the stream ahead of the host, so the
-        # events bracket back-to-back GPU work of each stage
-        for rep in range(2):
+        def stage_times(runners, reps):
+            """Per frame: the three stage durations from the frame's events,
+            and the spacing of two events recorded back to back after it (the
+            stream time one event takes; it sits inside every stage)."""
+            sets = []
+            stream = torch.cuda.current_stream()
+            runners[0]()
             plain[0]()
-            for k in range(reps):
-                build, ev_m, merge, ev_p = calls[k]
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-                e[0].record()
-                build()
-                e[1].record()
-                ev_m()
-                e[2].record()
-                merge()
-                e[3].record()
-                ev_p()
-                e[4].record()
-                if rep == 1:
-                    ev["build_masks"].append((e[0], e[1]))
-                    ev["eval_ssao_multi"].append((e[1], e[2]))
-                    ev["merge"].append((e[2], e[3]))
-                    ev["eval_ssao_plain"].append((e[3], e[4]))
-                    counts.append(masks.count[:3].clone())
-        torch.cuda.synchronize()
-        for s in names:
-            stages[s] = float(np.median([a.elapsed_time(b) for a, b in ev[s]]))
+            for rep in range(reps):
+                for k in range(nf):
+                    e = [mr.DeviceEvent() for _ in range(6)]
+                    runners[k].set_stage_events(e[:4])
+                    runners[k]()
+                    mr.record(e[4], stream)
+                    mr.record(e[5], stream)
+                    sets.append(e)
+            torch.cuda.synchronize()
+            for r in runners:
+                r.set_stage_events(None)
+            t = np.array([[e[j].elapsed_ms(e[j + 1]) for j in (0, 1, 2, 4)] for e in sets])  # ms
+            return t
+
+        reps = max(1, 96 // nf)
+        tm = stage_times(multi, reps)
+        tp = stage_times(plain, reps)
+        ev_ms = float(np.median(np.concatenate([tm[:, 3], tp[:, 3]])))
+        for j, nm in enumerate(["masks", "eval", "merge"]):
+            stages[f"multi_{nm}_ms"] = round(float(tm[:, j].mean()) - ev_ms, 5)
+        stages["plain_eval_ms"] = round(float(tp[:, 1].mean()) - ev_ms, 5)
+        stages["event_ms"] = round(ev_ms, 5)
+        stages["stage_samples"] = len(tm)
+
+        # stencil coverage of every configuration (identical masks through the
+        # separate mask entry point)
+        masks = mr.alloc_masks(W, H, focal, mp, dev, level_map=False)
+        counts = []
+        for k in range(nf):
+            f = frames[k]
+            mr.prepare_build_masks(f["d"], f["n"], focal, mp, masks)()
+            counts.append(masks.count[:3].clone())
         cnt = np.array([c.cpu().numpy().view(np.uint32) for c in counts], np.float64).mean(0)
         n = [npx >> (2 * (i - 1)) for i in (1, 2, 3, 4)]
         cov = [cnt[0] / n[0], cnt[1] / n[1], cnt[2] / n[2]]
         F = cov[0] + cov[1] / 4 + cov[2] / 16 + 1 / 64
-        evaluated = cnt[0] + cnt[1] + cnt[2] + n[3]
-        # algorithmic bytes (per-kernel byte accounting)
-        b_edges = 16 * n[0] + n[0] + n[1] + n[2] + 4 * (n[1] + n[2] + n[3])
-        b_blur = sum(6 * n[i] for i in range(3))
-        b_compact = sum(2 * n[i] + 4 * cnt[i] for i in range(3))
-        b_eval = 20 * evaluated + 4 * (cnt[0] + cnt[1] + cnt[2])
-        b_merge = 5 * n[0] + 4 * cnt[0] + 9 * (n[1] + n[2]) + 4 * n[3] + 4 * n[0]
-        b_frame = b_edges + b_blur + b_compact + b_eval + b_merge
-        gathers = 4.0 * S * evaluated
+        listed = cnt[0] + cnt[1] + cnt[2]
+        evaluated = listed + n[3]
+        nb = n[0] + n[1] + n[2]  # texels of the list levels (one bit each in the bit masks)
+        # algorithmic bytes per stage of the multi-resolution frame:
+        # compulsory reads and writes, sample gathers excluded
+        b_masks = (16 * n[0] + nb / 8 + 4 * (n[1] + n[2] + n[3])   # edges: G-buffer in, edge bits + level depth out
+                   + nb / 8 + nb / 8                               # stencil: edge bits in, stencil bits out
+                   + nb / 8 + 4 * nb / 32 + 4 * listed)            # ranks and lists
+        b_eval = 4 * listed + 16 * evaluated + nb / 8 + 4 * evaluated + 4 * listed
+        b_merge = nb / 8 + 4 * nb / 32 + 8 * listed + 4 * n[3] + 4 * n[0]
+        b_frame = b_masks + b_eval + b_merge
         t_frame = wall_m / args.steps
         ops_multi = evaluated * (SSAO_OPS_PER_SAMPLE * S + SSAO_OPS_PER_TEXEL)
         ops_plain = n[0] * (SSAO_OPS_PER_SAMPLE * S + SSAO_OPS_PER_TEXEL)
-        t_eval = stages["eval_ssao_multi"] * 1e-3
-        t_plain_eval = stages["eval_ssao_plain"] * 1e-3
+        t_eval = stages["multi_eval_ms"] * 1e-3
         stages.update({
             "coverage_f1_f2_f3": [round(c, 5) for c in cov], "F": round(F, 5),
-            "frame_alg_bytes": b_frame, "frame_hbm_frac": b_frame / t_frame / (HBM_PEAK_GBS * 1e9),
-            "frame_hbm_frac_incl_gathers": (b_frame + gathers) / t_frame / (HBM_PEAK_GBS * 1e9),
-            "build_masks_hbm_frac": (b_edges + b_blur + b_compact) / (stages["build_masks"] * 1e-3) / 8e12,
-            "merge_hbm_frac": b_merge / (stages["merge"] * 1e-3) / 8e12,
-            "eval_multi_valu_frac": ops_multi / t_eval / (VALU_PEAK_TOPS * 1e12),
-            "eval_plain_valu_frac": ops_plain / t_plain_eval / (VALU_PEAK_TOPS * 1e12),
+            "evaluated_texels": int(evaluated),
+            "frame_alg_bytes": int(b_frame),
+            "frame_hbm_frac": round(b_frame / t_frame / (HBM_PEAK_GBS * 1e9), 4),
+            "frame_hbm_frac_incl_gathers": round((b_frame + 4.0 * S * evaluated) / t_frame / (HBM_PEAK_GBS * 1e9), 4),
+            "masks_hbm_frac": round(b_masks / (stages["multi_masks_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "merge_hbm_frac": round(b_merge / (stages["multi_merge_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "eval_multi_valu_frac": round(ops_multi / t_eval / (VALU_PEAK_TOPS * 1e12), 4),
+            "eval_plain_valu_frac": round(ops_plain / (stages["plain_eval_ms"] * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4),
         })
-        # dominant kernel of the multi-resolution frame
+        # dominant kernel of the multi-resolution frame: the per-level SSAO
+        # evaluation, one launch per frame bracketed by events [1] and [2]
         achieved = ops_multi / t_eval / 1e12
-        roofline = {"kernel": "k_ssao (multi-res, all levels in one launch)", "bound": "alu",
+        roofline = {"kernel": "k_ssao<float, true> (all levels of one frame in one launch)", "bound": "alu",
                     "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None}
-        log(f"[bench] stages (ms): " + ", ".join(f"{s}={stages[s]:.4f}" for s in names))
+                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi"),
+                    "launch_ms": stages["multi_eval_ms"]}
+        log("[bench] stages (ms): " + ", ".join(f"{k}={v}" for k, v in stages.items() if k.endswith("_ms")))
 
     # ---------------- CPU oracle on a bounded sample ----------------
     cpu = None
@@ -223,15 +251,17 @@ def main():
         omp = oracle.MaskParams(num_levels=4, level_enable=0xF, sigma2=mp.sigma2, weight=mp.weight,
                                 normal_cos=float(np.float32(mp.normal_cos)))
         op = oracle.SSAOParams(K, args.radius, 0.02)
-        t_c = time.perf_counter()
-        done = 0
-        for k in range(3):
-            gb = frames[k]["gb"]
-            oracle.frame("ssao", gb.depth, gb.normal, gb.focal, omp, op)
-            done += 1
-            if time.perf_counter() - t_c > 25:
-                break
-        dt = time.perf_counter() - t_c
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):  # numpy's elementwise work is single-threaded; pin any BLAS too
+            t_c = time.perf_counter()
+            done = 0
+            for k in range(nf):  # about 20 s of CPU work
+                gb = frames[k]["gb"]
+                oracle.frame("ssao", gb.depth, gb.normal, gb.focal, omp, op)
+                done += 1
+                if time.perf_counter() - t_c > 20:
+                    break
+            dt = time.perf_counter() - t_c
         cpu = {"value": round(npx * done / dt / 1e6, 4), "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
                "sample": f"{done} full multi-resolution SSAO frames at {W}x{H} (configurations 0..{done - 1}), "
                          f"numpy single thread, {dt:.1f}s"}
@@ -260,8 +290,8 @@ def main():
         "p99_ms": round(float(np.percentile(lat_m, 99)), 4),
         "plain_p50_ms": round(float(np.percentile(lat_p, 50)), 4),
         "plain_p99_ms": round(float(np.percentile(lat_p, 99)), 4),
-        "mad_vs_plain": round(float(np.mean(mads)), 6),
-        "rms_vs_plain": round(float(np.mean(rmss)), 6),
+        "mad_vs_plain": round(float(np.mean(mads)), 6) if mads else None,
+        "rms_vs_plain": round(float(np.mean(rmss)), 6) if rmss else None,
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -56,6 +56,7 @@ extern "C" {
 #define MR_MAX_SAMPLES 8192
 #define MR_MAX_DIM 16384
 #define MR_VERSION 100
+#define MR_FRAME_EVENTS 4  /* stage events of mr_frame_desc */
 
 /* status codes */
 #define MR_OK 0
@@ -194,7 +195,14 @@ typedef struct {
  * effect     MR_EFFECT_*; the matching params pointer must be non-NULL (host).
  * multires   0 = naive full-resolution pass (masks unused), 1 = multi-res.
  * out        f32 [C][H][W], C = 3 for SSGI, else 1.
- * level_map  optional u8 [H][W] owner-level output (multires only). */
+ * level_map  optional u8 [H][W] owner-level output (multires only).
+ * stage_events  optional hipEvent_t handles (each may be NULL), recorded on
+ *            the frame's stream: [0] before the first kernel, [1] after the
+ *            masks and work lists (after the hard-shadow pass on the naive
+ *            path), [2] after the per-level evaluation, [3] after the merge.
+ *            They are owned by the caller and must have been created on the
+ *            stream's device; event [k+1] minus event [k] is the GPU time of
+ *            that stage. */
 typedef struct {
     int effect;
     int multires;
@@ -206,6 +214,7 @@ typedef struct {
     const mr_ssgi_params* ssgi;
     float* out;
     uint8_t* level_map;
+    void* stage_events[MR_FRAME_EVENTS];
 } mr_frame_desc;
 
 /* Workspace bytes needed by mr_frame for `effect` (MR_EFFECT_*) or by

@@ -620,11 +620,22 @@ int check_effect_params(int effect, const mr_ssao_params* ssao, const mr_shadow_
     return fail(MR_E_PARAM, "unknown effect %d", effect);
 }
 
+// records the caller's stage event k, if any, on the frame's stream
+int mark(const mr_frame_desc* d, int k, hipStream_t s) {
+    void* e = d->stage_events[k];
+    if (!e) return MR_OK;
+    const hipError_t r = hipEventRecord(static_cast<hipEvent_t>(e), s);
+    if (r != hipSuccess) return fail(MR_E_DEVICE, "stage event %d: %s", k, hipGetErrorString(r));
+    return MR_OK;
+}
+
 int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, hipStream_t s) {
     const int effect = d->effect;
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
     const LeanLayout f = lean_layout(g, effect);
     uint32_t* count = reinterpret_cast<uint32_t*>(b + f.count);
+    int st = mark(d, 0, s);
+    if (st) return st;
     const uint8_t* hard = nullptr;
     if (effect == MR_EFFECT_SHADOW) {
         HardArgs ha{};
@@ -720,8 +731,10 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
             lo[i - 1] = reinterpret_cast<float*>(b + f.cL);
         }
     }
-    int st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s, /*compact=*/true, &la);
+    if ((st = mark(d, 1, s))) return st;
+    st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s, /*compact=*/true, &la);
     if (st) return st;
+    if ((st = mark(d, 2, s))) return st;
     // merge by rank
     LeanMergeArgs ma{};
     ma.nlev = g.nlev;
@@ -755,7 +768,7 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         }
     }
     if (launch_lean_merge(ma, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
-    return MR_OK;
+    return mark(d, 3, s);
 }
 
 }  // namespace
@@ -898,7 +911,10 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
         if (!st) st = check_gbuffer(&d->g, effect != MR_EFFECT_SHADOW, effect == MR_EFFECT_SSGI);
         if (st) return st;
         float* out[kMaxLevels] = {d->out};
-        return do_eval(effect, &d->g, &d->cam, g, nullptr, params, out, s);
+        if ((st = mark(d, 0, s)) || (st = mark(d, 1, s))) return st;
+        if ((st = do_eval(effect, &d->g, &d->cam, g, nullptr, params, out, s))) return st;
+        if ((st = mark(d, 2, s))) return st;
+        return mark(d, 3, s);
     }
     Geo g;
     st = check_geo(&d->cam, &d->mp, g);
@@ -928,6 +944,7 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
         if (i >= 2) m.level_depth[i - 1] = reinterpret_cast<float*>(b + f.level_depth[i - 1]);
         lo[i - 1] = reinterpret_cast<float*>(b + f.level_out[i - 1]);
     }
+    if ((st = mark(d, 0, s))) return st;
     const uint8_t* hard = nullptr;
     if (effect == MR_EFFECT_SHADOW) {
         HardArgs a{};
@@ -946,11 +963,14 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     }
     st = do_build_masks(&d->g, g, &d->mp, hard, &m, b + f.scratch, s);
     if (st) return st;
+    if ((st = mark(d, 1, s))) return st;
     st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s);
     if (st) return st;
+    if ((st = mark(d, 2, s))) return st;
     const float* clo[kMaxLevels];
     for (int k = 0; k < kMaxLevels; ++k) clo[k] = lo[k];
-    return do_merge(g, &d->mp, &m, clo, C, d->out, s);
+    if ((st = do_merge(g, &d->mp, &m, clo, C, d->out, s))) return st;
+    return mark(d, 3, s);
 }
 
 const char* mr_status_string(int status) {

@@ -23,6 +23,7 @@ MR_OK, MR_E_NULL, MR_E_SHAPE, MR_E_PARAM, MR_E_WORKSPACE, MR_E_DTYPE, MR_E_DEVIC
 MR_F32, MR_F16 = 0, 1
 MR_EFFECT_SSAO, MR_EFFECT_SHADOW, MR_EFFECT_SSGI = 0, 1, 2
 MR_WS_MASKS = -1
+MR_FRAME_EVENTS = 4
 EFFECTS = {"ssao": MR_EFFECT_SSAO, "shadow": MR_EFFECT_SHADOW, "ssgi": MR_EFFECT_SSGI}
 
 c_float6 = ctypes.c_float * MR_MAX_LEVELS
@@ -72,7 +73,7 @@ class mr_frame_desc(ctypes.Structure):
                 ("cam", mr_camera), ("mp", mr_mask_params),
                 ("ssao", ctypes.POINTER(mr_ssao_params)), ("shadow", ctypes.POINTER(mr_shadow_params)),
                 ("ssgi", ctypes.POINTER(mr_ssgi_params)), ("out", ctypes.c_void_p),
-                ("level_map", ctypes.c_void_p)]
+                ("level_map", ctypes.c_void_p), ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS)]
 
 
 # entry points and their ctypes signatures (also used by the export test)
@@ -397,6 +398,57 @@ def mr_upsample_merge(focal, mp: MaskParams, masks: Masks, level_out: dict, chan
     return out
 
 
+_hip = None
+
+
+def _hip_runtime():
+    """The HIP runtime torch has loaded (one runtime per process)."""
+    global _hip
+    if _hip is None:
+        path = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+        _hip = ctypes.CDLL(path if os.path.exists(path) else "libamdhip64.so")
+        _hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        _hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        _hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        _hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    return _hip
+
+
+HIP_EVENT_RELEASE_TO_DEVICE = 0x40000000  # hipEventReleaseToDevice
+
+
+class DeviceEvent:
+    """A timing event recorded with a device-scope release, so that marking a
+    stage boundary does not write caches back to the system between two
+    kernels (torch's events use the default, system-scope release)."""
+
+    def __init__(self):
+        torch.cuda.init()
+        h = ctypes.c_void_p()
+        err = _hip_runtime().hipEventCreateWithFlags(ctypes.byref(h), HIP_EVENT_RELEASE_TO_DEVICE)
+        if err != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({err})")
+        self.handle = h.value
+
+    def elapsed_ms(self, later: "DeviceEvent") -> float:
+        ms = ctypes.c_float()
+        err = _hip_runtime().hipEventElapsedTime(ctypes.byref(ms), self.handle, later.handle)
+        if err != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({err})")
+        return ms.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _hip is not None:
+            _hip.hipEventDestroy(self.handle)
+
+
+def record(event: DeviceEvent, stream=None):
+    """Record a DeviceEvent on `stream` (default: torch's current stream)."""
+    err = _hip_runtime().hipEventRecord(event.handle, _stream(stream))
+    if err != 0:
+        raise RuntimeError(f"hipEventRecord failed ({err})")
+
+
 class FrameRunner:
     """Pre-marshalled mr_frame call: the descriptor and workspace are built
     once so that repeated calls cost one ctypes call each."""
@@ -433,6 +485,26 @@ class FrameRunner:
         self._fn = lib().mr_frame
         self._ws = _ptr(self.workspace)
         self._nws = self.workspace.numel()
+
+    def set_stage_events(self, events):
+        """Have mr_frame record `events` (MR_FRAME_EVENTS DeviceEvent or
+        torch.cuda.Event objects with timing, or None to stop) at its stage
+        boundaries."""
+        if events is None:
+            for k in range(MR_FRAME_EVENTS):
+                self.desc.stage_events[k] = None
+            self._events = None
+            return
+        if len(events) != MR_FRAME_EVENTS:
+            raise ValueError(f"need {MR_FRAME_EVENTS} events")
+        for k, e in enumerate(events):
+            if isinstance(e, DeviceEvent):
+                self.desc.stage_events[k] = e.handle
+                continue
+            if not e.cuda_event:  # torch creates the HIP event at its first record
+                e.record()
+            self.desc.stage_events[k] = e.cuda_event
+        self._events = tuple(events)
 
     def __call__(self, stream=None):
         _check(self._fn(ctypes.byref(self.desc), self._ws, self._nws, _stream(stream)))

@@ -5,6 +5,8 @@ import ctypes
 import math
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -38,6 +40,35 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(mr.mr_mask_params) == 4 + 4 + 4 + 4 + 24 + 24 + 24
     assert ctypes.sizeof(mr.mr_masks) == 8 * (2 + 4 * 6 + 1)
     assert ctypes.sizeof(mr.mr_gbuffer) == 40
+
+
+STRUCTS = ["mr_gbuffer", "mr_camera", "mr_mask_params", "mr_masks", "mr_ssao_params", "mr_shadow_params",
+           "mr_ssgi_params", "mr_frame_desc"]
+
+
+@pytest.mark.skipif(not shutil.which("gcc"), reason="needs a C compiler")
+def test_struct_layout_matches_the_c_compiler(tmp_path):
+    # sizeof / offsetof of every header struct as the C compiler lays them
+    # out, against the ctypes mirrors the binding passes across the boundary
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mr.h"', 'int main(void) {']
+    for st in STRUCTS:
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for name, _ in getattr(mr, st)._fields_:
+            lines.append(f'printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        st, name, v = line.split()
+        got[(st, name)] = int(v)
+    for st in STRUCTS:
+        cls = getattr(mr, st)
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)
 
 
 def test_version_and_status_strings():

@@ -248,6 +248,36 @@ def test_deterministic_across_runs():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("multires", [True, False])
+def test_stage_events(multires):
+    """The stage events bracket the frame in order and leave its output
+    unchanged."""
+    log(f"[gpu] stage events multires={multires}")
+    c = case("1080p")
+    sp = mr.ssao_params(c["k"], c["r"], 0.02)
+    fr = mr.FrameRunner("ssao", c["d"], c["n"], c["gb"].focal, c["mp"], multires, params=sp)
+    ref = fr().clone()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(mr.MR_FRAME_EVENTS)]
+    fr.set_stage_events(ev)
+    out = fr().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    t = [ev[k].elapsed_time(ev[k + 1]) for k in range(3)]
+    assert all(x >= 0 for x in t)
+    assert abs(sum(t) - ev[0].elapsed_time(ev[3])) <= 1e-3 + 1e-3 * sum(t)
+    assert t[1] > 0  # the evaluation kernel runs between events 1 and 2
+    fr.set_stage_events(None)
+    assert torch.equal(fr(), ref)
+    dv = [mr.DeviceEvent() for _ in range(mr.MR_FRAME_EVENTS)]
+    fr.set_stage_events(dv)
+    out = fr().clone()
+    torch.cuda.synchronize()
+    fr.set_stage_events(None)
+    assert torch.equal(out, ref)
+    t = [dv[k].elapsed_ms(dv[k + 1]) for k in range(3)]
+    assert all(x >= 0 for x in t) and t[1] > 0
+
+
 def test_errors_enqueue_nothing():
     log("[gpu] error paths")
     c = case("256_3lv")
