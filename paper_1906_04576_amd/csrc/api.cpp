@@ -304,9 +304,14 @@ bool lean_ok(const Geo& g, const mr_mask_params* mp) {
     return true;
 }
 
+// ranking tiles of a level with wpr words per row and H rows
+unsigned lean_tiles(int wpr, int H) {
+    return (unsigned)((wpr + kLeanTileWords - 1) / kLeanTileWords) * (unsigned)((H + kLeanTileRows - 1) / kLeanTileRows);
+}
+
 struct LeanLayout {
     size_t count = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, ac[3] = {}, cc[3] = {};
-    size_t zi[kMaxLevels] = {}, cL = 0, blk_sum = 0, blk_off = 0, hard = 0;
+    size_t zi[kMaxLevels] = {}, cL = 0, hard = 0;
     unsigned nblk = 0;
     size_t bytes = 0;
 };
@@ -331,15 +336,13 @@ LeanLayout lean_layout(const Geo& g, int effect) {
         f.list[i - 1] = take(4 * n);
         f.ac[i - 1] = take(4 * n);
         f.cc[i - 1] = take(4 * n * C);
-        f.nblk += (unsigned)((words + 255) / 256);
+        f.nblk += lean_tiles(g.Wi[i - 1] / 32, g.Hi[i - 1]);
     }
     for (int j = 0; j < g.nlev; ++j) {
         const int i = g.levels[j];
         if (i >= 2) f.zi[i - 1] = take(4 * (size_t)g.n(i));
     }
     f.cL = take(4 * (size_t)g.n(g.L) * C);
-    f.blk_sum = take(4 * (size_t)f.nblk + 4);
-    f.blk_off = take(4 * (size_t)f.nblk + 4);
     if (effect == MR_EFFECT_SHADOW) f.hard = take((size_t)g.W * g.H);
     f.bytes = off;
     return f;
@@ -674,13 +677,12 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
             ea.wpr[i - 1] = g.Wi[i - 1] / 32;
         }
     }
+    ea.zero_counts = count;
     if (launch_edges(ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
-    // stencils, ranks, lists, a_i at listed texels
+    // stencils, ranks, lists (a_i at listed texels comes with the evaluation)
     LeanArgs la{};
     la.nlev = g.nlev - 1;
     la.count = count;
-    la.blk_sum = reinterpret_cast<uint32_t*>(b + f.blk_sum);
-    la.blk_off = reinterpret_cast<uint32_t*>(b + f.blk_off);
     unsigned blk = 0;
     for (int j = 0; j + 1 < g.nlev; ++j) {
         const int i = g.levels[j];
@@ -695,13 +697,14 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         L.wpr = L.W / 32;
         gauss(&d->mp, i, L.g, L.r);
         L.nwords = (unsigned)L.wpr * (unsigned)L.H;
+        L.tiles_x = (L.wpr + kLeanTileWords - 1) / kLeanTileWords;
         L.blk_base = blk;
         L.count_idx = i - 1;
-        blk += (L.nwords + 255) / 256;
+        blk += lean_tiles(L.wpr, L.H);
     }
     la.nblk = blk;
-    // a_i is written by the evaluation kernel (alpha_blocks = 0)
-    if (launch_lean_masks(la, 0, s) != hipSuccess)
+    // a_i is written by the evaluation kernel
+    if (launch_lean_masks(la, s) != hipSuccess)
         return fail(MR_E_DEVICE, "lean mask kernels launch failed");
     if (d->level_map) {
         LeanMapArgs lm{};

@@ -51,6 +51,17 @@ __device__ __forceinline__ unsigned item_local(const ItemMap& m, unsigned item, 
     return item - base;
 }
 
+// Item chunks of 256 are handed out in rounds of gridDim.x blocks; inside a
+// round, block b takes chunk xcd_remap(b, n), so each XCD works through one
+// contiguous run of chunks (consecutive items are neighbouring texels, and
+// their sample gathers then share that XCD's L2).  Returns the first item of
+// the block's chunk in round `base`, or ~0u when the block has none.
+__device__ __forceinline__ unsigned chunk_of(unsigned base, unsigned nchunks) {
+    const unsigned n = min(gridDim.x, nchunks - base);
+    if (blockIdx.x >= n) return ~0u;
+    return (base + xcd_remap(blockIdx.x, n)) * 256u;
+}
+
 // Sample sets of at most this many entries are staged in LDS once per
 // workgroup; the sample loops then read them with uniform LDS addresses
 // instead of a vector load (and its full wait) per sample.

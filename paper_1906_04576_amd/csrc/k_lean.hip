@@ -29,8 +29,30 @@ __device__ __forceinline__ int lean_level(const LeanArgs& A, unsigned b) {
     return l;
 }
 
-// S words (dilated edge bits) and per-256-word popcount sums; the radius is
-// a template parameter so that all rows' words are loaded in one batch
+// Words are ranked tile by tile (kLeanTileWords words x kLeanTileRows rows,
+// one 256-thread block per tile, row-major inside a tile, tiles row-major),
+// so that consecutive work-list entries lie close together on screen and the
+// evaluation's sample gathers of one wave touch a compact region.  The rank
+// of a texel is still woff[word] + popcount of the lower bits of its word.
+struct TileWord {
+    int y, xw;
+    bool ok;
+    unsigned w;
+};
+
+__device__ __forceinline__ TileWord tile_word(const LeanLevel& L, unsigned b, unsigned t) {
+    const unsigned bl = b - L.blk_base;
+    const unsigned ty = bl / (unsigned)L.tiles_x, tx = bl - ty * (unsigned)L.tiles_x;
+    TileWord r;
+    r.xw = (int)(tx * kLeanTileWords + (t % kLeanTileWords));
+    r.y = (int)(ty * kLeanTileRows + (t / kLeanTileWords));
+    r.ok = r.xw < L.wpr && r.y < L.H;
+    r.w = (unsigned)r.y * (unsigned)L.wpr + (unsigned)r.xw;
+    return r;
+}
+
+// one stencil word (dilated edge bits); the radius is a template parameter
+// so that all rows' words are loaded in one batch
 template <int R>
 __device__ __forceinline__ unsigned stencil_word(const LeanLevel& L, int y, int xw) {
     unsigned c[2 * R + 1], p[2 * R + 1], n[2 * R + 1];
@@ -49,33 +71,6 @@ __device__ __forceinline__ unsigned stencil_word(const LeanLevel& L, int y, int 
     return acc;
 }
 
-__global__ __launch_bounds__(256) void k_lean_stencil(LeanArgs A) {
-    __shared__ unsigned wsum[4];
-    const unsigned b = blockIdx.x;
-    const int l = lean_level(A, b);
-    const LeanLevel& L = A.lv[l];
-    const unsigned w = (b - L.blk_base) * 256 + threadIdx.x;
-    unsigned cnt = 0;
-    if (w < L.nwords) {
-        const int y = (int)(w / (unsigned)L.wpr), xw = (int)(w - (unsigned)y * (unsigned)L.wpr);
-        unsigned acc = 0;
-        switch (L.r) {
-#define MR_STENCIL(R) \
-    case R: acc = stencil_word<R>(L, y, xw); break;
-            MR_STENCIL(0) MR_STENCIL(1) MR_STENCIL(2) MR_STENCIL(3) MR_STENCIL(4) MR_STENCIL(5) MR_STENCIL(6)
-            MR_STENCIL(7) MR_STENCIL(8)
-#undef MR_STENCIL
-            default: break;
-        }
-        L.Sb[w] = acc;
-        cnt = __popc(acc);
-    }
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-    if (__lane_id() == 0) wsum[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) A.blk_sum[b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-}
-
 __device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
     const int lane = __lane_id();
 #pragma unroll
@@ -86,57 +81,47 @@ __device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
     return v;
 }
 
-// exclusive scan of the block sums per level; level totals into count[]
-__global__ __launch_bounds__(1024) void k_lean_scan(LeanArgs A) {
-    __shared__ unsigned wtot[16];
-    const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
-    if (t < kMaxLevels) A.count[t] = 0;
-    __syncthreads();
-    for (int l = 0; l < A.nlev; ++l) {
-        const unsigned b0 = A.lv[l].blk_base;
-        const unsigned b1 = l + 1 < A.nlev ? A.lv[l + 1].blk_base : A.nblk;
-        unsigned carry = 0;
-        for (unsigned base = b0; base < b1; base += 1024) {
-            const unsigned c = base + t;
-            const unsigned v = c < b1 ? A.blk_sum[c] : 0u;
-            const unsigned inc = wave_scan_incl(v);
-            if (lane == 63) wtot[wv] = inc;
-            __syncthreads();
-            unsigned before = 0, all = 0;
-            for (int w = 0; w < 16; ++w) {
-                if (w < wv) before += wtot[w];
-                all += wtot[w];
-            }
-            if (c < b1) A.blk_off[c] = carry + before + inc - v;
-            carry += all;
-            __syncthreads();
-        }
-        if (t == 0) A.count[A.lv[l].count_idx] = carry;
-    }
-}
-
-// per-word ranks and the row-major lists of stencil texels
-__global__ __launch_bounds__(256) void k_lean_scatter(LeanArgs A) {
+// One block per ranking tile: the tile's stencil words (dilated edge bits),
+// their ranks and list entries.  The tile takes its run of list positions
+// with one atomic add on the level's count, so tiles land in the list in
+// the order they finish; the rank of every texel is stored with it (woff),
+// which is all the merge needs, and each texel's result does not depend on
+// where in the list it sits.  The counts are zeroed by the edge kernel.
+__global__ __launch_bounds__(256) void k_lean_rank(LeanArgs A) {
     __shared__ unsigned wtot[4];
+    __shared__ unsigned tile_base;
     const unsigned b = blockIdx.x;
     const int l = lean_level(A, b);
     const LeanLevel& L = A.lv[l];
-    const unsigned w = (b - L.blk_base) * 256 + threadIdx.x;
-    const unsigned s = w < L.nwords ? L.Sb[w] : 0u;
-    const unsigned cnt = __popc(s);
+    const TileWord tw = tile_word(L, b, threadIdx.x);
+    unsigned acc = 0;
+    if (tw.ok) {
+        switch (L.r) {
+#define MR_STENCIL(R) \
+    case R: acc = stencil_word<R>(L, tw.y, tw.xw); break;
+            MR_STENCIL(0) MR_STENCIL(1) MR_STENCIL(2) MR_STENCIL(3) MR_STENCIL(4) MR_STENCIL(5) MR_STENCIL(6)
+            MR_STENCIL(7) MR_STENCIL(8)
+#undef MR_STENCIL
+            default: break;
+        }
+    }
+    const unsigned cnt = __popc(acc);
     const unsigned inc = wave_scan_incl(cnt);
     const int wv = threadIdx.x >> 6;
     if (__lane_id() == 63) wtot[wv] = inc;
     __syncthreads();
-    unsigned before = 0;
-    for (int k = 0; k < wv; ++k) before += wtot[k];
-    if (w >= L.nwords) return;
-    unsigned pos = A.blk_off[b] + before + inc - cnt;
-    L.woff[w] = pos;
-    if (!s) return;
-    const int y = (int)(w / (unsigned)L.wpr), xw = (int)(w - (unsigned)y * (unsigned)L.wpr);
-    const unsigned base = (unsigned)y * (unsigned)L.W + (unsigned)xw * 32u;
-    unsigned m = s;
+    if (threadIdx.x == 0) {
+        const unsigned total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        tile_base = total ? atomicAdd(A.count + L.count_idx, total) : 0u;
+    }
+    __syncthreads();
+    if (!tw.ok) return;
+    unsigned pos = tile_base + inc - cnt;
+    for (int k = 0; k < wv; ++k) pos += wtot[k];
+    L.Sb[tw.w] = acc;
+    L.woff[tw.w] = pos;
+    const unsigned base = (unsigned)tw.y * (unsigned)L.W + (unsigned)tw.xw * 32u;
+    unsigned m = acc;
     while (m) {
         const int bit = __builtin_ctz(m);
         m &= m - 1;
@@ -144,43 +129,8 @@ __global__ __launch_bounds__(256) void k_lean_scatter(LeanArgs A) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_lean_alpha(LeanArgs A) {
-    unsigned cum[4];
-    cum[0] = 0;
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        unsigned n = 0;
-        if (l < A.nlev) n = min(A.count[A.lv[l].count_idx], A.lv[l].nwords * 32u);
-        cum[l + 1] = cum[l] + n;
-    }
-    const unsigned total = cum[3];
-    for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
-        const int l = (item >= cum[1] ? 1 : 0) + (item >= cum[2] ? 1 : 0);
-        const LeanLevel& L = A.lv[l];
-        const unsigned local = item - (l == 0 ? 0u : (l == 1 ? cum[1] : cum[2]));
-        const unsigned t = L.list[local];
-        const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
-        float a = 0.0f;
-        switch (L.r) {
-#define MR_ALPHA(R) \
-    case R: a = alpha_at<R>(L.Eb, L.wpr, L.H, L.g, x, y); break;
-            MR_ALPHA(0) MR_ALPHA(1) MR_ALPHA(2) MR_ALPHA(3) MR_ALPHA(4) MR_ALPHA(5) MR_ALPHA(6) MR_ALPHA(7)
-            MR_ALPHA(8)
-#undef MR_ALPHA
-            default: break;
-        }
-        L.ac[local] = a;
-    }
-}
-
-// alpha_blocks = 0: a_i is computed by the evaluation kernel instead
-hipError_t launch_lean_masks(const LeanArgs& a, unsigned alpha_blocks, hipStream_t s) {
-    if (a.nblk) hipLaunchKernelGGL(k_lean_stencil, dim3(a.nblk), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_lean_scan, dim3(1), dim3(1024), 0, s, a);
-    if (a.nblk) {
-        hipLaunchKernelGGL(k_lean_scatter, dim3(a.nblk), dim3(256), 0, s, a);
-        if (alpha_blocks) hipLaunchKernelGGL(k_lean_alpha, dim3(alpha_blocks), dim3(256), 0, s, a);
-    }
+hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s) {
+    if (a.nblk) hipLaunchKernelGGL(k_lean_rank, dim3(a.nblk), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

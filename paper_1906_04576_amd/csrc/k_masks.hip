@@ -59,6 +59,7 @@ __device__ __forceinline__ bool ndot_lt(const float* a, const float* b, float cn
 template <typename NT>
 __global__ __launch_bounds__(256) void k_edges_generic(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
     __shared__ uint8_t p4[4][8];
+    if (a.zero_counts && blockIdx.x == 0 && threadIdx.x < kMaxLevels) a.zero_counts[threadIdx.x] = 0u;
     const unsigned tile = xcd_remap(blockIdx.x, ntiles);
     const int x0 = (int)(tile % tiles_x) * kEdgeTW;
     const int y0 = (int)(tile / tiles_x) * kEdgeTH;
@@ -281,16 +282,21 @@ struct NormalRow<_Float16> {
     }
 };
 
-template <typename NT, bool HARD, bool BITS>
+// WIDE: the four waves of a block sit side by side (256 x 8 pixel tile), so
+// that a block reads 1 KB runs of every row; levels up to 4 only (the 8 x 8
+// pooling blocks stay inside one wave).  Otherwise they are stacked (64 x 32
+// tile) and levels 5 and 6 are pooled across the waves through LDS.
+template <typename NT, bool HARD, bool BITS, bool WIDE>
 __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
     __shared__ uint8_t p4[4][8];
+    if (a.zero_counts && blockIdx.x == 0 && threadIdx.x < kMaxLevels) a.zero_counts[threadIdx.x] = 0u;
     const unsigned tile = xcd_remap(blockIdx.x, ntiles);
-    const int x0 = (int)(tile % tiles_x) * kEdgeTW;
-    const int y0 = (int)(tile / tiles_x) * kEdgeTH;
-    const int W = a.W, H = a.H;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int x0 = WIDE ? (int)(tile % tiles_x) * (4 * kEdgeTW) + wave * kEdgeTW : (int)(tile % tiles_x) * kEdgeTW;
+    const int y0 = WIDE ? (int)(tile / tiles_x) * 8 : (int)(tile / tiles_x) * kEdgeTH;
+    const int W = a.W, H = a.H;
     const int cg = lane & 15, rp = lane >> 4;
-    const int xb = x0 + 4 * cg, yb = y0 + 8 * wave + 2 * rp;
+    const int xb = x0 + 4 * cg, yb = y0 + (WIDE ? 0 : 8 * wave) + 2 * rp;
     const bool any = xb < W && yb < H;
     const unsigned plane = (unsigned)W * (unsigned)H;
     const __amdgpu_buffer_rsrc_t rz = buf_rsrc(a.depth, plane * 4u);
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
     v |= __shfl_xor(v, 32, 64);
     if (any && a.Ei[3] && (cg & 1) == 0 && rp == 0)
         a.Ei[3][(unsigned)(yb >> 3) * (unsigned)a.Wi[3] + (unsigned)(xb >> 3)] = (uint8_t)v;
-    if (a.num_levels >= 5) {
+    if (!WIDE && a.num_levels >= 5) {
         if (rp == 0 && (cg & 1) == 0) p4[wave][cg >> 1] = (uint8_t)v;
         __syncthreads();
         if (a.Ei[4] && t < 8) {
@@ -487,7 +493,15 @@ hipError_t launch_edges(const EdgeArgs& a, int normal_dtype, hipStream_t s) {
     const unsigned n = tx * ty;
     const bool f16 = normal_dtype == MR_F16, hard = a.hard != nullptr, bits = a.Eb[0] != nullptr;
     if ((a.W & 3) == 0 && a.W >= 4) {
-#define MR_EDGES(NT, HD, BT) hipLaunchKernelGGL((k_edges_vec<NT, HD, BT>), dim3(n), dim3(256), 0, s, a, tx, n)
+        const bool wide = a.num_levels <= 4;
+        const unsigned wx = (a.W + 4 * kEdgeTW - 1) / (4 * kEdgeTW), wy = (a.H + 7) / 8;
+#define MR_EDGES(NT, HD, BT)                                                                                 \
+    do {                                                                                                     \
+        if (wide)                                                                                            \
+            hipLaunchKernelGGL((k_edges_vec<NT, HD, BT, true>), dim3(wx * wy), dim3(256), 0, s, a, wx, wx * wy); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_edges_vec<NT, HD, BT, false>), dim3(n), dim3(256), 0, s, a, tx, n);        \
+    } while (0)
         if (bits) {
             if (f16 && hard) MR_EDGES(_Float16, true, true);
             else if (f16) MR_EDGES(_Float16, false, true);

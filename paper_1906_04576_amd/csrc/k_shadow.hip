@@ -101,7 +101,12 @@ template <bool LDS, bool AL>
 __device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds, const float* pds, const float* eg) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
-    for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+    const unsigned nchunks = (total + 255) / 256;
+    for (unsigned base = 0; base < nchunks; base += gridDim.x) {
+        const unsigned first = chunk_of(base, nchunks);
+        if (first == ~0u) break;
+        const unsigned item = first + threadIdx.x;
+        if (item >= total) continue;
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);

@@ -26,24 +26,27 @@ __device__ __forceinline__ float ssao_texel(const SsaoArgs& a, const EvalLevel& 
     const float rnx = r * nx, rny = r * ny, rnz = r * nz;
     const float Wf = (float)L.W, Hf = (float)L.H;
     const float f = L.f, cx = L.cx, cy = L.cy;
+    // Branch-free sample loop: every sample computes its projection and
+    // gathers (texel 0 when it is off-screen or behind the eye), and counts
+    // only if all tests pass; the count is the same as skipping the sample,
+    // and the unrolled body keeps several gathers in flight per wave.
     int occ = 0;
+#pragma unroll 4
     for (int s = 0; s < S; ++s) {
         const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
         const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
         const float d = -qz;
-        if (!(d > 0.0f)) continue;
         const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
         const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
         const float inv = 1.0f / d;
         const float u = cx + (qx * inv) * f;
         const float v = cy - (qy * inv) * f;
-        if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
-        // u, v >= 0 here, so truncation is floor
-        const int sx = (int)u, sy = (int)v;
+        const bool on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
+        // u, v >= 0 when on, so truncation is floor
+        const int sx = (int)(on ? u : 0.0f), sy = (int)(on ? v : 0.0f);
         const float zs = zb[(unsigned)sy * zpy + (unsigned)sx * zpx];
-        // z_s <= 0 must not count; +inf and NaN fail the first test below
-        if (!(zs > 0.0f)) continue;
-        if (zs < d - (b * d) && fabsf(z - zs) < r) ++occ;
+        // z_s <= 0 must not count; +inf and NaN fail the depth test
+        occ += (on & (zs > 0.0f) & (zs < d - (b * d)) & (fabsf(z - zs) < r)) ? 1 : 0;
     }
     return (float)occ / (float)S;
 }
@@ -54,7 +57,12 @@ __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, c
     const unsigned total = item_total(m);
     const NT* nrm = static_cast<const NT*>(a.c.normal);
     const unsigned plane = (unsigned)a.c.plane;
-    for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+    const unsigned nchunks = (total + 255) / 256;
+    for (unsigned base = 0; base < nchunks; base += gridDim.x) {
+        const unsigned first = chunk_of(base, nchunks);
+        if (first == ~0u) break;
+        const unsigned item = first + threadIdx.x;
+        if (item >= total) continue;
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);

@@ -21,7 +21,12 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
     const float rmin = 0.1f * r;
     const float rmin2 = rmin * rmin;
     const float scale = (r * r) / (float)S;
-    for (unsigned item = blockIdx.x * 256 + threadIdx.x; item < total; item += gridDim.x * 256) {
+    const unsigned nchunks = (total + 255) / 256;
+    for (unsigned base = 0; base < nchunks; base += gridDim.x) {
+        const unsigned first = chunk_of(base, nchunks);
+        if (first == ~0u) break;
+        const unsigned item = first + threadIdx.x;
+        if (item >= total) continue;
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);

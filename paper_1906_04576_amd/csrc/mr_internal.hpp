@@ -68,6 +68,7 @@ struct EdgeArgs {
     // bit x % 32 of word x / 32, rows of wpr words; null = not written
     uint32_t* Eb[3];
     int wpr[3];
+    uint32_t* zero_counts;  // optional: MR_MAX_LEVELS counters set to 0 by block 0
 };
 
 struct BlurLevel {
@@ -209,13 +210,16 @@ constexpr int kMergeLDS = 640;  // >= sum of rw * rh over levels 2..6 (518)
 // ---------------------------------------------------------------------------
 // lean frame path (bit-packed stencils, values stored by rank)
 // ---------------------------------------------------------------------------
+constexpr int kLeanTileWords = 16, kLeanTileRows = 16;  // 256 words per ranking tile
+
 struct LeanLevel {
     const uint32_t* Eb;  // edge bits
     uint32_t* Sb;        // stencil bits
-    uint32_t* woff;      // per word: number of stencil texels before it (its rank base)
-    uint32_t* list;      // stencil texels, row-major
+    uint32_t* woff;      // per word: number of stencil texels ranked before it
+    uint32_t* list;      // stencil texels in rank (tile) order
     float* ac;           // a_i by rank
     int W, H, wpr, r;
+    int tiles_x;         // ranking tiles per row of words
     unsigned nwords, blk_base;
     int count_idx;
     float g[2 * kMaxRadius + 1];
@@ -224,10 +228,8 @@ struct LeanLevel {
 struct LeanArgs {
     LeanLevel lv[3];  // enabled levels below the coarsest (levels 1..3)
     int nlev;
-    unsigned nblk;    // 256-word blocks over all levels
-    uint32_t* blk_sum;
-    uint32_t* blk_off;
-    uint32_t* count;
+    unsigned nblk;    // ranking tiles (one block each) over all levels
+    uint32_t* count;  // per level, zero on entry
 };
 
 struct LeanMapArgs {
@@ -277,7 +279,7 @@ hipError_t launch_shadow(const ShadowArgs& a, unsigned total_hint, hipStream_t s
 hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
                        hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
-hipError_t launch_lean_masks(const LeanArgs& a, unsigned alpha_blocks, hipStream_t s);
+hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s);
 hipError_t launch_lean_level_map(const LeanMapArgs& a, hipStream_t s);
 hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s);
 
