@@ -4,13 +4,18 @@
 #pragma once
 
 #include "mr_internal.hpp"
+#include "recip.hpp"
 
 namespace mr {
 
-// Item ranges: level j owns items [cum[j], cum[j+1]); list levels take their
-// length from the device counts, dense levels from dense_n.
+// Item ranges: level j owns items [cum[j], cum[j+1]), its cnt[j] texels
+// padded to a multiple of 64, so that every wave's 64 items belong to one
+// level: the level index is then wave-uniform and the level's parameters
+// are read with scalar loads (the padding items are skipped).  List levels
+// take their length from the device counts, dense levels from dense_n.
 struct ItemMap {
     unsigned cum[kMaxLevels + 1];
+    unsigned cnt[kMaxLevels];
     int nlev;
 };
 
@@ -25,7 +30,8 @@ __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
             // a list never holds more entries than its level has texels
             n = c.lv[j].list ? min(c.counts[c.lv[j].count_idx], c.lv[j].dense_n) : c.lv[j].dense_n;
         }
-        m.cum[j + 1] = m.cum[j] + n;
+        m.cnt[j] = n;
+        m.cum[j + 1] = m.cum[j] + ((n + 63u) & ~63u);
     }
     return m;
 }
@@ -34,32 +40,45 @@ __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
 __device__ __forceinline__ unsigned item_total(const ItemMap& m) { return m.cum[kMaxLevels]; }
 
 // level of an item: unrolled comparisons (a dynamically indexed prefix
-// array would be demoted to per-thread LDS)
+// array would be demoted to per-thread LDS); the same for all lanes of a
+// wave, which readfirstlane tells the compiler
 __device__ __forceinline__ int item_level(const ItemMap& m, unsigned item) {
     int j = 0;
 #pragma unroll
     for (int k = 1; k < kMaxLevels; ++k) j += (k < m.nlev && item >= m.cum[k]) ? 1 : 0;
-    return j;
+    return __builtin_amdgcn_readfirstlane(j);
 }
 
-// item index relative to its level's first item
+// item index relative to its level's first item, or ~0u for a padding item
 __device__ __forceinline__ unsigned item_local(const ItemMap& m, unsigned item, int j) {
-    unsigned base = 0;
+    unsigned base = 0, n = 0;
 #pragma unroll
     for (int k = 0; k < kMaxLevels; ++k)
-        if (k == j) base = m.cum[k];
-    return item - base;
+        if (k == j) {
+            base = m.cum[k];
+            n = m.cnt[k];
+        }
+    const unsigned local = item - base;
+    return local < n ? local : ~0u;
 }
 
-// Item chunks of 256 are handed out in rounds of gridDim.x blocks; inside a
-// round, block b takes chunk xcd_remap(b, n), so each XCD works through one
-// contiguous run of chunks (consecutive items are neighbouring texels, and
-// their sample gathers then share that XCD's L2).  Returns the first item of
-// the block's chunk in round `base`, or ~0u when the block has none.
-__device__ __forceinline__ unsigned chunk_of(unsigned base, unsigned nchunks) {
-    const unsigned n = min(gridDim.x, nchunks - base);
-    if (blockIdx.x >= n) return ~0u;
-    return (base + xcd_remap(blockIdx.x, n)) * 256u;
+// Item chunks of 256 (neighbouring texels) are split into 8 contiguous
+// regions, one per XCD (block b runs on XCD b % 8); the blocks of an XCD
+// sweep its region in rounds, so that the depth rows its sample gathers touch
+// stay in that XCD's L2 from one round to the next.  Grids of fewer than 8
+// blocks stride over all chunks.
+struct ChunkRange {
+    unsigned first, end, step;
+};
+
+__device__ __forceinline__ ChunkRange chunk_range(unsigned nchunks) {
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    if (G < 8) return {b, nchunks, G};
+    const unsigned x = b & 7u, k = b >> 3;
+    const unsigned per = (G - x + 7u) >> 3;  // blocks of this XCD
+    const unsigned lo = (unsigned)((unsigned long long)nchunks * x / 8u);
+    const unsigned hi = (unsigned)((unsigned long long)nchunks * (x + 1u) / 8u);
+    return {lo + k, hi, per};
 }
 
 // Sample sets of at most this many entries are staged in LDS once per
@@ -155,11 +174,32 @@ __host__ inline bool fused_alpha(const EvalCommon& c) {
     return false;
 }
 
-// grid for a grid-stride evaluation pass over `total_hint` items at most
+// Blocks of 256 threads of `Kernel` that are resident on the device at once
+// (CUs x blocks per CU at the kernel's occupancy), queried once per kernel.
+template <auto Kernel>
+__host__ unsigned resident_blocks() {
+    static const unsigned n = [] {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(Kernel), 256, 0) !=
+                hipSuccess ||
+            cus <= 0 || per <= 0)
+            return 8192u;
+        return (unsigned)cus * (unsigned)per;
+    }();
+    return n;
+}
+
+// grid for a grid-stride evaluation pass over `total_hint` items at most:
+// one chunk of 256 items per block, at most one resident wave of blocks
+// (more blocks would only wait for a slot and repeat the per-block set-up)
+template <auto Kernel>
 __host__ inline unsigned eval_blocks(unsigned total_hint) {
     unsigned b = (total_hint + 255) / 256;
+    const unsigned cap = resident_blocks<Kernel>();
+    if (b > cap) b = cap;
     if (b < 1) b = 1;
-    if (b > 8192) b = 8192;
     return b;
 }
 

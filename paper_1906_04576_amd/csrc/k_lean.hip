@@ -368,12 +368,250 @@ __global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned ti
         *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
 }
 
+// ---------------------------------------------------------------------------
+// merge for the four consecutive levels 1, 2, 3, 4 (scales 1, 2, 4, 8): the
+// same arithmetic as k_lean_merge with the tap geometry fixed at compile
+// time.  A thread's four pixels start at a multiple of 4, so for scales 2 and
+// 4 their tap phases (fx) and column offsets are constants; a level's values
+// are staged once per tile, stencil membership is a > 0 (exact on this path)
+// and texels off the stencil are staged as 0, so that their products with
+// the tap weights are +0 and leave the sums unchanged.
+// ---------------------------------------------------------------------------
+template <int SH>
+__device__ __forceinline__ void taps4(int X, int n, int lo, int& ia, int& ib, float& f) {
+    constexpr int s = 1 << SH;
+    const int m = X - (s >> 1);
+    const int x0 = m >> SH;
+    f = ((float)(m & (s - 1)) + 0.5f) * (1.0f / (float)s);
+    ia = min(max(x0, 0), n - 1) - lo;
+    ib = min(max(x0 + 1, 0), n - 1) - lo;
+}
+
+// staged region of a level: (kMergeTW >> SH) + 2 columns, (kMergeTH >> SH) + 2 rows
+template <int SH>
+struct Region4 {
+    static constexpr int rw = (kMergeTW >> SH) + 2, rh = (kMergeTH >> SH) + 2, n = rw * rh;
+};
+
+// one list level (scale 2^SH) blended into out[][4] for the thread's pixels
+template <int SH, int C>
+__device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region4<SH>::n], const LeanMergeLevel& L,
+                                       int x0, int y0, int XQ, int Y, float (&out)[C][4]) {
+    constexpr int RW = Region4<SH>::rw;
+    int ya, yb;
+    float fy;
+    taps4<SH>(Y, L.H, (y0 >> SH) - 1, ya, yb, fy);
+    const float gy = 1.0f - fy;
+    const int r0 = ya * RW, r1 = yb * RW;
+    int ia[4], ib[4];
+    float fx[4], A[4];
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        taps4<SH>(XQ + k, L.W, (x0 >> SH) - 1, ia[k], ib[k], fx[k]);
+        const float gx = 1.0f - fx[k];
+        float s_ = (gx * gy) * la[r0 + ia[k]];
+        s_ = s_ + (fx[k] * gy) * la[r0 + ib[k]];
+        s_ = s_ + (gx * fy) * la[r1 + ia[k]];
+        s_ = s_ + (fx[k] * fy) * la[r1 + ib[k]];
+        A[k] = s_;
+        nz |= s_ != 0.0f;
+    }
+    if (!nz) return;  // A = 0: alpha = 0 at all four pixels
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float gx = 1.0f - fx[k];
+        const float b0 = gx * gy, b1 = fx[k] * gy, b2 = gx * fy, b3 = fx[k] * fy;
+        const int i00 = r0 + ia[k], i01 = r0 + ib[k], i10 = r1 + ia[k], i11 = r1 + ib[k];
+        float den = la[i00] > 0.0f ? b0 : 0.0f;
+        den = den + (la[i01] > 0.0f ? b1 : 0.0f);
+        den = den + (la[i10] > 0.0f ? b2 : 0.0f);
+        den = den + (la[i11] > 0.0f ? b3 : 0.0f);
+        const bool use = A[k] != 0.0f && den > 0.0f;
+        const float alpha = use ? fminf(A[k] * L.w, 1.0f) : 0.0f;
+        const float om = 1.0f - alpha;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float num = b0 * lc[c][i00];
+            num = num + b1 * lc[c][i01];
+            num = num + b2 * lc[c][i10];
+            num = num + b3 * lc[c][i11];
+            const float Ci = use ? (den == 1.0f ? num : num / den) : 0.0f;
+            out[c][k] = Ci * alpha + out[c][k] * om;
+        }
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
+    using R2 = Region4<1>;
+    using R3 = Region4<2>;
+    using R4 = Region4<3>;
+    __shared__ float la2[R2::n], la3[R3::n];
+    __shared__ float lc2[C][R2::n], lc3[C][R3::n], lc4[C][R4::n];
+    __shared__ int any2, any3;
+    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
+    const int x0 = (int)(tile % tiles_x) * kMergeTW;
+    const int y0 = (int)(tile / tiles_x) * kMergeTH;
+    const int t = threadIdx.x;
+    if (t == 0) any2 = any3 = 0;
+    __syncthreads();
+    // ---- stage levels 2, 3 (by rank, 0 off the stencil) and 4 (dense) ----
+    constexpr int kSlots = (R2::n + R3::n + R4::n + 255) / 256;
+    float av[kSlots], cv[kSlots][C];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int idx = t + 256 * j;
+        av[j] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) cv[j][c] = 0.0f;
+        if (idx >= R2::n + R3::n + R4::n) continue;
+        int lv, k, rw, sh;
+        if (idx < R2::n) {
+            lv = 1, k = idx, rw = R2::rw, sh = 1;
+        } else if (idx < R2::n + R3::n) {
+            lv = 2, k = idx - R2::n, rw = R3::rw, sh = 2;
+        } else {
+            lv = 3, k = idx - R2::n - R3::n, rw = R4::rw, sh = 3;
+        }
+        const LeanMergeLevel& L = a.lv[lv];
+        const int yy = k / rw, xx = k - yy * rw;
+        const int Xl = min(max((x0 >> sh) - 1 + xx, 0), L.W - 1);
+        const int Yl = min(max((y0 >> sh) - 1 + yy, 0), L.H - 1);
+        if (lv == 3) {
+            const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
+#pragma unroll
+            for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + p];
+        } else {
+            const unsigned wi = (unsigned)Yl * (unsigned)L.wpr + (unsigned)(Xl >> 5);
+            const unsigned word = L.Sb[wi];
+            const unsigned bit = (unsigned)Xl & 31u;
+            if ((word >> bit) & 1u) {
+                const unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
+                av[j] = L.ac[rank];
+#pragma unroll
+                for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + rank];
+            }
+        }
+    }
+    const int q = t & 15, row = t >> 4;
+    const int Y = y0 + row;
+    const int XQ = x0 + 4 * q;
+    const bool active = Y < a.H && XQ < a.W;
+    // ---- level 1: four pixels per thread, values by rank ----
+    float a1[4] = {0, 0, 0, 0}, c1[C][4];
+    unsigned nib = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) c1[c][0] = c1[c][1] = c1[c][2] = c1[c][3] = 0.0f;
+    if (active) {
+        const LeanMergeLevel& L = a.lv[0];
+        const unsigned wi = (unsigned)Y * (unsigned)L.wpr + (unsigned)(XQ >> 5);
+        const unsigned word = L.Sb[wi];
+        const unsigned bit = (unsigned)XQ & 31u;
+        nib = (word >> bit) & 0xFu;
+        if (nib) {
+            unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((nib >> k) & 1u) {
+                    a1[k] = L.ac[rank];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) c1[c][k] = L.c[c * L.c_plane + rank];
+                    ++rank;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int idx = t + 256 * j;
+        if (idx >= R2::n + R3::n + R4::n) continue;
+        if (idx < R2::n) {
+            la2[idx] = av[j];
+#pragma unroll
+            for (int c = 0; c < C; ++c) lc2[c][idx] = cv[j][c];
+            if (av[j] != 0.0f) any2 = 1;
+        } else if (idx < R2::n + R3::n) {
+            la3[idx - R2::n] = av[j];
+#pragma unroll
+            for (int c = 0; c < C; ++c) lc3[c][idx - R2::n] = cv[j][c];
+            if (av[j] != 0.0f) any3 = 1;
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) lc4[c][idx - R2::n - R3::n] = cv[j][c];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    float out[C][4];
+    {
+        // coarsest level (scale 8): plain bilinear, normalising sum exactly 1
+        const LeanMergeLevel& L = a.lv[3];
+        int ya, yb;
+        float fy;
+        taps4<3>(Y, L.H, (y0 >> 3) - 1, ya, yb, fy);
+        const float gy = 1.0f - fy;
+        const int r0 = ya * R4::rw, r1 = yb * R4::rw;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int xa, xb;
+            float fx;
+            taps4<3>(XQ + k, L.W, (x0 >> 3) - 1, xa, xb, fx);
+            const float gx = 1.0f - fx;
+            const float b0 = gx * gy, b1 = fx * gy, b2 = gx * fy, b3 = fx * fy;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float num = b0 * lc4[c][r0 + xa];
+                num = num + b1 * lc4[c][r0 + xb];
+                num = num + b2 * lc4[c][r1 + xa];
+                num = num + b3 * lc4[c][r1 + xb];
+                out[c][k] = num;
+            }
+        }
+    }
+    if (any3) blend4<2, C>(la3, lc3, a.lv[2], x0, y0, XQ, Y, out);
+    if (any2) blend4<1, C>(la2, lc2, a.lv[1], x0, y0, XQ, Y, out);
+    if (nib) {
+        const float w1 = a.lv[0].w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!((nib >> k) & 1u)) continue;  // alpha_1 = 0: out unchanged
+            const float alpha = fminf(a1[k] * w1, 1.0f);
+            const float om = 1.0f - alpha;
+#pragma unroll
+            for (int c = 0; c < C; ++c) out[c][k] = c1[c][k] * alpha + out[c][k] * om;
+        }
+    }
+    const unsigned p = (unsigned)Y * (unsigned)a.W + (unsigned)XQ;
+    const unsigned plane = (unsigned)a.W * (unsigned)a.H;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
+}
+
+// levels 1, 2, 3, 4 with level 1 by rank (the common 4-level frame)
+bool merge4_applies(const LeanMergeArgs& a) {
+    if (a.nlev != 4 || !a.fine1 || (a.W & 3) != 0) return false;
+    for (int j = 0; j < 4; ++j)
+        if (a.lv[j].sh != j) return false;
+    return true;
+}
+
 hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s) {
     const unsigned tx = (a.W + kMergeTW - 1) / kMergeTW, ty = (a.H + kMergeTH - 1) / kMergeTH;
-    if (a.C == 3)
-        hipLaunchKernelGGL(k_lean_merge<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
-    else
-        hipLaunchKernelGGL(k_lean_merge<1>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    const bool m4 = merge4_applies(a);
+    if (a.C == 3) {
+        if (m4)
+            hipLaunchKernelGGL(k_lean_merge4<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+        else
+            hipLaunchKernelGGL(k_lean_merge<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    } else {
+        if (m4)
+            hipLaunchKernelGGL(k_lean_merge4<1>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+        else
+            hipLaunchKernelGGL(k_lean_merge<1>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    }
     return hipGetLastError();
 }
 

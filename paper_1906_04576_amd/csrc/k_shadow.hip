@@ -101,15 +101,14 @@ template <bool LDS, bool AL>
 __device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds, const float* pds, const float* eg) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
-    const unsigned nchunks = (total + 255) / 256;
-    for (unsigned base = 0; base < nchunks; base += gridDim.x) {
-        const unsigned first = chunk_of(base, nchunks);
-        if (first == ~0u) break;
-        const unsigned item = first + threadIdx.x;
+    const ChunkRange cr = chunk_range((total + 255) / 256);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        const unsigned item = c * 256u + threadIdx.x;
         if (item >= total) continue;
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);
+        if (local == ~0u) continue;  // padding of the level's item range
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
@@ -145,9 +144,9 @@ __global__ __launch_bounds__(256) void k_pcss(ShadowArgs a) {
 
 hipError_t launch_shadow(const ShadowArgs& a, unsigned total_hint, hipStream_t s) {
     if (fused_alpha(a.c))
-        hipLaunchKernelGGL(k_pcss<true>, dim3(eval_blocks(total_hint)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_pcss<true>, dim3(eval_blocks<k_pcss<true>>(total_hint)), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_pcss<false>, dim3(eval_blocks(total_hint)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_pcss<false>, dim3(eval_blocks<k_pcss<false>>(total_hint)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -7,65 +7,134 @@
 
 namespace mr {
 
-// occlusion of one texel; K points to LDS (staged samples) or global memory
-template <typename NT, typename KP>
-__device__ __forceinline__ float ssao_texel(const SsaoArgs& a, const EvalLevel& L, const NT* nrm, unsigned plane,
-                                            KP K, int x, int y, float z) {
+// Occluding samples of one texel.  Branch-free: every sample computes its
+// projection and gathers (texel 0 when it is off-screen or behind the eye),
+// and counts only if all tests pass; the count is the same as skipping the
+// sample.  Samples go in groups of kSsaoGroup whose gathers are issued back
+// to back, so that several are in flight per wave.  FAST: 1/d by
+// recip_fast, which the caller has shown to equal 1.0f / d for every sample
+// of the texel.
+struct SsaoTexel {
+    float px, py, pz, z;
+    float rtx, rty, rtz, rbx, rby, rbz, rnx, rny, rnz;
+};
+
+constexpr int kSsaoGroup = 4;
+
+template <bool FAST, typename KP>
+__device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, const SsaoTexel& T, unsigned zpy,
+                                             unsigned zpx, bool& on, float& d, unsigned& off) {
+    const float Wf = (float)L.W, Hf = (float)L.H;
+    const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
+    const float qz = ((T.pz + kx * T.rtz) + ky * T.rbz) + kz * T.rnz;
+    d = -qz;
+    const float qx = ((T.px + kx * T.rtx) + ky * T.rbx) + kz * T.rnx;
+    const float qy = ((T.py + kx * T.rty) + ky * T.rby) + kz * T.rny;
+    const float inv = FAST ? recip_fast(d) : 1.0f / d;
+    const float u = L.cx + (qx * inv) * L.f;
+    const float v = L.cy - (qy * inv) * L.f;
+    on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
+    // u, v >= 0 when on, so truncation is floor; rows < 2^14 and pitches
+    // < 2^20 keep the offset products within 24 bits
+    const unsigned sx = (unsigned)(int)(on ? u : 0.0f), sy = (unsigned)(int)(on ? v : 0.0f);
+    off = __umul24(sy, zpy) + __umul24(sx, zpx);  // element offset
+}
+
+// GROUPED: gathers of a group of samples issued together, one projection
+// at a time (low register use, full occupancy: best when every SIMD has
+// many waves, as in the naive pass); else a plain unrolled loop that the
+// compiler interleaves (more instruction-level parallelism per wave: best
+// for the shorter multi-resolution launch, whose last waves run nearly alone)
+template <bool FAST, bool GROUPED, typename KP>
+__device__ __forceinline__ int ssao_count(const SsaoArgs& a, const EvalLevel& L, KP K, const SsaoTexel& T) {
     const float r = a.r, b = a.b;
     const int S = a.S;
-    const float* zb = L.z;
-    const int zpy = L.zpy, zpx = L.zpx;
+    // L is wave-uniform here: the depth plane is a buffer resource
+    const unsigned zpy = (unsigned)L.zpy, zpx = (unsigned)L.zpx;
+    const __amdgpu_buffer_rsrc_t rz =
+        buf_rsrc(L.z, ((unsigned)(L.H - 1) * zpy + (unsigned)(L.W - 1) * zpx + 1u) * 4u);
+    // z_s <= 0 must not count; +inf and NaN fail the depth test
+    auto occluded = [&](bool on, float d, float zs) {
+        return (on & (zs > 0.0f) & (zs < d - (b * d)) & (fabsf(T.z - zs) < r)) ? 1 : 0;
+    };
+    int occ = 0;
+    int s = 0;
+    if (!GROUPED) {
+#pragma unroll 4
+        for (; s < S; ++s) {
+            bool on;
+            float d;
+            unsigned off;
+            ssao_project<FAST>(L, K, s, T, zpy, zpx, on, d, off);
+            occ += occluded(on, d, L.z[off]);
+        }
+        return occ;
+    }
+    for (; s + kSsaoGroup <= S; s += kSsaoGroup) {
+        bool on[kSsaoGroup];
+        float d[kSsaoGroup], zs[kSsaoGroup];
+        unsigned off[kSsaoGroup];
+#pragma unroll
+        for (int k = 0; k < kSsaoGroup; ++k) {
+            ssao_project<FAST>(L, K, s + k, T, zpy, zpx, on[k], d[k], off[k]);
+            // one projection at a time: interleaving them buys little ILP
+            // and costs registers (occupancy)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int k = 0; k < kSsaoGroup; ++k) zs[k] = buf_f1(rz, off[k] * 4u);
+#pragma unroll
+        for (int k = 0; k < kSsaoGroup; ++k) occ += occluded(on[k], d[k], zs[k]);
+    }
+    for (; s < S; ++s) {
+        bool on;
+        float d;
+        unsigned off;
+        ssao_project<FAST>(L, K, s, T, zpy, zpx, on, d, off);
+        occ += occluded(on, d, buf_f1(rz, off * 4u));
+    }
+    return occ;
+}
+
+// occlusion of one texel; K points to LDS (staged samples) or global memory;
+// kmax = the largest |component| over the samples (+inf when unknown)
+template <typename NT, bool GROUPED, typename KP>
+__device__ __forceinline__ float ssao_texel(const SsaoArgs& a, const EvalLevel& L, const NT* nrm, unsigned plane,
+                                            KP K, float kmax, int x, int y, float z) {
+    const float r = a.r;
     const unsigned g = (unsigned)L.goff + (unsigned)y * (unsigned)L.gpy + (unsigned)x * (unsigned)L.gpx;
     const float nx = ld(nrm, g), ny = ld(nrm, plane + g), nz = ld(nrm, 2 * plane + g);
-    float px, py, pz;
-    view_pos(x, y, z, L.f, L.cx, L.cy, px, py, pz);
+    SsaoTexel T;
+    T.z = z;
+    view_pos(x, y, z, L.f, L.cx, L.cy, T.px, T.py, T.pz);
     float tx, ty, tz, bx, by, bz;
     onb(nx, ny, nz, tx, ty, tz, bx, by, bz);
-    const float rtx = r * tx, rty = r * ty, rtz = r * tz;
-    const float rbx = r * bx, rby = r * by, rbz = r * bz;
-    const float rnx = r * nx, rny = r * ny, rnz = r * nz;
-    const float Wf = (float)L.W, Hf = (float)L.H;
-    const float f = L.f, cx = L.cx, cy = L.cy;
-    // Branch-free sample loop: every sample computes its projection and
-    // gathers (texel 0 when it is off-screen or behind the eye), and counts
-    // only if all tests pass; the count is the same as skipping the sample,
-    // and the unrolled body keeps several gathers in flight per wave.
-    int occ = 0;
-#pragma unroll 4
-    for (int s = 0; s < S; ++s) {
-        const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
-        const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
-        const float d = -qz;
-        const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
-        const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
-        const float inv = 1.0f / d;
-        const float u = cx + (qx * inv) * f;
-        const float v = cy - (qy * inv) * f;
-        const bool on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
-        // u, v >= 0 when on, so truncation is floor
-        const int sx = (int)(on ? u : 0.0f), sy = (int)(on ? v : 0.0f);
-        const float zs = zb[(unsigned)sy * zpy + (unsigned)sx * zpx];
-        // z_s <= 0 must not count; +inf and NaN fail the depth test
-        occ += (on & (zs > 0.0f) & (zs < d - (b * d)) & (fabsf(z - zs) < r)) ? 1 : 0;
-    }
-    return (float)occ / (float)S;
+    T.rtx = r * tx, T.rty = r * ty, T.rtz = r * tz;
+    T.rbx = r * bx, T.rby = r * by, T.rbz = r * bz;
+    T.rnx = r * nx, T.rny = r * ny, T.rnz = r * nz;
+    // Every sample's d = z - (kx rtz + ky rbz + kz rnz) (rounded) lies within
+    // B0 = kmax (|rtz| + |rbz| + |rnz|) of z, up to a relative 2^-21; with
+    // these margins all d are in [2^-126, 2^126), where recip_fast is exact.
+    const float B0 = kmax * ((fabsf(T.rtz) + fabsf(T.rbz)) + fabsf(T.rnz));
+    const bool safe = (z * 0.999f > B0 * 1.001f + 1e-37f) && ((z + B0) * 1.001f < 0x1p125f);
+    const int occ = __ballot(!safe) == 0 ? ssao_count<true, GROUPED>(a, L, K, T) : ssao_count<false, GROUPED>(a, L, K, T);
+    return (float)occ / (float)a.S;
 }
 
 template <typename NT, bool KLDS, bool AL>
-__device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, const float* eg) {
+__device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, const float* eg, float kmax) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
     const NT* nrm = static_cast<const NT*>(a.c.normal);
     const unsigned plane = (unsigned)a.c.plane;
-    const unsigned nchunks = (total + 255) / 256;
-    for (unsigned base = 0; base < nchunks; base += gridDim.x) {
-        const unsigned first = chunk_of(base, nchunks);
-        if (first == ~0u) break;
-        const unsigned item = first + threadIdx.x;
+    const ChunkRange cr = chunk_range((total + 255) / 256);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        const unsigned item = c * 256u + threadIdx.x;
         if (item >= total) continue;
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);
+        if (local == ~0u) continue;  // padding of the level's item range
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
@@ -74,43 +143,63 @@ __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, c
         float res = 0.0f;
         if (valid_depth(z)) {
             if (KLDS)
-                res = ssao_texel<NT>(a, L, nrm, plane, ks, x, y, z);
+                res = ssao_texel<NT, !AL>(a, L, nrm, plane, ks, kmax, x, y, z);
             else
-                res = ssao_texel<NT>(a, L, nrm, plane, a.kernel, x, y, z);
+                res = ssao_texel<NT, !AL>(a, L, nrm, plane, a.kernel, kmax, x, y, z);
         }
         L.out[L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x] = res;
     }
 }
 
-template <typename NT, bool AL>
+// KLDS: the S <= kLdsSamples samples are staged in LDS (else read from
+// global memory); separate instances keep the common one's register budget.
+template <typename NT, bool AL, bool KLDS>
 __global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
-    __shared__ float ks[3 * kLdsSamples];
+    __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
+    __shared__ unsigned kmax_bits;  // max |component| of the staged samples (as bits: all >= 0)
     if (AL) stage_taps(a.c, eg);
-    if (a.S <= kLdsSamples) {
-        for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
+    if (KLDS) {
+        if (threadIdx.x == 0) kmax_bits = 0u;
         __syncthreads();
-        ssao_items<NT, true, AL>(a, ks, eg);
+        unsigned m = 0u;
+        for (int i = threadIdx.x; i < 3 * a.S; i += 256) {
+            const float v = a.kernel[i];
+            ks[i] = v;
+            m = max(m, __float_as_uint(fabsf(v)));
+        }
+        for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+        if (__lane_id() == 0) atomicMax(&kmax_bits, m);
+        __syncthreads();
+        ssao_items<NT, true, AL>(a, ks, eg, __uint_as_float(kmax_bits));
     } else {
         __syncthreads();
-        ssao_items<NT, false, AL>(a, ks, eg);
+        ssao_items<NT, false, AL>(a, ks, eg, __builtin_inff());
     }
 }
 
 hipError_t launch_ssao(const SsaoArgs& a, int normal_dtype, unsigned total_hint, hipStream_t s) {
-    const unsigned nb = eval_blocks(total_hint);
-    const bool al = fused_alpha(a.c);
+    const bool al = fused_alpha(a.c), lds = a.S <= kLdsSamples;
+#define MR_SSAO(NT, AL, KL) \
+    hipLaunchKernelGGL((k_ssao<NT, AL, KL>), dim3(eval_blocks<k_ssao<NT, AL, KL>>(total_hint)), dim3(256), 0, s, a)
     if (normal_dtype == MR_F16) {
-        if (al)
-            hipLaunchKernelGGL((k_ssao<_Float16, true>), dim3(nb), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_ssao<_Float16, false>), dim3(nb), dim3(256), 0, s, a);
+        if (al) {
+            if (lds) MR_SSAO(_Float16, true, true);
+            else MR_SSAO(_Float16, true, false);
+        } else {
+            if (lds) MR_SSAO(_Float16, false, true);
+            else MR_SSAO(_Float16, false, false);
+        }
     } else {
-        if (al)
-            hipLaunchKernelGGL((k_ssao<float, true>), dim3(nb), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_ssao<float, false>), dim3(nb), dim3(256), 0, s, a);
+        if (al) {
+            if (lds) MR_SSAO(float, true, true);
+            else MR_SSAO(float, true, false);
+        } else {
+            if (lds) MR_SSAO(float, false, true);
+            else MR_SSAO(float, false, false);
+        }
     }
+#undef MR_SSAO
     return hipGetLastError();
 }
 

@@ -21,15 +21,14 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
     const float rmin = 0.1f * r;
     const float rmin2 = rmin * rmin;
     const float scale = (r * r) / (float)S;
-    const unsigned nchunks = (total + 255) / 256;
-    for (unsigned base = 0; base < nchunks; base += gridDim.x) {
-        const unsigned first = chunk_of(base, nchunks);
-        if (first == ~0u) break;
-        const unsigned item = first + threadIdx.x;
+    const ChunkRange cr = chunk_range((total + 255) / 256);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        const unsigned item = c * 256u + threadIdx.x;
         if (item >= total) continue;
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);
+        if (local == ~0u) continue;  // padding of the level's item range
         const unsigned t = L.list ? L.list[local] : local;
         if (t >= L.dense_n) continue;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
@@ -54,7 +53,7 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
                 const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
                 const float d = -qz;
                 if (!(d > 0.0f)) continue;
-                const float inv = 1.0f / d;
+                const float inv = recip_pos(d);  // = 1.0f / d (d > 0)
                 const float u = L.cx + (qx * inv) * L.f;
                 const float v = L.cy - (qy * inv) * L.f;
                 if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
@@ -68,7 +67,7 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
                 const float dd = ((vx * vx) + (vy * vy)) + (vz * vz);
                 if (!(dd > 0.0f)) continue;
                 const float dist2 = fmaxf(dd, rmin2);
-                const float il = 1.0f / sqrtf(dd);
+                const float il = rsqrt_pos(dd);  // = 1.0f / sqrtf(dd) (dd > 0)
                 const float vhx = vx * il, vhy = vy * il, vhz = vz * il;
                 const long long gt = L.goff + (long long)sy * L.gpy + (long long)sx * L.gpx;
                 const float mx = ld(nrm, gt), my = ld(nrm, plane + gt), mz = ld(nrm, 2 * plane + gt);
@@ -104,14 +103,15 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
 
 hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
                        hipStream_t s) {
-    const unsigned nb = eval_blocks(total_hint);
     const bool al = fused_alpha(a.c);
-#define MR_SSGI(NT, CT)                                                                  \
-    do {                                                                                 \
-        if (al)                                                                          \
-            hipLaunchKernelGGL((k_ssgi<NT, CT, true>), dim3(nb), dim3(256), 0, s, a);  \
-        else                                                                             \
-            hipLaunchKernelGGL((k_ssgi<NT, CT, false>), dim3(nb), dim3(256), 0, s, a); \
+#define MR_SSGI(NT, CT)                                                                                   \
+    do {                                                                                                  \
+        if (al)                                                                                           \
+            hipLaunchKernelGGL((k_ssgi<NT, CT, true>), dim3(eval_blocks<k_ssgi<NT, CT, true>>(total_hint)), \
+                               dim3(256), 0, s, a);                                                       \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_ssgi<NT, CT, false>),                                                   \
+                               dim3(eval_blocks<k_ssgi<NT, CT, false>>(total_hint)), dim3(256), 0, s, a); \
     } while (0)
     if (normal_dtype == MR_F16 && color_dtype == MR_F16)
         MR_SSGI(_Float16, _Float16);

@@ -46,6 +46,12 @@ CASES = {
                     (-1, 11, 16, -1)),
     "1080p": (1920, 1080, 200, 50, 1, 0, 4, 0b1111, (0.924, 1.848, 3.696, 0), (100, 50, 20, 1), 32, 1.0,
               (-1, -1, -1, -1)),
+    # compact frame path (width divisible by 128) with ragged merge tiles
+    # (heights not divisible by 16) and a ragged last column of edge tiles
+    "lean_640x360": (640, 360, 60, 15, 8, 5, 4, 0b1111, (0.924, 1.848, 3.696, 0), (100, 50, 20, 1), 16, 1.0,
+                     (-1, -1, -1, -1)),
+    "lean_384x200": (384, 200, 40, 10, 9, 2, 4, 0b1111, (0.924, 1.848, 3.696, 0), (100, 50, 20, 1), 16, 0.8,
+                     (-1, -1, -1, -1)),
 }
 
 _cache = {}
@@ -144,7 +150,8 @@ def test_ssao_levels_and_merge(name):
 
 # 256_3lv, skip_level2 (width 320 -> dense), wide_radius (radius > 8 -> dense), 1080p:
 # mr_frame takes the bit-packed path where it is eligible and the dense one elsewhere
-@pytest.mark.parametrize("name", ["256_3lv", "ragged_200x120", "skip_level2", "wide_radius", "1080p"])
+@pytest.mark.parametrize("name", ["256_3lv", "ragged_200x120", "skip_level2", "wide_radius", "1080p", "lean_640x360",
+                                  "lean_384x200"])
 def test_plain_and_frame(name):
     log(f"[gpu] plain + frame {name}")
     c = case(name)
@@ -276,6 +283,20 @@ def test_stage_events(multires):
     assert torch.equal(out, ref)
     t = [dv[k].elapsed_ms(dv[k + 1]) for k in range(3)]
     assert all(x >= 0 for x in t) and t[1] > 0
+
+
+def test_fast_reciprocal_is_exact_over_its_range():
+    """The evaluators replace the IEEE division 1/d by the hardware reciprocal
+    and one Newton-Raphson step on [2^-126, 2^126); every float there must
+    give the same bits (native program built with the library's flags)."""
+    import os
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "native", "_bin", "recip_check")
+    assert os.path.exists(exe), "tests/native programs are not built (run __graft_entry__.build())"
+    log("[gpu] recip_check (exhaustive)")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    log(r.stdout.strip())
+    assert r.returncode == 0 and "mismatches 0" in r.stdout, r.stdout + r.stderr
 
 
 def test_errors_enqueue_nothing():
