@@ -51,23 +51,35 @@ __device__ __forceinline__ TileWord tile_word(const LeanLevel& L, unsigned b, un
     return r;
 }
 
-// one stencil word (dilated edge bits); the radius is a template parameter
-// so that all rows' words are loaded in one batch
+// Stencil words of one ranking tile (dilated edge bits), separably: the
+// tile's edge words plus a halo of R rows and one word on each side are
+// staged in LDS, dilated horizontally per row, then ORed over 2R + 1 rows.
+// Words outside the level are 0 (no edges), as the blur's zero padding.
+constexpr int kStageCols = kLeanTileWords + 2, kStageRows = kLeanTileRows + 2 * kBlurFusedMaxRadiusC;
+
 template <int R>
-__device__ __forceinline__ unsigned stencil_word(const LeanLevel& L, int y, int xw) {
-    unsigned c[2 * R + 1], p[2 * R + 1], n[2 * R + 1];
-#pragma unroll
-    for (int k = 0; k <= 2 * R; ++k) {
-        const int yy = y - R + k;
-        const bool ok = yy >= 0 && yy < L.H;
-        const uint32_t* row = L.Eb + (unsigned)(ok ? yy : 0) * (unsigned)L.wpr;
-        c[k] = ok ? row[xw] : 0u;
-        p[k] = (ok && xw > 0) ? row[xw - 1] : 0u;
-        n[k] = (ok && xw + 1 < L.wpr) ? row[xw + 1] : 0u;
+__device__ __forceinline__ unsigned stencil_tile(const LeanLevel& L, unsigned b, unsigned (*eb)[kStageCols],
+                                                 unsigned (*hd)[kLeanTileWords]) {
+    const unsigned bl = b - L.blk_base;
+    const unsigned ty = bl / (unsigned)L.tiles_x, tx = bl - ty * (unsigned)L.tiles_x;
+    const int yw0 = (int)(ty * kLeanTileRows) - R, xw0 = (int)(tx * kLeanTileWords) - 1;
+    constexpr int rows = kLeanTileRows + 2 * R, n = rows * kStageCols;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int r = i / kStageCols, c = i - r * kStageCols;
+        const int y = yw0 + r, xw = xw0 + c;
+        eb[r][c] = (y >= 0 && y < L.H && xw >= 0 && xw < L.wpr) ? L.Eb[(unsigned)y * (unsigned)L.wpr + (unsigned)xw]
+                                                                : 0u;
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < rows * kLeanTileWords; i += 256) {
+        const int r = i / kLeanTileWords, c = i - r * kLeanTileWords;
+        hd[r][c] = hdilate(eb[r][c], eb[r][c + 1], eb[r][c + 2], R);
+    }
+    __syncthreads();
+    const int c = threadIdx.x % kLeanTileWords, r0 = threadIdx.x / kLeanTileWords;
     unsigned acc = 0;
 #pragma unroll
-    for (int k = 0; k <= 2 * R; ++k) acc |= hdilate(p[k], c[k], n[k], R);
+    for (int k = 0; k <= 2 * R; ++k) acc |= hd[r0 + k][c];
     return acc;
 }
 
@@ -93,18 +105,19 @@ __global__ __launch_bounds__(256) void k_lean_rank(LeanArgs A) {
     const unsigned b = blockIdx.x;
     const int l = lean_level(A, b);
     const LeanLevel& L = A.lv[l];
+    __shared__ unsigned eb[kStageRows][kStageCols];
+    __shared__ unsigned hd[kStageRows][kLeanTileWords];
     const TileWord tw = tile_word(L, b, threadIdx.x);
     unsigned acc = 0;
-    if (tw.ok) {
-        switch (L.r) {
+    switch (L.r) {  // uniform: every thread takes part in the staging
 #define MR_STENCIL(R) \
-    case R: acc = stencil_word<R>(L, tw.y, tw.xw); break;
-            MR_STENCIL(0) MR_STENCIL(1) MR_STENCIL(2) MR_STENCIL(3) MR_STENCIL(4) MR_STENCIL(5) MR_STENCIL(6)
-            MR_STENCIL(7) MR_STENCIL(8)
+    case R: acc = stencil_tile<R>(L, b, eb, hd); break;
+        MR_STENCIL(0) MR_STENCIL(1) MR_STENCIL(2) MR_STENCIL(3) MR_STENCIL(4) MR_STENCIL(5) MR_STENCIL(6)
+        MR_STENCIL(7) MR_STENCIL(8)
 #undef MR_STENCIL
-            default: break;
-        }
+        default: break;
     }
+    if (!tw.ok) acc = 0u;
     const unsigned cnt = __popc(acc);
     const unsigned inc = wave_scan_incl(cnt);
     const int wv = threadIdx.x >> 6;

@@ -282,6 +282,21 @@ struct NormalRow<_Float16> {
     }
 };
 
+// Row shifts within the 16-lane DPP rows: lane i takes src of lane i - 1
+// (shr) or i + 1 (shl); the lane with no source in its row keeps `own`.
+__device__ __forceinline__ unsigned dpp_shr1u(unsigned own, unsigned src) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)own, (int)src, 0x111, 0xF, 0xF, false);
+}
+__device__ __forceinline__ unsigned dpp_shl1u(unsigned own, unsigned src) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)own, (int)src, 0x101, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float dpp_shr1(float own, float src) {
+    return __builtin_bit_cast(float, dpp_shr1u(__builtin_bit_cast(unsigned, own), __builtin_bit_cast(unsigned, src)));
+}
+__device__ __forceinline__ float dpp_shl1(float own, float src) {
+    return __builtin_bit_cast(float, dpp_shl1u(__builtin_bit_cast(unsigned, own), __builtin_bit_cast(unsigned, src)));
+}
+
 // WIDE: the four waves of a block sit side by side (256 x 8 pixel tile), so
 // that a block reads 1 KB runs of every row; levels up to 4 only (the 8 x 8
 // pooling blocks stay inside one wave).  Otherwise they are stacked (64 x 32
@@ -310,7 +325,11 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
     unsigned ro[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ro[r] = (unsigned)min(max(yb - 1 + r, 0), H - 1) * (unsigned)W;
-    const unsigned xl = (unsigned)max(xb - 1, 0), xr = (unsigned)min(xb + 4, W - 1);
+    // Side columns xb - 1 and xb + 4 are the neighbouring lanes' pixels (the
+    // 16 lanes of a DPP row cover the wave's 64 columns of one row pair);
+    // only the wave's outer columns x0 - 1 and x0 + 64 are loaded, by every
+    // lane of the row from the same address (one cache line).
+    const unsigned xl = (unsigned)max(x0 - 1, 0), xr = (unsigned)min(x0 + 64, W - 1);
 
     float z[4][4], n[4][4][3];
     float zs[2][2], ns[2][2][3];
@@ -345,6 +364,19 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
             ns[r][sd][1] = NormalRow<NT>::load1(rn1, e);
             ns[r][sd][2] = NormalRow<NT>::load1(rn2, e);
             if (HARD) hside[r][sd] = __builtin_amdgcn_raw_buffer_load_b8(rh, e, 0, 0);
+        }
+        // lane cg takes column xb - 1 from lane cg - 1 and xb + 4 from lane
+        // cg + 1; lanes 0 and 15 of the row keep the loaded outer columns
+        zs[r][0] = dpp_shr1(zs[r][0], z[r + 1][3]);
+        zs[r][1] = dpp_shl1(zs[r][1], z[r + 1][0]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ns[r][0][c] = dpp_shr1(ns[r][0][c], n[r + 1][3][c]);
+            ns[r][1][c] = dpp_shl1(ns[r][1][c], n[r + 1][0][c]);
+        }
+        if (HARD) {
+            hside[r][0] = dpp_shr1u(hside[r][0], (hrow[r + 1] >> 24) & 0xFFu);
+            hside[r][1] = dpp_shl1u(hside[r][1], hrow[r + 1] & 0xFFu);
         }
     }
     // normal pair tests, each pair once
