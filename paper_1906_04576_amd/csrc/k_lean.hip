@@ -400,6 +400,28 @@ __device__ __forceinline__ void taps4(int X, int n, int lo, int& ia, int& ib, fl
     ib = min(max(x0 + 1, 0), n - 1) - lo;
 }
 
+// The x taps of a thread's four pixels X = XQ + k (XQ a multiple of 4) at
+// scale s = 2^SH, with m = X - s/2, x0 = m >> SH, fx = ((m & (s-1)) + 0.5)/s:
+//   s = 2: k = 0..3 -> x0 = XQ/2 - 1, XQ/2, XQ/2, XQ/2 + 1; fx = 3/4, 1/4, 3/4, 1/4
+//   s = 4: x0 = XQ/4 - 1, XQ/4 - 1, XQ/4, XQ/4; fx = 5/8, 7/8, 1/8, 3/8
+//   s = 8: x0 = XQ/8 - 1 (all k) and fx = (4.5 + k)/8 when XQ % 8 = 0,
+//          x0 = XQ/8 and fx = (0.5 + k)/8 when XQ % 8 = 4.
+// So the four pixels read at most 4 distinct tap columns: col[j] = x-tap
+// base + j (clamped to the level, relative to the staged region), and
+// pixel k uses columns cofs(k) and cofs(k) + 1.
+template <int SH>
+struct XTaps4 {
+    static constexpr int ncol = SH == 1 ? 4 : (SH == 2 ? 3 : 2);
+    __device__ static constexpr int cofs(int k) { return SH == 1 ? (k + 1) / 2 : (SH == 2 ? k / 2 : 0); }
+    __device__ static float fx(int k, int XQ) {
+        if (SH == 1) return (k & 1) ? 0.25f : 0.75f;
+        if (SH == 2) return (float)(2 * ((k + 2) & 3) + 1) * 0.125f;
+        return (XQ & 4) ? (0.5f + (float)k) * 0.125f : (4.5f + (float)k) * 0.125f;
+    }
+    // first tap column (level texels, before clamping)
+    __device__ static int base(int XQ) { return SH == 3 ? ((XQ & 4) ? XQ >> 3 : (XQ >> 3) - 1) : (XQ >> SH) - 1; }
+};
+
 // staged region of a level: (kMergeTW >> SH) + 2 columns, (kMergeTH >> SH) + 2 rows
 template <int SH>
 struct Region4 {
@@ -410,45 +432,62 @@ struct Region4 {
 template <int SH, int C>
 __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region4<SH>::n], const LeanMergeLevel& L,
                                        int x0, int y0, int XQ, int Y, float (&out)[C][4]) {
+    using XT = XTaps4<SH>;
     constexpr int RW = Region4<SH>::rw;
     int ya, yb;
     float fy;
     taps4<SH>(Y, L.H, (y0 >> SH) - 1, ya, yb, fy);
     const float gy = 1.0f - fy;
     const int r0 = ya * RW, r1 = yb * RW;
-    int ia[4], ib[4];
-    float fx[4], A[4];
+    const int lo = (x0 >> SH) - 1, xb0 = XT::base(XQ);
+    int col[XT::ncol];
+    float a0[XT::ncol], a1[XT::ncol];
+#pragma unroll
+    for (int j = 0; j < XT::ncol; ++j) {
+        col[j] = min(max(xb0 + j, 0), L.W - 1) - lo;
+        a0[j] = la[r0 + col[j]];
+        a1[j] = la[r1 + col[j]];
+    }
+    float A[4];
     bool nz = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        taps4<SH>(XQ + k, L.W, (x0 >> SH) - 1, ia[k], ib[k], fx[k]);
-        const float gx = 1.0f - fx[k];
-        float s_ = (gx * gy) * la[r0 + ia[k]];
-        s_ = s_ + (fx[k] * gy) * la[r0 + ib[k]];
-        s_ = s_ + (gx * fy) * la[r1 + ia[k]];
-        s_ = s_ + (fx[k] * fy) * la[r1 + ib[k]];
+        const int ja = XT::cofs(k), jb = ja + 1;
+        const float fx = XT::fx(k, XQ), gx = 1.0f - fx;
+        float s_ = (gx * gy) * a0[ja];
+        s_ = s_ + (fx * gy) * a0[jb];
+        s_ = s_ + (gx * fy) * a1[ja];
+        s_ = s_ + (fx * fy) * a1[jb];
         A[k] = s_;
         nz |= s_ != 0.0f;
     }
     if (!nz) return;  // A = 0: alpha = 0 at all four pixels
+    float v0[C][XT::ncol], v1[C][XT::ncol];
+#pragma unroll
+    for (int j = 0; j < XT::ncol; ++j)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            v0[c][j] = lc[c][r0 + col[j]];
+            v1[c][j] = lc[c][r1 + col[j]];
+        }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float gx = 1.0f - fx[k];
-        const float b0 = gx * gy, b1 = fx[k] * gy, b2 = gx * fy, b3 = fx[k] * fy;
-        const int i00 = r0 + ia[k], i01 = r0 + ib[k], i10 = r1 + ia[k], i11 = r1 + ib[k];
-        float den = la[i00] > 0.0f ? b0 : 0.0f;
-        den = den + (la[i01] > 0.0f ? b1 : 0.0f);
-        den = den + (la[i10] > 0.0f ? b2 : 0.0f);
-        den = den + (la[i11] > 0.0f ? b3 : 0.0f);
+        const int ja = XT::cofs(k), jb = ja + 1;
+        const float fx = XT::fx(k, XQ), gx = 1.0f - fx;
+        const float b0 = gx * gy, b1 = fx * gy, b2 = gx * fy, b3 = fx * fy;
+        float den = a0[ja] > 0.0f ? b0 : 0.0f;
+        den = den + (a0[jb] > 0.0f ? b1 : 0.0f);
+        den = den + (a1[ja] > 0.0f ? b2 : 0.0f);
+        den = den + (a1[jb] > 0.0f ? b3 : 0.0f);
         const bool use = A[k] != 0.0f && den > 0.0f;
         const float alpha = use ? fminf(A[k] * L.w, 1.0f) : 0.0f;
         const float om = 1.0f - alpha;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            float num = b0 * lc[c][i00];
-            num = num + b1 * lc[c][i01];
-            num = num + b2 * lc[c][i10];
-            num = num + b3 * lc[c][i11];
+            float num = b0 * v0[c][ja];
+            num = num + b1 * v0[c][jb];
+            num = num + b2 * v1[c][ja];
+            num = num + b3 * v1[c][jb];
             const float Ci = use ? (den == 1.0f ? num : num / den) : 0.0f;
             out[c][k] = Ci * alpha + out[c][k] * om;
         }
@@ -560,25 +599,25 @@ __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned t
     float out[C][4];
     {
         // coarsest level (scale 8): plain bilinear, normalising sum exactly 1
+        using XT = XTaps4<3>;
         const LeanMergeLevel& L = a.lv[3];
         int ya, yb;
         float fy;
         taps4<3>(Y, L.H, (y0 >> 3) - 1, ya, yb, fy);
         const float gy = 1.0f - fy;
         const int r0 = ya * R4::rw, r1 = yb * R4::rw;
+        const int lo = (x0 >> 3) - 1, xb0 = XT::base(XQ);
+        const int ca = min(max(xb0, 0), L.W - 1) - lo, cb = min(max(xb0 + 1, 0), L.W - 1) - lo;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            int xa, xb;
-            float fx;
-            taps4<3>(XQ + k, L.W, (x0 >> 3) - 1, xa, xb, fx);
-            const float gx = 1.0f - fx;
-            const float b0 = gx * gy, b1 = fx * gy, b2 = gx * fy, b3 = fx * fy;
+        for (int c = 0; c < C; ++c) {
+            const float v00 = lc4[c][r0 + ca], v01 = lc4[c][r0 + cb], v10 = lc4[c][r1 + ca], v11 = lc4[c][r1 + cb];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                float num = b0 * lc4[c][r0 + xa];
-                num = num + b1 * lc4[c][r0 + xb];
-                num = num + b2 * lc4[c][r1 + xa];
-                num = num + b3 * lc4[c][r1 + xb];
+            for (int k = 0; k < 4; ++k) {
+                const float fx = XT::fx(k, XQ), gx = 1.0f - fx;
+                float num = (gx * gy) * v00;
+                num = num + (fx * gy) * v01;
+                num = num + (gx * fy) * v10;
+                num = num + (fx * fy) * v11;
                 out[c][k] = num;
             }
         }
