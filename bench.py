@@ -36,7 +36,7 @@ SSAO_OPS_PER_TEXEL = 40         # per evaluated texel outside the sample loop
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (profiles/), scaled by the copy-kernel calibration;
 # None until measured for the current kernel
-TRAFFIC_BYTES = {"k_ssao_multi": 213443683}
+TRAFFIC_BYTES = {"k_ssao_multi": 87630895}
 
 
 def log(*a):
@@ -238,7 +238,7 @@ def main():
         # dominant kernel of the multi-resolution frame: the per-level SSAO
         # evaluation, one launch per frame bracketed by events [1] and [2]
         achieved = ops_multi / t_eval / 1e12
-        roofline = {"kernel": "k_ssao<float, true> (all levels of one frame in one launch)", "bound": "alu",
+        roofline = {"kernel": "k_ssao<float, true, true> (all levels of one frame in one launch)", "bound": "alu",
                     "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi"),
                     "launch_ms": stages["multi_eval_ms"]}
