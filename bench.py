@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--cameras", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="also report throughput with frames spread over this many streams (1 = off)")
     ap.add_argument("--no-quality", action="store_true", help="profile helper: skip the multi vs naive comparison")
     ap.add_argument("--plain", action="store_true", help="profile helper: time only the naive pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -132,6 +134,25 @@ def main():
         lat = np.array([a.elapsed_ms(b) for a, b in ev])
         return wall, lat
 
+    def concurrent(multires, streams, steps):
+        """Throughput with frames spread round robin over `streams` HIP
+        streams (one workspace each), so that one frame's memory-bound stages
+        overlap another's evaluation; reported beside the one-stream figure."""
+        ss = [torch.cuda.Stream() for _ in range(streams)]
+        nws = mr.mr_workspace_bytes(W, H, focal, mp, mr.MR_EFFECT_SSAO) if multires else 256
+        wss = [torch.empty(nws, dtype=torch.uint8, device=dev) for _ in range(streams)]
+        outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(streams)]
+        rs = [[mr.FrameRunner("ssao", f["d"], f["n"], focal, mp, multires, params=sp, workspace=wss[j], out=outs[j])
+               for f in frames] for j in range(streams)]
+        for k in range(streams * 4):
+            rs[k % streams][k % nf](ss[k % streams])
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(steps):
+            rs[k % streams][k % nf](ss[k % streams])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t_start) / steps
+
     if args.plain:
         wall, lat = timed(plain, args.steps, args.warmup)
         log(f"[bench] plain {args.steps} frames {wall * 1e3 / args.steps:.3f} ms/frame")
@@ -145,6 +166,13 @@ def main():
     npx = W * H
     value = npx * args.steps / wall_m / 1e6
     plain_mpx = npx * args.steps / wall_p / 1e6
+    conc = None
+    if args.streams > 1:
+        tm2 = concurrent(True, args.streams, args.steps)
+        tp2 = concurrent(False, args.streams, args.steps)
+        conc = {"streams": args.streams, "mpixels_s": round(npx / tm2 / 1e6, 2),
+                "plain_mpixels_s": round(npx / tp2 / 1e6, 2), "speedup_vs_plain": round(tp2 / tm2, 3)}
+        log(f"[bench] {args.streams} streams: multi-res {tm2 * 1e3:.3f} ms/frame, plain {tp2 * 1e3:.3f} ms/frame")
 
     # ---------------- quality: multi-res vs naive on every configuration ----------------
     mads, rmss = [], []
@@ -292,6 +320,7 @@ def main():
         "plain_p99_ms": round(float(np.percentile(lat_p, 99)), 4),
         "mad_vs_plain": round(float(np.mean(mads)), 6) if mads else None,
         "rms_vs_plain": round(float(np.mean(rmss)), 6) if rmss else None,
+        "concurrent": conc,
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

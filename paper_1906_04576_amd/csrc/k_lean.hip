@@ -448,8 +448,13 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
         a0[j] = la[r0 + col[j]];
         a1[j] = la[r1 + col[j]];
     }
+    // a >= 0 and every tap weight > 0, so A = 0 at all four pixels (alpha = 0,
+    // out unchanged) exactly when all their tap values are +0
+    unsigned any = 0u;
+#pragma unroll
+    for (int j = 0; j < XT::ncol; ++j) any |= __float_as_uint(a0[j]) | __float_as_uint(a1[j]);
+    if (!any) return;
     float A[4];
-    bool nz = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int ja = XT::cofs(k), jb = ja + 1;
@@ -459,9 +464,7 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
         s_ = s_ + (gx * fy) * a1[ja];
         s_ = s_ + (fx * fy) * a1[jb];
         A[k] = s_;
-        nz |= s_ != 0.0f;
     }
-    if (!nz) return;  // A = 0: alpha = 0 at all four pixels
     float v0[C][XT::ncol], v1[C][XT::ncol];
 #pragma unroll
     for (int j = 0; j < XT::ncol; ++j)
