@@ -196,6 +196,11 @@ typedef struct {
  * multires   0 = naive full-resolution pass (masks unused), 1 = multi-res.
  * out        f32 [C][H][W], C = 3 for SSGI, else 1.
  * level_map  optional u8 [H][W] owner-level output (multires only).
+ * level_dtype  MR_F32 (0) or MR_F16: storage of the sub-image values between
+ *            the evaluation and the merge (FP16 halves that traffic; every
+ *            value is rounded to nearest even once, all arithmetic stays
+ *            FP32).  MR_F16 needs the compact frame path (coarsest level
+ *            <= 4, width divisible by 128, blur radii <= 8), else MR_E_DTYPE.
  * stage_events  optional hipEvent_t handles (each may be NULL), recorded on
  *            the frame's stream: [0] before the first kernel, [1] after the
  *            masks and work lists (after the hard-shadow pass on the naive
@@ -214,6 +219,7 @@ typedef struct {
     const mr_ssgi_params* ssgi;
     float* out;
     uint8_t* level_map;
+    int level_dtype;
     void* stage_events[MR_FRAME_EVENTS];
 } mr_frame_desc;
 

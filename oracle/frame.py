@@ -25,10 +25,12 @@ class Frame:
 
 
 def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None,
-          dtype=np.float32) -> Frame:
+          dtype=np.float32, level_dtype=None) -> Frame:
     """effect in {"ssao", "shadow", "ssgi"}; params the matching *Params.
 
-    multires=False is the naive full-resolution pass."""
+    multires=False is the naive full-resolution pass.  level_dtype (e.g.
+    np.float16) stores every sub-image value in that type (rounded to
+    nearest) between the evaluation and the merge."""
     H, W = depth.shape
     channels = 3 if effect == "ssgi" else 1
 
@@ -57,6 +59,8 @@ def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, c
     lo = {}
     for i in pyr.levels:
         lo[i] = evaluate(i, None if i == L else pyr.stencil[i])
+        if level_dtype is not None:
+            lo[i] = lo[i].astype(level_dtype).astype(dtype)
     weights = {i: mp.weight[i - 1] for i in pyr.levels}
     out = upsample_merge(W, H, pyr.levels, weights, pyr.alpha, pyr.stencil, lo, channels, dtype)
     return Frame(out=out, pyramid=pyr, level_out=lo)

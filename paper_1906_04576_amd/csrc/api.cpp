@@ -512,8 +512,9 @@ void set_level_cameras(const mr_camera* cam, const Geo& g, EvalCommon& c, bool p
 // compact) also has the evaluators write a_i at the list position
 int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g, const mr_masks* m,
             const void* params, float* const out[kMaxLevels], hipStream_t s, bool compact = false,
-            const LeanArgs* lean = nullptr) {
+            const LeanArgs* lean = nullptr, bool out16 = false) {
     auto set_compact = [&](EvalCommon& c) {
+        for (int j = 0; j < c.nlev; ++j) c.lv[j].out16 = out16 ? 1 : 0;
         if (!compact) return;
         for (int j = 0; j < c.nlev; ++j) {
             EvalLevel& L = c.lv[j];
@@ -735,7 +736,7 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         }
     }
     if ((st = mark(d, 1, s))) return st;
-    st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s, /*compact=*/true, &la);
+    st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s, /*compact=*/true, &la, d->level_dtype == MR_F16);
     if (st) return st;
     if ((st = mark(d, 2, s))) return st;
     // merge by rank
@@ -746,6 +747,7 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
     ma.C = C;
     ma.out = d->out;
     ma.fine1 = true;
+    ma.c16 = d->level_dtype == MR_F16;
     for (int j = 0; j < g.nlev; ++j) {
         const int i = g.levels[j];
         LeanMergeLevel& L = ma.lv[j];
@@ -908,6 +910,8 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if (!d->out) return fail(MR_E_NULL, "out is NULL");
     if (misaligned(d->out)) return fail(MR_E_PARAM, "out is not 16-byte aligned");
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    if (d->level_dtype != MR_F32 && d->level_dtype != MR_F16)
+        return fail(MR_E_DTYPE, "level_dtype %d is neither MR_F32 nor MR_F16", d->level_dtype);
     if (!d->multires) {
         Geo g;
         st = check_geo(&d->cam, nullptr, g);
@@ -931,6 +935,9 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
     if (lean_ok(g, &d->mp)) return do_frame_lean(d, g, params, static_cast<uint8_t*>(ws), s);
+    if (d->level_dtype == MR_F16)
+        return fail(MR_E_DTYPE, "f16 sub-image storage needs the compact frame path (coarsest level <= 4, width "
+                                "divisible by 128, blur radii <= 8 with positive taps)");
     uint8_t* b = static_cast<uint8_t*>(ws);
     mr_masks m{};
     m.edge = b + f.edge;

@@ -142,6 +142,14 @@ __device__ __forceinline__ float alpha_dispatch(const EvalLevel& L, const float*
     }
 }
 
+// store one sub-image value (f16 storage rounds to nearest even)
+__device__ __forceinline__ void store_out(const EvalLevel& L, unsigned idx, float v) {
+    if (L.out16)
+        reinterpret_cast<_Float16*>(L.out)[idx] = (_Float16)v;
+    else
+        L.out[idx] = v;
+}
+
 // P = (X z, Y z, -z), X = ((x + 0.5) - cx) / f, Y = (cy - (y + 0.5)) / f
 __device__ __forceinline__ void view_pos(int x, int y, float z, float f, float cx, float cy,
                                          float& px, float& py, float& pz) {

@@ -181,7 +181,13 @@ __device__ __forceinline__ void axis_taps_l(int X, int sh, int n, int lo, int& i
     ib = min(max(x0 + 1, 0), n - 1) - lo;
 }
 
-template <int C>
+// value of a sub-image (f32 or f16 storage)
+template <typename VT>
+__device__ __forceinline__ float cval(const void* c, long long i) {
+    return (float)static_cast<const VT*>(c)[i];
+}
+
+template <int C, typename VT>
 __global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
     __shared__ float la[kMergeLDS];
     __shared__ uint8_t ls[kMergeLDS];
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned ti
             sv[j] = 1;
             const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
 #pragma unroll
-            for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + p];
+            for (int c = 0; c < C; ++c) cv[j][c] = cval<VT>(L.c, c * L.c_plane + p);
         } else {
             const unsigned wi = (unsigned)Yl * (unsigned)L.wpr + (unsigned)(Xl >> 5);
             const unsigned word = L.Sb[wi];
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned ti
                 sv[j] = 1;
                 av[j] = L.ac[rank];
 #pragma unroll
-                for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + rank];
+                for (int c = 0; c < C; ++c) cv[j][c] = cval<VT>(L.c, c * L.c_plane + rank);
             }
         }
     }
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned ti
                     s1[k] = 1;
                     a1[k] = L.ac[rank];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) c1[c][k] = L.c[c * L.c_plane + rank];
+                    for (int c = 0; c < C; ++c) c1[c][k] = cval<VT>(L.c, c * L.c_plane + rank);
                     ++rank;
                 }
             }
@@ -497,7 +503,7 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
     }
 }
 
-template <int C>
+template <int C, typename VT>
 __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
     using R2 = Region4<1>;
     using R3 = Region4<2>;
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned t
         if (lv == 3) {
             const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
 #pragma unroll
-            for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + p];
+            for (int c = 0; c < C; ++c) cv[j][c] = cval<VT>(L.c, c * L.c_plane + p);
         } else {
             const unsigned wi = (unsigned)Yl * (unsigned)L.wpr + (unsigned)(Xl >> 5);
             const unsigned word = L.Sb[wi];
@@ -545,7 +551,7 @@ __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned t
                 const unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
                 av[j] = L.ac[rank];
 #pragma unroll
-                for (int c = 0; c < C; ++c) cv[j][c] = L.c[c * L.c_plane + rank];
+                for (int c = 0; c < C; ++c) cv[j][c] = cval<VT>(L.c, c * L.c_plane + rank);
             }
         }
     }
@@ -571,7 +577,7 @@ __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned t
                 if ((nib >> k) & 1u) {
                     a1[k] = L.ac[rank];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) c1[c][k] = L.c[c * L.c_plane + rank];
+                    for (int c = 0; c < C; ++c) c1[c][k] = cval<VT>(L.c, c * L.c_plane + rank);
                     ++rank;
                 }
             }
@@ -653,21 +659,26 @@ bool merge4_applies(const LeanMergeArgs& a) {
     return true;
 }
 
-hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s) {
+template <typename VT>
+hipError_t launch_lean_merge_t(const LeanMergeArgs& a, hipStream_t s) {
     const unsigned tx = (a.W + kMergeTW - 1) / kMergeTW, ty = (a.H + kMergeTH - 1) / kMergeTH;
     const bool m4 = merge4_applies(a);
     if (a.C == 3) {
         if (m4)
-            hipLaunchKernelGGL(k_lean_merge4<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+            hipLaunchKernelGGL((k_lean_merge4<3, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
         else
-            hipLaunchKernelGGL(k_lean_merge<3>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+            hipLaunchKernelGGL((k_lean_merge<3, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
     } else {
         if (m4)
-            hipLaunchKernelGGL(k_lean_merge4<1>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+            hipLaunchKernelGGL((k_lean_merge4<1, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
         else
-            hipLaunchKernelGGL(k_lean_merge<1>, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+            hipLaunchKernelGGL((k_lean_merge<1, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s) {
+    return a.c16 ? launch_lean_merge_t<_Float16>(a, s) : launch_lean_merge_t<float>(a, s);
 }
 
 }  // namespace mr

@@ -121,7 +121,7 @@ __device__ __forceinline__ void pcss_items(const ShadowArgs& a, const float* bds
             else
                 vis = pcss_texel(a, L, a.bd, a.pd, x, y, z);
         }
-        L.out[L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x] = vis;
+        store_out(L, L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x, vis);
     }
 }
 

@@ -147,7 +147,7 @@ __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, c
             else
                 res = ssao_texel<NT, !AL>(a, L, nrm, plane, a.kernel, kmax, x, y, z);
         }
-        L.out[L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x] = res;
+        store_out(L, L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x, res);
     }
 }
 

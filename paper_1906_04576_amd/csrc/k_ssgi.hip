@@ -80,9 +80,9 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
             }
         }
         const long long o = L.compact ? (long long)local : (long long)y * L.W + x;
-        L.out[o] = acc0 * scale;
-        L.out[L.out_plane + o] = acc1 * scale;
-        L.out[2 * L.out_plane + o] = acc2 * scale;
+        store_out(L, (unsigned)o, acc0 * scale);
+        store_out(L, (unsigned)L.out_plane + (unsigned)o, acc1 * scale);
+        store_out(L, 2u * (unsigned)L.out_plane + (unsigned)o, acc2 * scale);
     }
 }
 

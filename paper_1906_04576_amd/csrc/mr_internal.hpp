@@ -123,7 +123,8 @@ struct EvalLevel {
     int gpx;
     int W, H;
     float f, cx, cy;
-    float* out;
+    float* out;            // f32, or f16 when out16
+    int out16;
     long long out_plane;
     const uint32_t* list;  // null = dense
     int count_idx;         // list length = counts[count_idx]
@@ -243,7 +244,7 @@ struct LeanMapArgs {
 };
 
 struct LeanMergeLevel {
-    const float* c;      // by rank (levels below the coarsest) or dense (coarsest)
+    const void* c;       // f32 or f16 values by rank (levels below the coarsest) or dense (coarsest)
     long long c_plane;
     const uint32_t* Sb;  // null for the coarsest
     const uint32_t* woff;
@@ -260,6 +261,7 @@ struct LeanMergeArgs {
     int W, H, C;
     int staged;
     bool fine1;
+    bool c16;  // sub-image values stored as f16
     float* out;
 };
 

@@ -73,7 +73,8 @@ class mr_frame_desc(ctypes.Structure):
                 ("cam", mr_camera), ("mp", mr_mask_params),
                 ("ssao", ctypes.POINTER(mr_ssao_params)), ("shadow", ctypes.POINTER(mr_shadow_params)),
                 ("ssgi", ctypes.POINTER(mr_ssgi_params)), ("out", ctypes.c_void_p),
-                ("level_map", ctypes.c_void_p), ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS)]
+                ("level_map", ctypes.c_void_p), ("level_dtype", ctypes.c_int),
+                ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS)]
 
 
 # entry points and their ctypes signatures (also used by the export test)
@@ -454,7 +455,7 @@ class FrameRunner:
     once so that repeated calls cost one ctypes call each."""
 
     def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
-                 out=None, level_map=None, workspace=None):
+                 out=None, level_map=None, workspace=None, level_dtype=torch.float32):
         self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         H, W = depth.shape
         C = 3 if self.effect == MR_EFFECT_SSGI else 1
@@ -475,6 +476,7 @@ class FrameRunner:
             d.ssgi = ctypes.pointer(params)
         d.out = _ptr(self.out)
         d.level_map = _ptr(level_map)
+        d.level_dtype = MR_F16 if level_dtype == torch.float16 else MR_F32
         self.desc = d
         self._keep = (depth, normal, color, level_map)
         nws = mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0
@@ -512,8 +514,9 @@ class FrameRunner:
 
 
 def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,
-             level_map=None, stream=None):
-    return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map)(stream)
+             level_map=None, stream=None, level_dtype=torch.float32):
+    return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map,
+                       level_dtype=level_dtype)(stream)
 
 
 class Prepared:
