@@ -1,0 +1,232 @@
+"""Continuous-batching request loop for multi-resolution lighting frames.
+
+Requests (a resident seeded scene at some resolution, one of the three
+effects) arrive as a Poisson stream.  A request is admitted as soon as one of
+the slots is free and its working memory (workspace and output) fits the HBM
+budget next to the requests in flight; each slot is a HIP stream with its own
+workspace, so admitted requests overlap on the device while others keep
+arriving.  Latency is completion minus arrival, throughput the pixels
+finished per second of wall time.  Every frame goes through mr_frame; this
+module only schedules.
+
+    python -m paper_1906_04576_amd.serve --qps 4000 --seconds 2
+prints one JSON line with p50/p99 latency and Mpixels/s, multi-resolution
+and naive, on the same request stream, and the throughput with the same
+requests admitted back to back (the loop's capacity).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import mr
+
+RESOLUTIONS = ((1280, 720), (1920, 1080), (2560, 1440), (3840, 2160))
+RES_WEIGHTS = (0.2, 0.4, 0.2, 0.2)
+EFFECTS = ("ssao", "shadow", "ssgi")
+
+
+@dataclass
+class Scene:
+    """Resident inputs of one seeded scene at one resolution."""
+    W: int
+    H: int
+    focal: float
+    depth: torch.Tensor
+    normal: torch.Tensor
+    color: torch.Tensor
+    shadow: mr.mr_shadow_params
+    bytes: int
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds after the start of the stream
+    effect: str
+    scene: int      # index into the resident scene pool
+
+
+@dataclass
+class Done:
+    rid: int
+    arrival: float
+    start: float
+    end: float
+    pixels: int
+    out: torch.Tensor | None = None
+
+
+def _mask_params(effect: str) -> mr.MaskParams:
+    import scenegen
+    t = scenegen.TABLE1[effect]
+    en = 0b1101 if effect == "ssgi" else 0b1111  # Table 1: SSGI leaves level 2 out
+    return mr.MaskParams(num_levels=4, level_enable=en, sigma2=t["sigma2"], weight=t["weight"])
+
+
+class Pool:
+    """Resident scenes (G-buffer, colour, shadow map) and effect parameters."""
+
+    def __init__(self, scenes_per_res: int = 2, device="cuda", resolutions=RESOLUTIONS, shadow_map=2048):
+        import scenegen
+        self.device = device
+        self.scenes: list[Scene] = []
+        self.res_index: dict[tuple, list[int]] = {}
+        for (W, H) in resolutions:
+            for k in range(scenes_per_res):
+                seed = 100 + 10 * len(self.res_index) + k
+                sc = scenegen.make_scene(seed, 200, 50)
+                gb = scenegen.render_gbuffer(sc, scenegen.orbit_view(k % 8), W, H)
+                si = scenegen.render_shadow_inputs(sc, gb.view, shadow_map)
+                col = scenegen.lambert_color(sc, gb)
+                d = torch.from_numpy(gb.depth).to(device)
+                n = torch.from_numpy(gb.normal).to(device)
+                c = torch.from_numpy(col).to(device)
+                sm = torch.from_numpy(si.shadow_map).to(device)
+                bd = torch.from_numpy(scenegen.disk_samples(16, 11)).to(device)
+                pd = torch.from_numpy(scenegen.disk_samples(32, 12)).to(device)
+                sp = mr.shadow_params(sm, si.view_to_light, si.light_focal, si.light_size, si.light_near, 0.05,
+                                      bd, pd)
+                nbytes = sum(t.numel() * t.element_size() for t in (d, n, c, sm))
+                self.res_index.setdefault((W, H), []).append(len(self.scenes))
+                self.scenes.append(Scene(W, H, float(gb.focal), d, n, c, sp, nbytes))
+        self.mp = {e: _mask_params(e) for e in EFFECTS}
+        self.ssao = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(32)).to(device), 1.0, 0.02)
+        self.ssgi = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(64)).to(device), 2.0, 0.02)
+
+    def params(self, effect: str, scene: Scene):
+        return {"ssao": self.ssao, "shadow": scene.shadow, "ssgi": self.ssgi}[effect]
+
+    def workspace_bytes(self) -> int:
+        W, H = max(RESOLUTIONS, key=lambda r: r[0] * r[1])
+        f = self.scenes[0].focal
+        return max(mr.mr_workspace_bytes(W, H, f, self.mp[e], mr.EFFECTS[e]) for e in EFFECTS)
+
+
+def poisson_requests(pool: Pool, qps: float, seconds: float, seed: int = 7) -> list[Request]:
+    """Arrivals at rate qps (exponential gaps), resolution by RES_WEIGHTS
+    (pool resolutions outside that mix: equal weights), effect uniform, scene
+    uniform among that resolution's resident scenes."""
+    rng = np.random.default_rng(seed)
+    reqs, t, rid = [], 0.0, 0
+    res = list(pool.res_index)
+    # the serving mix's weights for its resolutions, equal weights otherwise
+    w = np.array([RES_WEIGHTS[RESOLUTIONS.index(r)] if r in RESOLUTIONS else 1.0 for r in res], float)
+    w /= w.sum()
+    while True:
+        t += rng.exponential(1.0 / qps)
+        if t >= seconds:
+            break
+        r = res[rng.choice(len(res), p=w)]
+        reqs.append(Request(rid, t, EFFECTS[rng.integers(3)], int(rng.choice(pool.res_index[r]))))
+        rid += 1
+    return reqs
+
+
+class Server:
+    """slots concurrent frames (one stream and workspace each) under an HBM
+    budget for the working memory of the requests in flight."""
+
+    def __init__(self, pool: Pool, slots: int = 4, budget_bytes: int = 64 << 30, multires: bool = True,
+                 level_dtype=torch.float32, keep_outputs: bool = False):
+        self.pool, self.multires, self.level_dtype, self.keep = pool, multires, level_dtype, keep_outputs
+        self.budget = budget_bytes
+        ws = pool.workspace_bytes() if multires else 256
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.ws = [torch.empty(ws, dtype=torch.uint8, device=pool.device) for _ in range(slots)]
+        self.ws_bytes = ws
+
+    def _launch(self, req: Request, slot: int):
+        sc = self.pool.scenes[req.scene]
+        C = 3 if req.effect == "ssgi" else 1
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            out = torch.empty((C, sc.H, sc.W) if C > 1 else (sc.H, sc.W), dtype=torch.float32,
+                              device=self.pool.device)
+        fr = mr.FrameRunner(req.effect, sc.depth, sc.normal, sc.focal, self.pool.mp[req.effect], self.multires,
+                            color=sc.color if req.effect == "ssgi" else None,
+                            params=self.pool.params(req.effect, sc), out=out, workspace=self.ws[slot],
+                            level_dtype=self.level_dtype)
+        fr(st)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        return out, ev, out.numel() * 4 + self.ws_bytes
+
+    def run(self, reqs: list[Request], realtime: bool = True) -> list[Done]:
+        """Serve the request stream; realtime=False admits every request as
+        soon as a slot is free (arrival times ignored)."""
+        pending = list(reqs)
+        free = list(range(len(self.streams)))
+        inflight = {}  # slot -> (req, out, event, bytes, start)
+        used = 0
+        done: list[Done] = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while pending or inflight:
+            now = time.perf_counter() - t0
+            for slot in list(inflight):
+                req, out, ev, nb, start = inflight[slot]
+                if ev.query():
+                    end = time.perf_counter() - t0
+                    sc = self.pool.scenes[req.scene]
+                    done.append(Done(req.rid, req.arrival if realtime else start, start, end, sc.W * sc.H,
+                                     out if self.keep else None))
+                    used -= nb
+                    del inflight[slot]
+                    free.append(slot)
+            while pending and free and (not realtime or pending[0].arrival <= now):
+                req = pending[0]
+                sc = self.pool.scenes[req.scene]
+                need = (3 if req.effect == "ssgi" else 1) * sc.W * sc.H * 4 + self.ws_bytes
+                if used + need > self.budget and inflight:
+                    break  # admitted when memory frees up
+                pending.pop(0)
+                slot = free.pop(0)
+                out, ev, nb = self._launch(req, slot)
+                used += nb
+                inflight[slot] = (req, out, ev, nb, time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        return sorted(done, key=lambda d: d.rid)
+
+
+def summary(done: list[Done]) -> dict:
+    lat = np.array([d.end - d.arrival for d in done]) * 1e3
+    span = max(d.end for d in done) - min(d.arrival for d in done)
+    px = sum(d.pixels for d in done)
+    return {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4), "mpixels_s": round(px / span / 1e6, 2)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--qps", type=float, default=4000.0)
+    ap.add_argument("--seconds", type=float, default=2.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--scenes-per-res", type=int, default=2)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    args = ap.parse_args(argv)
+    t = time.time()
+    pool = Pool(args.scenes_per_res)
+    print(f"[serve] {len(pool.scenes)} resident scenes in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    reqs = poisson_requests(pool, args.qps, args.seconds)
+    res = {"qps": args.qps, "seconds": args.seconds, "slots": args.slots, "budget_gb": args.budget_gb}
+    for multires in (True, False):
+        srv = Server(pool, args.slots, int(args.budget_gb * (1 << 30)), multires)
+        srv.run(reqs[: min(len(reqs), 64)])  # warm-up
+        s = summary(srv.run(reqs))
+        # the same requests admitted back to back: the loop's capacity
+        sat = summary(srv.run(reqs, realtime=False))
+        s["saturated_mpixels_s"] = sat["mpixels_s"]
+        res["multires" if multires else "plain"] = s
+        print(f"[serve] {'multi-res' if multires else 'plain'}: {s}", file=sys.stderr, flush=True)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
