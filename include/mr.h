@@ -109,7 +109,21 @@ typedef struct {
  * weight[i-1]  blend weight w_i (> 0, finite).
  * radius[i-1]  blur radius in level-i texels, -1 = ceil(3 sigma), at most
  *              MR_MAX_RADIUS.  Entries of disabled levels and of level N are
- *              ignored. */
+ *              ignored.
+ * fovea        optional importance mask of a gaze point (Sec. 6: foveated
+ *              rendering by modulating the mask; masks combined by minimum
+ *              and maximum, Sec. 3.1), applied to the edge image before the
+ *              pyramid: with d2 = dx*dx + dy*dy, dx = (x + 0.5f) - gaze_x,
+ *              dy = (y + 0.5f) - gaze_y (FP32, in that order),
+ *              E'(x, y) = (E(x, y) && d2 <= r_outer*r_outer) || d2 <= r_inner*r_inner:
+ *              full detail near the gaze, the coarsest level beyond r_outer.
+ *              enable = 0 turns it off; radii finite and >= 0. */
+typedef struct {
+    int enable;
+    float gaze_x, gaze_y;
+    float r_inner, r_outer;
+} mr_fovea;
+
 typedef struct {
     int num_levels;
     uint32_t level_enable;
@@ -118,6 +132,7 @@ typedef struct {
     float sigma2[MR_MAX_LEVELS];
     float weight[MR_MAX_LEVELS];
     int radius[MR_MAX_LEVELS];
+    mr_fovea fovea;
 } mr_mask_params;
 
 /* Mask pyramid (outputs of mr_build_masks, inputs of eval/merge).  Index

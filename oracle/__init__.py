@@ -35,7 +35,7 @@ correctly rounded, floor/abs/min/max are exact.
 Where the paper is silent the oracle takes one fixed reading; each such
 reading is marked "reading:" at the place it is used.
 """
-from .masks import (MaskParams, edge_image, gaussian_weights, blur_radius, or_pool,
+from .masks import (MaskParams, edge_image, foveate, gaussian_weights, blur_radius, or_pool,
                     build_pyramid, Pyramid, level_sample, work_lists, level_dims)
 from .ssao import SSAOParams, ssao_texels, ssao_level, ssao_plain
 from .merge import upsample_merge
@@ -44,7 +44,7 @@ from .ssgi import SSGIParams, ssgi_texels, ssgi_level
 from .frame import frame, Frame
 
 __all__ = [
-    "MaskParams", "edge_image", "gaussian_weights", "blur_radius", "or_pool", "build_pyramid",
+    "MaskParams", "edge_image", "foveate", "gaussian_weights", "blur_radius", "or_pool", "build_pyramid",
     "Pyramid", "level_sample", "work_lists", "level_dims", "SSAOParams", "ssao_texels",
     "ssao_level", "ssao_plain", "upsample_merge", "ShadowParams", "light_coords", "hard_shadow",
     "shadow_edges", "pcss_texels", "pcss_level", "SSGIParams", "ssgi_texels", "ssgi_level",

@@ -10,7 +10,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .masks import MaskParams, edge_image, build_pyramid, level_sample, Pyramid
+from .masks import MaskParams, edge_image, foveate, build_pyramid, level_sample, Pyramid
 from .ssao import SSAOParams, ssao_level
 from .merge import upsample_merge
 from .shadow import ShadowParams, hard_shadow, shadow_edges, pcss_level
@@ -54,6 +54,7 @@ def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, c
         # geometry edges, combined by maximum.
         hard = hard_shadow(depth, focal, 1, params, dtype)
         E = E | shadow_edges(hard, depth)
+    E = foveate(E, mp.fovea)
     pyr = build_pyramid(E, mp, dtype)
     L = pyr.levels[-1]
     lo = {}

@@ -27,6 +27,7 @@ class MaskParams:
     sigma2       blur variance per level, in level-i texels (Table 1).
     weight       blend weight per level (Table 1).
     radius       blur radius per level; -1 means ceil(3 sigma).
+    fovea        (gaze_x, gaze_y, r_inner, r_outer) or None: see foveate().
     """
     num_levels: int = 4
     level_enable: int = 0xF
@@ -35,6 +36,7 @@ class MaskParams:
     sigma2: tuple = (0.924, 1.848, 3.696, 0.0)
     weight: tuple = (100.0, 50.0, 20.0, 1.0)
     radius: tuple = (-1, -1, -1, -1)
+    fovea: tuple = None
 
     def enabled(self):
         return [i for i in range(1, self.num_levels + 1) if (self.level_enable >> (i - 1)) & 1]
@@ -115,6 +117,26 @@ def edge_image(depth, normal, depth_ratio, normal_cos, dtype=np.float32):
 # --------------------------------------------------------------------------
 # Sec. 3.1: downsampling of the mask to each sub-image resolution
 # --------------------------------------------------------------------------
+def foveate(E, fovea):
+    """Sec. 6 (foveated rendering: the mask modulated by an importance mask
+    from an eye tracker) with Sec. 3.1's combination of masks by minimum and
+    maximum.  Reading: the importance mask of a gaze point g is 1 within
+    r_inner of g (full resolution there), 0 beyond r_outer (coarsest level
+    there) and leaves the edges alone in between:
+        E' = max(min(E, [d2 <= r_outer^2]), [d2 <= r_inner^2]),
+    d2 = dx^2 + dy^2 from the pixel centre, all in FP32."""
+    if fovea is None:
+        return E
+    gx, gy, ri, ro = (np.float32(v) for v in fovea)
+    H, W = E.shape
+    dx = (np.arange(W, dtype=np.float32) + np.float32(0.5)) - gx
+    dy = (np.arange(H, dtype=np.float32) + np.float32(0.5)) - gy
+    d2 = (dx * dx)[None, :] + (dy * dy)[:, None]
+    outer = d2 <= ro * ro
+    inner = d2 <= ri * ri
+    return ((E.astype(bool) & outer) | inner).astype(np.uint8)
+
+
 def or_pool(E, s):
     """E_i(x, y) = OR of E over the s x s full-resolution block of texel (x, y).
 

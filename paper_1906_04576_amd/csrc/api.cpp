@@ -105,6 +105,12 @@ int check_mask_params(const mr_mask_params* mp, const Geo& g) {
         return fail(MR_E_PARAM, "depth_ratio must be finite and >= 0");
     if (!(mp->normal_cos >= -1.0f && mp->normal_cos <= 1.0f))
         return fail(MR_E_PARAM, "normal_cos must be in [-1, 1]");
+    if (mp->fovea.enable) {
+        const mr_fovea& f = mp->fovea;
+        if (!isfinite(f.gaze_x) || !isfinite(f.gaze_y) || !isfinite(f.r_inner) || !isfinite(f.r_outer) ||
+            !(f.r_inner >= 0.0f) || !(f.r_outer >= 0.0f))
+            return fail(MR_E_PARAM, "fovea: gaze and radii must be finite, radii >= 0");
+    }
     for (int j = 0; j + 1 < g.nlev; ++j) {
         const int i = g.levels[j];
         float taps[2 * kMaxRadius + 1];
@@ -351,6 +357,15 @@ LeanLayout lean_layout(const Geo& g, int effect) {
 // ---------------------------------------------------------------------------
 // pipeline pieces (arguments already validated)
 // ---------------------------------------------------------------------------
+// importance mask of a gaze point: squared radii in FP32
+void set_fovea(EdgeArgs& ea, const mr_mask_params* mp) {
+    ea.fov = mp->fovea.enable ? 1 : 0;
+    ea.fgx = mp->fovea.gaze_x;
+    ea.fgy = mp->fovea.gaze_y;
+    ea.fri2 = mp->fovea.r_inner * mp->fovea.r_inner;
+    ea.fro2 = mp->fovea.r_outer * mp->fovea.r_outer;
+}
+
 int do_build_masks(const mr_gbuffer* gb, const Geo& g, const mr_mask_params* mp, const uint8_t* hard,
                    const mr_masks* m, void* ws, hipStream_t s) {
     const MaskScratch sc = mask_scratch(g);
@@ -363,6 +378,7 @@ int do_build_masks(const mr_gbuffer* gb, const Geo& g, const mr_mask_params* mp,
     ea.H = g.H;
     ea.depth_ratio = mp->depth_ratio;
     ea.normal_cos = mp->normal_cos;
+    set_fovea(ea, mp);
     ea.E = m->edge;
     ea.num_levels = g.N;
     uint8_t* Ei[kMaxLevels] = {};
@@ -665,6 +681,7 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
     ea.H = g.H;
     ea.depth_ratio = d->mp.depth_ratio;
     ea.normal_cos = d->mp.normal_cos;
+    set_fovea(ea, &d->mp);
     ea.num_levels = g.N;
     for (int i = 1; i <= g.N; ++i) {
         ea.Wi[i - 1] = g.Wi[i - 1];

@@ -45,6 +45,15 @@ __device__ __forceinline__ void row4<_Float16>(const _Float16* p, unsigned off, 
     }
 }
 
+// Importance mask of a gaze point combined with the edge bit e (minimum with
+// the outer disk, maximum with the inner one), FP32 in the documented order.
+__device__ __forceinline__ bool fovea(const EdgeArgs& a, int x, int y, bool e) {
+    if (!a.fov) return e;
+    const float dx = ((float)x + 0.5f) - a.fgx, dy = ((float)y + 0.5f) - a.fgy;
+    const float d2 = (dx * dx) + (dy * dy);
+    return (e & (d2 <= a.fro2)) | (d2 <= a.fri2);
+}
+
 __device__ __forceinline__ bool ndot_lt(const float* a, const float* b, float cn) {
     // ((nx nx') + (ny ny')) + (nz nz') < c_n
     return ((a[0] * b[0]) + (a[1] * b[1])) + (a[2] * b[2]) < cn;
@@ -175,7 +184,7 @@ __global__ __launch_bounds__(256) void k_edges_generic(EdgeArgs a, unsigned tile
                 ed = ed || (hl && hl_ != hc) || (hr && hr_ != hc) || (hu && h[r][c] != hc) ||
                      (hd && h[r + 2][c] != hc);
             }
-            e[r][c] = (any && x < W && y < H && valid_depth(zc) && ed) ? 1 : 0;
+            e[r][c] = (any && x < W && y < H && fovea(a, x, y, valid_depth(zc) && ed)) ? 1 : 0;
         }
     }
     if (any) {
@@ -422,7 +431,7 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
                 const unsigned hu_ = (hrow[r] >> sh) & 0xFFu, hd_ = (hrow[r + 2] >> sh) & 0xFFu;
                 ed |= (hl & (hl_ != hc)) | (hr & (hr_ != hc)) | (hu & (hu_ != hc)) | (hd & (hd_ != hc));
             }
-            e[r][c] = (any & (y < H) & valid_depth(zc) & ed) ? 1 : 0;
+            e[r][c] = (any & (y < H) & fovea(a, x, y, valid_depth(zc) & ed)) ? 1 : 0;
         }
     }
     if (BITS) {

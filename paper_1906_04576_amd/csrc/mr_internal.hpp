@@ -69,6 +69,9 @@ struct EdgeArgs {
     uint32_t* Eb[3];
     int wpr[3];
     uint32_t* zero_counts;  // optional: MR_MAX_LEVELS counters set to 0 by block 0
+    // importance mask of a gaze point (fov != 0): squared radii, FP32
+    int fov;
+    float fgx, fgy, fri2, fro2;
 };
 
 struct BlurLevel {

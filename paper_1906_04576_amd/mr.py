@@ -40,10 +40,15 @@ class mr_camera(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int), ("focal_px", ctypes.c_float)]
 
 
+class mr_fovea(ctypes.Structure):
+    _fields_ = [("enable", ctypes.c_int), ("gaze_x", ctypes.c_float), ("gaze_y", ctypes.c_float),
+                ("r_inner", ctypes.c_float), ("r_outer", ctypes.c_float)]
+
+
 class mr_mask_params(ctypes.Structure):
     _fields_ = [("num_levels", ctypes.c_int), ("level_enable", ctypes.c_uint32),
                 ("depth_ratio", ctypes.c_float), ("normal_cos", ctypes.c_float),
-                ("sigma2", c_float6), ("weight", c_float6), ("radius", c_int6)]
+                ("sigma2", c_float6), ("weight", c_float6), ("radius", c_int6), ("fovea", mr_fovea)]
 
 
 class mr_masks(ctypes.Structure):
@@ -145,6 +150,7 @@ class MaskParams:
     sigma2: tuple = (0.924, 1.848, 3.696, 0.0)
     weight: tuple = (100.0, 50.0, 20.0, 1.0)
     radius: tuple = (-1, -1, -1, -1)
+    fovea: tuple = None  # (gaze_x, gaze_y, r_inner, r_outer) or None
 
     def levels(self):
         return [i for i in range(1, self.num_levels + 1) if (self.level_enable >> (i - 1)) & 1]
@@ -159,6 +165,9 @@ class MaskParams:
             p.sigma2[i] = self.sigma2[i] if i < len(self.sigma2) else 0.0
             p.weight[i] = self.weight[i] if i < len(self.weight) else 1.0
             p.radius[i] = self.radius[i] if i < len(self.radius) else -1
+        if self.fovea is not None:
+            p.fovea.enable = 1
+            p.fovea.gaze_x, p.fovea.gaze_y, p.fovea.r_inner, p.fovea.r_outer = (float(v) for v in self.fovea)
         return p
 
 

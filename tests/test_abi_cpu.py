@@ -37,12 +37,12 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     # mirrors of include/mr.h (x86-64 SysV alignment)
     assert ctypes.sizeof(mr.mr_camera) == 12
-    assert ctypes.sizeof(mr.mr_mask_params) == 4 + 4 + 4 + 4 + 24 + 24 + 24
+    assert ctypes.sizeof(mr.mr_mask_params) == 4 + 4 + 4 + 4 + 24 + 24 + 24 + 20
     assert ctypes.sizeof(mr.mr_masks) == 8 * (2 + 4 * 6 + 1)
     assert ctypes.sizeof(mr.mr_gbuffer) == 40
 
 
-STRUCTS = ["mr_gbuffer", "mr_camera", "mr_mask_params", "mr_masks", "mr_ssao_params", "mr_shadow_params",
+STRUCTS = ["mr_gbuffer", "mr_camera", "mr_fovea", "mr_mask_params", "mr_masks", "mr_ssao_params", "mr_shadow_params",
            "mr_ssgi_params", "mr_frame_desc"]
 
 

@@ -5,6 +5,7 @@ Bar: masks, stencils, owner-level map, work lists and counts bit-exact;
 lighting and merge within 1e-4 absolute in FP32 (the kernels follow the
 oracle's operation order, so they are expected to be bit-exact as well and
 the strict tests check that too)."""
+import dataclasses
 import math
 import sys
 
@@ -170,6 +171,34 @@ def test_plain_and_frame(name):
     assert np.abs(m - rf.out).max() <= TOL and np.array_equal(m, rf.out), "multi-res frame"
     # quality bound of the method against the naive pass
     assert np.abs(m - p).mean() <= 0.01
+
+
+@pytest.mark.parametrize("name,fovea", [("256_3lv", (100.3, 140.6, 30.0, 70.5)),
+                                        ("lean_640x360", (420.0, 150.5, 60.0, 150.0)),
+                                        ("lean_384x200", (-20.0, 90.0, 80.0, 120.0))])
+def test_foveated_masks_and_frame(name, fovea):
+    """Importance mask of a gaze point combined with the edges (min with the
+    outer disk, max with the inner one): masks bit-exact through the mask
+    entry point, frames (compact path for the 'lean' cases) against the
+    oracle."""
+    log(f"[gpu] fovea {name} {fovea}")
+    c = case(name)
+    gb = c["gb"]
+    mp = dataclasses.replace(c["mp"], fovea=fovea)
+    omp = dataclasses.replace(c["omp"], fovea=fovea)
+    E = oracle.foveate(oracle.edge_image(gb.depth, gb.normal, omp.depth_ratio, omp.normal_cos), fovea)
+    pyr = oracle.build_pyramid(E, omp)
+    masks = mr.mr_build_masks(c["d"], c["n"], gb.focal, mp)
+    torch.cuda.synchronize()
+    check_masks(dict(c, pyr=pyr), masks)
+    sp = mr.ssao_params(c["k"], c["r"], 0.02)
+    lm = torch.empty((c["H"], c["W"]), dtype=torch.uint8, device=DEV)
+    out = mr.mr_frame("ssao", c["d"], c["n"], gb.focal, mp, sp, multires=True, level_map=lm)
+    torch.cuda.synchronize()
+    rf = oracle.frame("ssao", gb.depth, gb.normal, gb.focal, omp, oracle.SSAOParams(c["K"], c["r"], 0.02))
+    assert np.array_equal(lm.cpu().numpy(), rf.pyramid.level_map)
+    o = out.cpu().numpy()
+    assert np.abs(o - rf.out).max() <= TOL and np.array_equal(o, rf.out)
 
 
 def test_all_finest_masks_reproduce_plain_bitwise():

@@ -226,3 +226,36 @@ def test_level_sample_point():
     assert oracle.level_sample(a, 1) is a
     assert oracle.level_sample(a, 2)[1, 2] == a[3, 5]
     assert oracle.level_sample(a, 4)[0, 0] == a[4, 4]
+
+
+def test_foveate_disks_brute_force():
+    """Pixels whose centre is clearly inside r_inner are on, clearly outside
+    r_outer are off, and in between keep the edge image (distances in
+    float64, pixels within 1e-3 of a circle skipped)."""
+    rng = np.random.default_rng(5)
+    E = (rng.random((40, 56)) < 0.3).astype(np.uint8)
+    g = (21.3, 17.8, 6.5, 14.25)
+    F = oracle.foveate(E, g)
+    for y in range(40):
+        for x in range(56):
+            d = math.hypot(x + 0.5 - g[0], y + 0.5 - g[1])
+            if abs(d - g[2]) < 1e-3 or abs(d - g[3]) < 1e-3:
+                continue
+            exp = 1 if d < g[2] else (0 if d > g[3] else E[y, x])
+            assert F[y, x] == exp, (x, y)
+    assert np.array_equal(oracle.foveate(E, None), E)
+
+
+def test_foveated_pyramid_owner_levels():
+    """The fovea is rendered at level 1 everywhere inside r_inner (minus one
+    pixel for the disk's discretisation), the periphery beyond r_outer plus
+    the largest blur footprint at the coarsest level."""
+    W = H = 128
+    E = np.zeros((H, W), np.uint8)
+    mp = oracle.MaskParams(num_levels=4, level_enable=0xF, fovea=(64.0, 64.0, 20.0, 40.0))
+    pyr = oracle.build_pyramid(oracle.foveate(E, mp.fovea), mp)
+    yy, xx = np.mgrid[0:H, 0:W]
+    d = np.hypot(xx + 0.5 - 64.0, yy + 0.5 - 64.0)
+    assert (pyr.level_map[d < 19.0] == 1).all()
+    reach = 40.0 + 8 * (6 + 1)  # outer radius + level-3 blur radius (6) + one texel, in pixels
+    assert (pyr.level_map[d > reach] == 4).all()
