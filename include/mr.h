@@ -292,6 +292,29 @@ MR_API int mr_upsample_merge(const mr_camera* cam, const mr_mask_params* mp, con
  * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */
 MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream);
 
+/* Batches: up to MR_MAX_BATCH frames of one effect (MR_EFFECT_SSAO or
+ * MR_EFFECT_SSGI) with identical mask and effect parameters and input types
+ * but any sizes, processed with one launch per stage for all frames (edges,
+ * ranks and work lists, per-level evaluation over one item space of all
+ * frames by a resident grid, merge).  Every frame must take the compact path
+ * (coarsest level <= 4, width divisible by 128, blur radii <= 8), have
+ * multires = 1 and level_map = NULL; stage_events are not recorded.
+ *
+ * mr_batch_setup validates the frames, lays them out in ws (at least
+ * mr_batch_workspace_bytes) and copies the kernel argument tables there; it
+ * returns when the copy is complete.  It fills `plan` (caller-owned host
+ * memory of MR_BATCH_PLAN_BYTES).  mr_batch_run enqueues the batch's kernels
+ * on `stream` and nothing else (no copies, no allocation, no memset), so it
+ * can be captured in a HIP graph; the frames' inputs may change between
+ * runs, their addresses and sizes may not.  ws and the inputs must stay
+ * valid while a run is in flight. */
+#define MR_MAX_BATCH 64
+#define MR_BATCH_PLAN_BYTES 512
+MR_API size_t mr_batch_workspace_bytes(const mr_frame_desc* frames, int n);
+MR_API int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan,
+                          size_t plan_bytes, void* stream);
+MR_API int mr_batch_run(const void* plan, void* stream);
+
 /* Host helpers. */
 MR_API const char* mr_status_string(int status);
 MR_API const char* mr_last_error(void);

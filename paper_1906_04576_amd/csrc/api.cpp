@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "mr_internal.hpp"
 
 using namespace mr;
@@ -19,6 +21,13 @@ int fail(int code, const char* fmt, ...) {
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
     return code;
+}
+
+// prefix the current error message with the frame index of a batch
+int fail_frame(int code, int k) {
+    char msg[sizeof(g_err)];
+    snprintf(msg, sizeof(msg), "%s", g_err);
+    return fail(code, "frame %d: %s", k, msg);
 }
 
 bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
@@ -526,9 +535,20 @@ void set_level_cameras(const mr_camera* cam, const Geo& g, EvalCommon& c, bool p
 
 // compact: list levels write their results at the list position; lean (with
 // compact) also has the evaluators write a_i at the list position
-int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g, const mr_masks* m,
-            const void* params, float* const out[kMaxLevels], hipStream_t s, bool compact = false,
-            const LeanArgs* lean = nullptr, bool out16 = false) {
+// Kernel arguments of one evaluation launch (one effect).
+struct EvalPlan {
+    int effect = MR_EFFECT_SSAO;
+    SsaoArgs sa{};
+    ShadowArgs sh{};
+    SsgiArgs gi{};
+    unsigned hint = 0;
+};
+
+// compact: list levels write their results at the list position; lean (with
+// compact) also has the evaluators write a_i at the list position
+void build_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g, const mr_masks* m,
+                const void* params, float* const out[kMaxLevels], bool compact, const LeanArgs* lean, bool out16,
+                EvalPlan& E) {
     auto set_compact = [&](EvalCommon& c) {
         for (int j = 0; j < c.nlev; ++j) c.lv[j].out16 = out16 ? 1 : 0;
         if (!compact) return;
@@ -547,22 +567,21 @@ int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g
         }
     };
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
-    hipError_t e;
+    E.effect = effect;
     if (effect == MR_EFFECT_SSAO) {
         const mr_ssao_params* p = static_cast<const mr_ssao_params*>(params);
-        SsaoArgs a{};
-        const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
+        SsaoArgs& a = E.sa;
+        E.hint = make_eval_common(gb, g, m, out, C, a.c);
         set_level_cameras(cam, g, a.c, !m);
         set_compact(a.c);
         a.kernel = p->kernel;
         a.S = p->samples;
         a.r = p->radius;
         a.b = p->bias_rel;
-        e = launch_ssao(a, gb->normal_dtype, hint, s);
     } else if (effect == MR_EFFECT_SHADOW) {
         const mr_shadow_params* p = static_cast<const mr_shadow_params*>(params);
-        ShadowArgs a{};
-        const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
+        ShadowArgs& a = E.sh;
+        E.hint = make_eval_common(gb, g, m, out, C, a.c);
         set_level_cameras(cam, g, a.c, !m);
         set_compact(a.c);
         a.sm = p->shadow_map;
@@ -576,21 +595,37 @@ int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g
         a.pd = p->pcf_disk;
         a.nb = p->n_blocker;
         a.np = p->n_pcf;
-        e = launch_shadow(a, hint, s);
     } else {
         const mr_ssgi_params* p = static_cast<const mr_ssgi_params*>(params);
-        SsgiArgs a{};
-        const unsigned hint = make_eval_common(gb, g, m, out, C, a.c);
+        SsgiArgs& a = E.gi;
+        E.hint = make_eval_common(gb, g, m, out, C, a.c);
         set_level_cameras(cam, g, a.c, !m);
         set_compact(a.c);
         a.kernel = p->kernel;
         a.S = p->samples;
         a.r = p->radius;
         a.b = p->bias_rel;
-        e = launch_ssgi(a, gb->normal_dtype, gb->color_dtype, hint, s);
     }
+}
+
+int launch_eval(const EvalPlan& E, int normal_dtype, int color_dtype, hipStream_t s) {
+    hipError_t e;
+    if (E.effect == MR_EFFECT_SSAO)
+        e = launch_ssao(E.sa, normal_dtype, E.hint, s);
+    else if (E.effect == MR_EFFECT_SHADOW)
+        e = launch_shadow(E.sh, E.hint, s);
+    else
+        e = launch_ssgi(E.gi, normal_dtype, color_dtype, E.hint, s);
     if (e != hipSuccess) return fail(MR_E_DEVICE, "evaluation kernel launch failed: %s", hipGetErrorString(e));
     return MR_OK;
+}
+
+int do_eval(int effect, const mr_gbuffer* gb, const mr_camera* cam, const Geo& g, const mr_masks* m,
+            const void* params, float* const out[kMaxLevels], hipStream_t s, bool compact = false,
+            const LeanArgs* lean = nullptr, bool out16 = false) {
+    EvalPlan E;
+    build_eval(effect, gb, cam, g, m, params, out, compact, lean, out16, E);
+    return launch_eval(E, gb->normal_dtype, gb->color_dtype, s);
 }
 
 int do_merge(const Geo& g, const mr_mask_params* mp, const mr_masks* m, const float* const lo[kMaxLevels], int C,
@@ -649,16 +684,26 @@ int mark(const mr_frame_desc* d, int k, hipStream_t s) {
     return MR_OK;
 }
 
-int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, hipStream_t s) {
+// Kernel arguments of one frame on the compact path, laid out in the
+// frame's workspace b.
+struct LeanPlan {
+    bool has_hard = false, has_map = false;
+    HardArgs ha{};
+    EdgeArgs ea{};
+    LeanArgs la{};
+    LeanMapArgs lm{};
+    EvalPlan ev;
+    LeanMergeArgs ma{};
+};
+
+void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, LeanPlan& P) {
     const int effect = d->effect;
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
     const LeanLayout f = lean_layout(g, effect);
     uint32_t* count = reinterpret_cast<uint32_t*>(b + f.count);
-    int st = mark(d, 0, s);
-    if (st) return st;
     const uint8_t* hard = nullptr;
     if (effect == MR_EFFECT_SHADOW) {
-        HardArgs ha{};
+        HardArgs& ha = P.ha;
         ha.depth = d->g.depth;
         ha.W = g.W;
         ha.H = g.H;
@@ -669,11 +714,11 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         ha.fL = d->shadow->light_focal_px;
         ha.bias = d->shadow->bias;
         ha.hard = b + f.hard;
-        if (launch_hard(ha, s) != hipSuccess) return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
+        P.has_hard = true;
         hard = b + f.hard;
     }
     // edges as bits, point-sampled level depth
-    EdgeArgs ea{};
+    EdgeArgs& ea = P.ea;
     ea.depth = d->g.depth;
     ea.normal = d->g.normal;
     ea.hard = hard;
@@ -696,9 +741,8 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         }
     }
     ea.zero_counts = count;
-    if (launch_edges(ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
     // stencils, ranks, lists (a_i at listed texels comes with the evaluation)
-    LeanArgs la{};
+    LeanArgs& la = P.la;
     la.nlev = g.nlev - 1;
     la.count = count;
     unsigned blk = 0;
@@ -721,11 +765,8 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         blk += lean_tiles(L.wpr, L.H);
     }
     la.nblk = blk;
-    // a_i is written by the evaluation kernel
-    if (launch_lean_masks(la, s) != hipSuccess)
-        return fail(MR_E_DEVICE, "lean mask kernels launch failed");
     if (d->level_map) {
-        LeanMapArgs lm{};
+        LeanMapArgs& lm = P.lm;
         lm.nlev = g.nlev - 1;
         for (int j = 0; j + 1 < g.nlev; ++j) {
             lm.Sb[j] = la.lv[j].Sb;
@@ -736,7 +777,7 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         lm.W = g.W;
         lm.H = g.H;
         lm.out = d->level_map;
-        if (launch_lean_level_map(lm, s) != hipSuccess) return fail(MR_E_DEVICE, "level map kernel launch failed");
+        P.has_map = true;
     }
     // per-level evaluation, list levels written by rank
     mr_masks m{};
@@ -752,12 +793,9 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
             lo[i - 1] = reinterpret_cast<float*>(b + f.cL);
         }
     }
-    if ((st = mark(d, 1, s))) return st;
-    st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s, /*compact=*/true, &la, d->level_dtype == MR_F16);
-    if (st) return st;
-    if ((st = mark(d, 2, s))) return st;
+    build_eval(effect, &d->g, &d->cam, g, &m, params, lo, /*compact=*/true, &la, d->level_dtype == MR_F16, P.ev);
     // merge by rank
-    LeanMergeArgs ma{};
+    LeanMergeArgs& ma = P.ma;
     ma.nlev = g.nlev;
     ma.W = g.W;
     ma.H = g.H;
@@ -789,8 +827,100 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
             ma.staged += L.rw * L.rh;
         }
     }
-    if (launch_lean_merge(ma, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
+}
+
+int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, hipStream_t s) {
+    LeanPlan P;
+    build_lean(d, g, params, b, P);
+    int st = mark(d, 0, s);
+    if (st) return st;
+    if (P.has_hard && launch_hard(P.ha, s) != hipSuccess) return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
+    if (launch_edges(P.ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
+    if (launch_lean_masks(P.la, s) != hipSuccess) return fail(MR_E_DEVICE, "lean mask kernels launch failed");
+    if (P.has_map && launch_lean_level_map(P.lm, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "level map kernel launch failed");
+    if ((st = mark(d, 1, s))) return st;
+    if ((st = launch_eval(P.ev, d->g.normal_dtype, d->g.color_dtype, s))) return st;
+    if ((st = mark(d, 2, s))) return st;
+    if (launch_lean_merge(P.ma, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
     return mark(d, 3, s);
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBatchMagic = 0x3142524du;  // "MRB1"
+
+struct BatchPlan {
+    uint32_t magic;
+    int n, effect, ndt, cdt, S, C;
+    bool hard, wide, c16, m4;
+    const EdgeArgs* te;
+    const LeanArgs* tl;
+    const void* tv;  // SsaoArgs or SsgiArgs
+    const LeanMergeArgs* tm;
+    const unsigned *edge_base, *edge_tx, *rank_base, *merge_base, *merge_tx;
+    unsigned edge_total, rank_total, eval_hint, merge_total;
+};
+static_assert(sizeof(BatchPlan) <= MR_BATCH_PLAN_BYTES, "batch plan exceeds MR_BATCH_PLAN_BYTES");
+
+struct BatchLayout {
+    size_t te, tl, tv, tm, bases, frames[MR_MAX_BATCH], bytes;
+};
+
+int check_batch(const mr_frame_desc* fr, int n, Geo* geos) {
+    if (!fr) return fail(MR_E_NULL, "frames are NULL");
+    if (n < 1 || n > MR_MAX_BATCH) return fail(MR_E_PARAM, "batch size %d outside [1, %d]", n, MR_MAX_BATCH);
+    const mr_frame_desc& f0 = fr[0];
+    if (f0.effect != MR_EFFECT_SSAO && f0.effect != MR_EFFECT_SSGI)
+        return fail(MR_E_PARAM, "batches take MR_EFFECT_SSAO or MR_EFFECT_SSGI frames");
+    for (int k = 0; k < n; ++k) {
+        const mr_frame_desc& d = fr[k];
+        if (d.effect != f0.effect) return fail(MR_E_PARAM, "frame %d: effect differs from frame 0", k);
+        if (!d.multires) return fail(MR_E_PARAM, "frame %d: batches are multi-resolution only", k);
+        if (d.level_map) return fail(MR_E_PARAM, "frame %d: level_map is not produced in batches", k);
+        const void* p = d.effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
+        const void* p0 = f0.effect == MR_EFFECT_SSAO ? (const void*)f0.ssao : (const void*)f0.ssgi;
+        int st = check_effect_params(d.effect, d.ssao, d.shadow, d.ssgi);
+        if (st) return fail_frame(st, k);
+        if (memcmp(p, p0, d.effect == MR_EFFECT_SSAO ? sizeof(mr_ssao_params) : sizeof(mr_ssgi_params)) != 0)
+            return fail(MR_E_PARAM, "frame %d: effect parameters differ from frame 0", k);
+        if (memcmp(&d.mp, &f0.mp, sizeof(mr_mask_params)) != 0)
+            return fail(MR_E_PARAM, "frame %d: mask parameters differ from frame 0", k);
+        if (d.g.normal_dtype != f0.g.normal_dtype || (d.effect == MR_EFFECT_SSGI && d.g.color_dtype != f0.g.color_dtype))
+            return fail(MR_E_DTYPE, "frame %d: input types differ from frame 0", k);
+        if (d.level_dtype != f0.level_dtype || (d.level_dtype != MR_F32 && d.level_dtype != MR_F16))
+            return fail(MR_E_DTYPE, "frame %d: level_dtype differs from frame 0 or is invalid", k);
+        if (!d.out) return fail(MR_E_NULL, "frame %d: out is NULL", k);
+        if (misaligned(d.out)) return fail(MR_E_PARAM, "frame %d: out is not 16-byte aligned", k);
+        Geo& g = geos[k];
+        st = check_geo(&d.cam, &d.mp, g);
+        if (!st) st = check_mask_params(&d.mp, g);
+        if (!st) st = check_gbuffer(&d.g, true, d.effect == MR_EFFECT_SSGI);
+        if (st) return fail_frame(st, k);
+        if (!lean_ok(g, &d.mp))
+            return fail(MR_E_PARAM, "frame %d: not on the compact frame path (coarsest level <= 4, width "
+                                    "divisible by 128, blur radii <= 8)", k);
+    }
+    return MR_OK;
+}
+
+BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos) {
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t nb) {
+        size_t o = off;
+        off += align256(nb);
+        return o;
+    };
+    L.te = take(sizeof(EdgeArgs) * n);
+    L.tl = take(sizeof(LeanArgs) * n);
+    L.tv = take((fr[0].effect == MR_EFFECT_SSAO ? sizeof(SsaoArgs) : sizeof(SsgiArgs)) * n);
+    L.tm = take(sizeof(LeanMergeArgs) * n);
+    L.bases = take(sizeof(unsigned) * 5 * (MR_MAX_BATCH + 1));
+    for (int k = 0; k < n; ++k) L.frames[k] = take(lean_layout(geos[k], fr[k].effect).bytes);
+    L.bytes = off;
+    return L;
 }
 
 }  // namespace
@@ -998,6 +1128,125 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     for (int k = 0; k < kMaxLevels; ++k) clo[k] = lo[k];
     if ((st = do_merge(g, &d->mp, &m, clo, C, d->out, s))) return st;
     return mark(d, 3, s);
+}
+
+size_t mr_batch_workspace_bytes(const mr_frame_desc* frames, int n) {
+    Geo geos[MR_MAX_BATCH];
+    if (check_batch(frames, n, geos)) return 0;
+    return batch_layout(frames, n, geos).bytes;
+}
+
+int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan, size_t plan_bytes,
+                   void* stream) {
+    Geo geos[MR_MAX_BATCH];
+    int st = check_batch(frames, n, geos);
+    if (st) return st;
+    if (!plan) return fail(MR_E_NULL, "plan is NULL");
+    if (plan_bytes < MR_BATCH_PLAN_BYTES) return fail(MR_E_PARAM, "plan needs %d bytes", MR_BATCH_PLAN_BYTES);
+    const BatchLayout BL = batch_layout(frames, n, geos);
+    if (!ws || ws_bytes < BL.bytes) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, BL.bytes);
+    if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
+    uint8_t* b = static_cast<uint8_t*>(ws);
+    const int effect = frames[0].effect;
+    // host copy of the tables region, then one copy to the device
+    std::vector<uint8_t> host(BL.frames[0], 0);
+    EdgeArgs* te = reinterpret_cast<EdgeArgs*>(host.data() + BL.te);
+    LeanArgs* tl = reinterpret_cast<LeanArgs*>(host.data() + BL.tl);
+    SsaoArgs* tsa = reinterpret_cast<SsaoArgs*>(host.data() + BL.tv);
+    SsgiArgs* tgi = reinterpret_cast<SsgiArgs*>(host.data() + BL.tv);
+    LeanMergeArgs* tm = reinterpret_cast<LeanMergeArgs*>(host.data() + BL.tm);
+    unsigned* bases = reinterpret_cast<unsigned*>(host.data() + BL.bases);
+    unsigned* edge_base = bases;
+    unsigned* edge_tx = bases + (MR_MAX_BATCH + 1);
+    unsigned* rank_base = bases + 2 * (MR_MAX_BATCH + 1);
+    unsigned* merge_base = bases + 3 * (MR_MAX_BATCH + 1);
+    unsigned* merge_tx = bases + 4 * (MR_MAX_BATCH + 1);
+    BatchPlan P{};
+    P.magic = kBatchMagic;
+    P.n = n;
+    P.effect = effect;
+    P.ndt = frames[0].g.normal_dtype;
+    P.cdt = frames[0].g.color_dtype;
+    P.C = effect == MR_EFFECT_SSGI ? 3 : 1;
+    P.c16 = frames[0].level_dtype == MR_F16;
+    unsigned et = 0, rt = 0, mt = 0, hint = 0;
+    for (int k = 0; k < n; ++k) {
+        const mr_frame_desc& d = frames[k];
+        const void* params = effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
+        LeanPlan L;
+        build_lean(&d, geos[k], params, b + BL.frames[k], L);
+        te[k] = L.ea;
+        tl[k] = L.la;
+        if (effect == MR_EFFECT_SSAO)
+            tsa[k] = L.ev.sa;
+        else
+            tgi[k] = L.ev.gi;
+        tm[k] = L.ma;
+        unsigned tx, nt;
+        bool wide;
+        edges_grid(geos[k].W, geos[k].H, geos[k].N, wide, tx, nt);
+        P.wide = wide;  // the same for all frames (same number of levels)
+        edge_base[k] = et;
+        edge_tx[k] = tx;
+        et += nt;
+        rank_base[k] = rt;
+        rt += L.la.nblk;
+        const unsigned mx = (unsigned)((geos[k].W + kMergeTW - 1) / kMergeTW);
+        merge_base[k] = mt;
+        merge_tx[k] = mx;
+        mt += mx * (unsigned)((geos[k].H + kMergeTH - 1) / kMergeTH);
+        hint += L.ev.hint + 1024u;  // + padding of the levels' and frame's item ranges
+        if (k == 0) {
+            P.m4 = merge4_applies(L.ma);
+            P.S = effect == MR_EFFECT_SSAO ? L.ev.sa.S : L.ev.gi.S;
+        }
+    }
+    edge_base[n] = et;
+    rank_base[n] = rt;
+    merge_base[n] = mt;
+    P.edge_total = et;
+    P.rank_total = rt;
+    P.merge_total = mt;
+    P.eval_hint = hint;
+    P.te = reinterpret_cast<const EdgeArgs*>(b + BL.te);
+    P.tl = reinterpret_cast<const LeanArgs*>(b + BL.tl);
+    P.tv = b + BL.tv;
+    P.tm = reinterpret_cast<const LeanMergeArgs*>(b + BL.tm);
+    const unsigned* db = reinterpret_cast<const unsigned*>(b + BL.bases);
+    P.edge_base = db;
+    P.edge_tx = db + (MR_MAX_BATCH + 1);
+    P.rank_base = db + 2 * (MR_MAX_BATCH + 1);
+    P.merge_base = db + 3 * (MR_MAX_BATCH + 1);
+    P.merge_tx = db + 4 * (MR_MAX_BATCH + 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(b, host.data(), host.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "batch table copy failed: %s", hipGetErrorString(e));
+    memcpy(plan, &P, sizeof(P));
+    return MR_OK;
+}
+
+int mr_batch_run(const void* plan, void* stream) {
+    if (!plan) return fail(MR_E_NULL, "plan is NULL");
+    BatchPlan P;
+    memcpy(&P, plan, sizeof(P));
+    if (P.magic != kBatchMagic || P.n < 1 || P.n > MR_MAX_BATCH)
+        return fail(MR_E_PARAM, "plan was not filled by mr_batch_setup");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (launch_edges_batch(P.te, P.edge_base, P.edge_tx, P.n, P.edge_total, P.ndt, false, P.wide, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "batched edge kernel launch failed");
+    if (launch_lean_masks_batch(P.tl, P.rank_base, P.n, P.rank_total, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "batched rank kernel launch failed");
+    hipError_t e;
+    if (P.effect == MR_EFFECT_SSAO)
+        e = launch_ssao_batch(static_cast<const SsaoArgs*>(P.tv), P.n, P.S, P.ndt, P.eval_hint, s);
+    else
+        e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.ndt, P.cdt, P.eval_hint, s);
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "batched evaluation kernel launch failed");
+    if (launch_lean_merge_batch(P.tm, P.merge_base, P.merge_tx, P.n, P.merge_total, P.C, P.c16, P.m4, s) !=
+        hipSuccess)
+        return fail(MR_E_DEVICE, "batched merge kernel launch failed");
+    return MR_OK;
 }
 
 const char* mr_status_string(int status) {

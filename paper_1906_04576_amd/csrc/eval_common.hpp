@@ -81,6 +81,30 @@ __device__ __forceinline__ ChunkRange chunk_range(unsigned nchunks) {
     return {lo + k, hi, per};
 }
 
+// Frames of one batched launch at most.
+constexpr int kMaxBatch = 64;
+
+// cbase[f] = first chunk (of 256 items) of frame f in a batch's item space,
+// cbase[n] = total: each frame's item range (from its device counts) rounded
+// up to whole chunks.  Computed by the first wave; ends with a barrier.
+template <typename Args>
+__device__ __forceinline__ void batch_chunk_bases(const Args* T, int n, unsigned* cbase) {
+    if (threadIdx.x < 64) {
+        const int f = threadIdx.x;
+        unsigned cnt = 0;
+        if (f < n) cnt = (item_total(make_item_map(T[f].c)) + 255u) / 256u;
+        unsigned inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned o = __shfl_up(inc, d, 64);
+            if (f >= d) inc += o;
+        }
+        if (f == 0) cbase[0] = 0;
+        if (f < n) cbase[f + 1] = inc;
+    }
+    __syncthreads();
+}
+
 // Sample sets of at most this many entries are staged in LDS once per
 // workgroup; the sample loops then read them with uniform LDS addresses
 // instead of a vector load (and its full wait) per sample.

@@ -99,10 +99,9 @@ __device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
 // the order they finish; the rank of every texel is stored with it (woff),
 // which is all the merge needs, and each texel's result does not depend on
 // where in the list it sits.  The counts are zeroed by the edge kernel.
-__global__ __launch_bounds__(256) void k_lean_rank(LeanArgs A) {
+__device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
     __shared__ unsigned wtot[4];
     __shared__ unsigned tile_base;
-    const unsigned b = blockIdx.x;
     const int l = lean_level(A, b);
     const LeanLevel& L = A.lv[l];
     __shared__ unsigned eb[kStageRows][kStageCols];
@@ -142,8 +141,23 @@ __global__ __launch_bounds__(256) void k_lean_rank(LeanArgs A) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_lean_rank(LeanArgs A) { rank_block(A, blockIdx.x); }
+
+// frames of a batch: blk_base[f] = first block of frame f, blk_base[n] = total
+__global__ __launch_bounds__(256) void k_lean_rank_batch(const LeanArgs* T, const unsigned* blk_base, int n) {
+    int f = 0;
+    for (int k = 1; k < n; ++k) f += blockIdx.x >= blk_base[k] ? 1 : 0;
+    rank_block(T[f], blockIdx.x - blk_base[f]);
+}
+
 hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s) {
     if (a.nblk) hipLaunchKernelGGL(k_lean_rank, dim3(a.nblk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lean_masks_batch(const LeanArgs* T, const unsigned* blk_base, int n, unsigned total,
+                                   hipStream_t s) {
+    if (total) hipLaunchKernelGGL(k_lean_rank_batch, dim3(total), dim3(256), 0, s, T, blk_base, n);
     return hipGetLastError();
 }
 
@@ -188,12 +202,11 @@ __device__ __forceinline__ float cval(const void* c, long long i) {
 }
 
 template <int C, typename VT>
-__global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
+__device__ __forceinline__ void merge_tile(const LeanMergeArgs& a, unsigned tile, unsigned tiles_x) {
     __shared__ float la[kMergeLDS];
     __shared__ uint8_t ls[kMergeLDS];
     __shared__ float lc[C][kMergeLDS];
     __shared__ int lvl_any[kMaxLevels];  // some staged a > 0 in the level's region
-    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
     const int x0 = (int)(tile % tiles_x) * kMergeTW;
     const int y0 = (int)(tile / tiles_x) * kMergeTH;
     const int nl = a.nlev, t = threadIdx.x;
@@ -504,14 +517,13 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
 }
 
 template <int C, typename VT>
-__global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
+__device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned tile, unsigned tiles_x) {
     using R2 = Region4<1>;
     using R3 = Region4<2>;
     using R4 = Region4<3>;
     __shared__ float la2[R2::n], la3[R3::n];
     __shared__ float lc2[C][R2::n], lc3[C][R3::n], lc4[C][R4::n];
     __shared__ int any2, any3;
-    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
     const int x0 = (int)(tile % tiles_x) * kMergeTW;
     const int y0 = (int)(tile / tiles_x) * kMergeTH;
     const int t = threadIdx.x;
@@ -651,6 +663,29 @@ __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned t
         *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
 }
 
+template <int C, typename VT>
+__global__ __launch_bounds__(256) void k_lean_merge(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
+    merge_tile<C, VT>(a, xcd_remap(blockIdx.x, ntiles), tiles_x);
+}
+
+template <int C, typename VT>
+__global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
+    merge4_tile<C, VT>(a, xcd_remap(blockIdx.x, ntiles), tiles_x);
+}
+
+// frames of a batch: tile_base[f] = first merge tile of frame f
+template <int C, typename VT, bool M4>
+__global__ __launch_bounds__(256) void k_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base,
+                                                          const unsigned* tiles_x, int n) {
+    const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
+    int f = 0;
+    for (int k = 1; k < n; ++k) f += g >= tile_base[k] ? 1 : 0;
+    if (M4)
+        merge4_tile<C, VT>(T[f], g - tile_base[f], tiles_x[f]);
+    else
+        merge_tile<C, VT>(T[f], g - tile_base[f], tiles_x[f]);
+}
+
 // levels 1, 2, 3, 4 with level 1 by rank (the common 4-level frame)
 bool merge4_applies(const LeanMergeArgs& a) {
     if (a.nlev != 4 || !a.fine1 || (a.W & 3) != 0) return false;
@@ -679,6 +714,31 @@ hipError_t launch_lean_merge_t(const LeanMergeArgs& a, hipStream_t s) {
 
 hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s) {
     return a.c16 ? launch_lean_merge_t<_Float16>(a, s) : launch_lean_merge_t<float>(a, s);
+}
+
+hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
+                                   unsigned total, int C, bool c16, bool m4, hipStream_t s) {
+#define MR_MB(CC, VT, M) \
+    hipLaunchKernelGGL((k_lean_merge_batch<CC, VT, M>), dim3(total), dim3(256), 0, s, T, tile_base, tiles_x, n)
+    if (C == 3) {
+        if (c16) {
+            if (m4) MR_MB(3, _Float16, true);
+            else MR_MB(3, _Float16, false);
+        } else {
+            if (m4) MR_MB(3, float, true);
+            else MR_MB(3, float, false);
+        }
+    } else {
+        if (c16) {
+            if (m4) MR_MB(1, _Float16, true);
+            else MR_MB(1, _Float16, false);
+        } else {
+            if (m4) MR_MB(1, float, true);
+            else MR_MB(1, float, false);
+        }
+    }
+#undef MR_MB
+    return hipGetLastError();
 }
 
 }  // namespace mr

@@ -310,11 +310,11 @@ __device__ __forceinline__ float dpp_shl1(float own, float src) {
 // that a block reads 1 KB runs of every row; levels up to 4 only (the 8 x 8
 // pooling blocks stay inside one wave).  Otherwise they are stacked (64 x 32
 // tile) and levels 5 and 6 are pooled across the waves through LDS.
+// One tile of the edge image (`first`: the block that zeroes the counters).
 template <typename NT, bool HARD, bool BITS, bool WIDE>
-__global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
+__device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, unsigned tiles_x, bool first) {
     __shared__ uint8_t p4[4][8];
-    if (a.zero_counts && blockIdx.x == 0 && threadIdx.x < kMaxLevels) a.zero_counts[threadIdx.x] = 0u;
-    const unsigned tile = xcd_remap(blockIdx.x, ntiles);
+    if (a.zero_counts && first && threadIdx.x < kMaxLevels) a.zero_counts[threadIdx.x] = 0u;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int x0 = WIDE ? (int)(tile % tiles_x) * (4 * kEdgeTW) + wave * kEdgeTW : (int)(tile % tiles_x) * kEdgeTW;
     const int y0 = WIDE ? (int)(tile / tiles_x) * 8 : (int)(tile / tiles_x) * kEdgeTH;
@@ -526,6 +526,55 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
                 for (int j = 0; j < 4; ++j) o |= p4[w][4 * t + j];
             if (X < a.Wi[5] && Y < a.Hi[5]) a.Ei[5][(unsigned)Y * (unsigned)a.Wi[5] + (unsigned)X] = o;
         }
+    }
+}
+
+template <typename NT, bool HARD, bool BITS, bool WIDE>
+__global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
+    edges_tile<NT, HARD, BITS, WIDE>(a, xcd_remap(blockIdx.x, ntiles), tiles_x, blockIdx.x == 0);
+}
+
+// Frames of a batch: one grid over all frames' tiles (tile_base[f] = first
+// tile of frame f, tile_base[n] = total); tiles_x[f] per frame.
+template <typename NT, bool HARD, bool BITS, bool WIDE>
+__global__ __launch_bounds__(256) void k_edges_batch(const EdgeArgs* T, const unsigned* tile_base,
+                                                     const unsigned* tiles_x, int n) {
+    const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
+    int f = 0;
+    for (int k = 1; k < n; ++k) f += g >= tile_base[k] ? 1 : 0;
+    const unsigned local = g - tile_base[f];
+    edges_tile<NT, HARD, BITS, WIDE>(T[f], local, tiles_x[f], local == 0);
+}
+
+hipError_t launch_edges_batch(const EdgeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
+                              unsigned total, int normal_dtype, bool hard, bool wide, hipStream_t s) {
+    // compact frame path only: bit-packed edges (BITS) and widths divisible by 4
+#define MR_EB(NT, HD, WD) \
+    hipLaunchKernelGGL((k_edges_batch<NT, HD, true, WD>), dim3(total), dim3(256), 0, s, T, tile_base, tiles_x, n)
+    const bool f16 = normal_dtype == MR_F16;
+    if (wide) {
+        if (f16 && hard) MR_EB(_Float16, true, true);
+        else if (f16) MR_EB(_Float16, false, true);
+        else if (hard) MR_EB(float, true, true);
+        else MR_EB(float, false, true);
+    } else {
+        if (f16 && hard) MR_EB(_Float16, true, false);
+        else if (f16) MR_EB(_Float16, false, false);
+        else if (hard) MR_EB(float, true, false);
+        else MR_EB(float, false, false);
+    }
+#undef MR_EB
+    return hipGetLastError();
+}
+
+void edges_grid(int W, int H, int num_levels, bool& wide, unsigned& tiles_x, unsigned& ntiles) {
+    wide = num_levels <= 4;
+    if (wide) {
+        tiles_x = (unsigned)((W + 4 * kEdgeTW - 1) / (4 * kEdgeTW));
+        ntiles = tiles_x * (unsigned)((H + 7) / 8);
+    } else {
+        tiles_x = (unsigned)((W + kEdgeTW - 1) / kEdgeTW);
+        ntiles = tiles_x * (unsigned)((H + kEdgeTH - 1) / kEdgeTH);
     }
 }
 

@@ -121,34 +121,64 @@ __device__ __forceinline__ float ssao_texel(const SsaoArgs& a, const EvalLevel& 
     return (float)occ / (float)a.S;
 }
 
+// one item (a listed texel, or a texel of a dense level)
+template <typename NT, bool KLDS, bool AL>
+__device__ __forceinline__ void ssao_item(const SsaoArgs& a, const ItemMap& m, unsigned item, const float* ks,
+                                          const float* eg, float kmax) {
+    const NT* nrm = static_cast<const NT*>(a.c.normal);
+    const unsigned plane = (unsigned)a.c.plane;
+    const int j = item_level(m, item);
+    const EvalLevel& L = a.c.lv[j];
+    const unsigned local = item_local(m, item, j);
+    if (local == ~0u) return;  // padding of the level's item range
+    const unsigned t = L.list ? L.list[local] : local;
+    if (t >= L.dense_n) return;  // malformed list entry
+    const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
+    if (AL && L.ac) L.ac[local] = alpha_dispatch(L, eg + j * kEgStride, x, y);
+    const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
+    float res = 0.0f;
+    if (valid_depth(z)) {
+        if (KLDS)
+            res = ssao_texel<NT, !AL>(a, L, nrm, plane, ks, kmax, x, y, z);
+        else
+            res = ssao_texel<NT, !AL>(a, L, nrm, plane, a.kernel, kmax, x, y, z);
+    }
+    store_out(L, L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x, res);
+}
+
 template <typename NT, bool KLDS, bool AL>
 __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, const float* eg, float kmax) {
     const ItemMap m = make_item_map(a.c);
     const unsigned total = item_total(m);
-    const NT* nrm = static_cast<const NT*>(a.c.normal);
-    const unsigned plane = (unsigned)a.c.plane;
     const ChunkRange cr = chunk_range((total + 255) / 256);
     for (unsigned c = cr.first; c < cr.end; c += cr.step) {
         const unsigned item = c * 256u + threadIdx.x;
-        if (item >= total) continue;
-        const int j = item_level(m, item);
-        const EvalLevel& L = a.c.lv[j];
-        const unsigned local = item_local(m, item, j);
-        if (local == ~0u) continue;  // padding of the level's item range
-        const unsigned t = L.list ? L.list[local] : local;
-        if (t >= L.dense_n) continue;  // malformed list entry
-        const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
-        if (AL && L.ac) L.ac[local] = alpha_dispatch(L, eg + j * kEgStride, x, y);
-        const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
-        float res = 0.0f;
-        if (valid_depth(z)) {
-            if (KLDS)
-                res = ssao_texel<NT, !AL>(a, L, nrm, plane, ks, kmax, x, y, z);
-            else
-                res = ssao_texel<NT, !AL>(a, L, nrm, plane, a.kernel, kmax, x, y, z);
-        }
-        store_out(L, L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x, res);
+        if (item < total) ssao_item<NT, KLDS, AL>(a, m, item, ks, eg, kmax);
     }
+}
+
+// Per block: the blur taps (AL) and, KLDS, the S <= kLdsSamples samples in
+// LDS; returns the largest |component| of the samples (+inf when not staged).
+template <bool AL, bool KLDS>
+__device__ __forceinline__ float ssao_stage(const SsaoArgs& a, float* ks, float* eg) {
+    __shared__ unsigned kmax_bits;  // as bits: all values >= 0
+    if (AL) stage_taps(a.c, eg);
+    if (!KLDS) {
+        __syncthreads();
+        return __builtin_inff();
+    }
+    if (threadIdx.x == 0) kmax_bits = 0u;
+    __syncthreads();
+    unsigned m = 0u;
+    for (int i = threadIdx.x; i < 3 * a.S; i += 256) {
+        const float v = a.kernel[i];
+        ks[i] = v;
+        m = max(m, __float_as_uint(fabsf(v)));
+    }
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+    if (__lane_id() == 0) atomicMax(&kmax_bits, m);
+    __syncthreads();
+    return __uint_as_float(kmax_bits);
 }
 
 // KLDS: the S <= kLdsSamples samples are staged in LDS (else read from
@@ -157,25 +187,47 @@ template <typename NT, bool AL, bool KLDS>
 __global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
     __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
-    __shared__ unsigned kmax_bits;  // max |component| of the staged samples (as bits: all >= 0)
-    if (AL) stage_taps(a.c, eg);
-    if (KLDS) {
-        if (threadIdx.x == 0) kmax_bits = 0u;
-        __syncthreads();
-        unsigned m = 0u;
-        for (int i = threadIdx.x; i < 3 * a.S; i += 256) {
-            const float v = a.kernel[i];
-            ks[i] = v;
-            m = max(m, __float_as_uint(fabsf(v)));
-        }
-        for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
-        if (__lane_id() == 0) atomicMax(&kmax_bits, m);
-        __syncthreads();
-        ssao_items<NT, true, AL>(a, ks, eg, __uint_as_float(kmax_bits));
-    } else {
-        __syncthreads();
-        ssao_items<NT, false, AL>(a, ks, eg, __builtin_inff());
+    const float kmax = ssao_stage<AL, KLDS>(a, ks, eg);
+    ssao_items<NT, KLDS, AL>(a, ks, eg, kmax);
+}
+
+// Frames of a batch (same samples, mask and effect parameters): one item
+// space over all frames, each frame's range padded to whole chunks of 256,
+// swept by a resident grid like the single-frame launch.
+template <typename NT, bool AL, bool KLDS>
+__global__ __launch_bounds__(256) void k_ssao_batch(const SsaoArgs* T, int n) {
+    __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
+    __shared__ float eg[kMaxLevels * kEgStride];
+    __shared__ unsigned cbase[kMaxBatch + 1];
+    const float kmax = ssao_stage<AL, KLDS>(T[0], ks, eg);
+    batch_chunk_bases(T, n, cbase);
+    const ChunkRange cr = chunk_range(cbase[n]);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        int f = 0;
+        for (int k = 1; k < n; ++k) f += c >= cbase[k] ? 1 : 0;
+        const SsaoArgs& a = T[f];
+        const ItemMap m = make_item_map(a.c);
+        const unsigned item = (c - cbase[f]) * 256u + threadIdx.x;
+        if (item < item_total(m)) ssao_item<NT, KLDS, AL>(a, m, item, ks, eg, kmax);
     }
+}
+
+hipError_t launch_ssao_batch(const SsaoArgs* T, int n, int S, int normal_dtype, unsigned total_hint,
+                             hipStream_t s) {
+    // the compact frame path fuses a_i into the evaluation
+    const bool lds = S <= kLdsSamples;
+#define MR_SB(NT, KL) \
+    hipLaunchKernelGGL((k_ssao_batch<NT, true, KL>), dim3(eval_blocks<k_ssao_batch<NT, true, KL>>(total_hint)), \
+                       dim3(256), 0, s, T, n)
+    if (normal_dtype == MR_F16) {
+        if (lds) MR_SB(_Float16, true);
+        else MR_SB(_Float16, false);
+    } else {
+        if (lds) MR_SB(float, true);
+        else MR_SB(float, false);
+    }
+#undef MR_SB
+    return hipGetLastError();
 }
 
 hipError_t launch_ssao(const SsaoArgs& a, int normal_dtype, unsigned total_hint, hipStream_t s) {

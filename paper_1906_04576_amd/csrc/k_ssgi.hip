@@ -9,10 +9,10 @@
 
 namespace mr {
 
+// one item (a listed texel, or a texel of a dense level)
 template <typename NT, typename CT, bool AL, typename KP>
-__device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float* eg) {
-    const ItemMap m = make_item_map(a.c);
-    const unsigned total = item_total(m);
+__device__ __forceinline__ void ssgi_item(const SsgiArgs& a, const ItemMap& m, unsigned item, KP K,
+                                          const float* eg) {
     const NT* nrm = static_cast<const NT*>(a.c.normal);
     const CT* col = static_cast<const CT*>(a.c.color);
     const long long plane = a.c.plane;
@@ -21,16 +21,13 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
     const float rmin = 0.1f * r;
     const float rmin2 = rmin * rmin;
     const float scale = (r * r) / (float)S;
-    const ChunkRange cr = chunk_range((total + 255) / 256);
-    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
-        const unsigned item = c * 256u + threadIdx.x;
-        if (item >= total) continue;
+    {
         const int j = item_level(m, item);
         const EvalLevel& L = a.c.lv[j];
         const unsigned local = item_local(m, item, j);
-        if (local == ~0u) continue;  // padding of the level's item range
+        if (local == ~0u) return;  // padding of the level's item range
         const unsigned t = L.list ? L.list[local] : local;
-        if (t >= L.dense_n) continue;  // malformed list entry
+        if (t >= L.dense_n) return;  // malformed list entry
         const int y = (int)(t / (unsigned)L.W), x = (int)(t - (unsigned)y * (unsigned)L.W);
         if (AL && L.ac) L.ac[local] = alpha_dispatch(L, eg + j * kEgStride, x, y);
         const float z = L.z[(unsigned)y * L.zpy + (unsigned)x * L.zpx];
@@ -86,19 +83,76 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
     }
 }
 
+template <typename NT, typename CT, bool AL, typename KP>
+__device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float* eg) {
+    const ItemMap m = make_item_map(a.c);
+    const unsigned total = item_total(m);
+    const ChunkRange cr = chunk_range((total + 255) / 256);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        const unsigned item = c * 256u + threadIdx.x;
+        if (item < total) ssgi_item<NT, CT, AL>(a, m, item, K, eg);
+    }
+}
+
+// per block: blur taps (AL) and the samples when S <= kLdsSamples; true when staged
+template <bool AL>
+__device__ __forceinline__ bool ssgi_stage(const SsgiArgs& a, float* ks, float* eg) {
+    if (AL) stage_taps(a.c, eg);
+    const bool staged = a.S <= kLdsSamples;  // uniform
+    if (staged)
+        for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
+    __syncthreads();
+    return staged;
+}
+
 template <typename NT, typename CT, bool AL>
 __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
     __shared__ float ks[3 * kLdsSamples];
     __shared__ float eg[kMaxLevels * kEgStride];
-    if (AL) stage_taps(a.c, eg);
-    if (a.S <= kLdsSamples) {  // uniform
-        for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
-        __syncthreads();
+    if (ssgi_stage<AL>(a, ks, eg))
         ssgi_items<NT, CT, AL>(a, (const float*)ks, (const float*)eg);
-    } else {
-        __syncthreads();
+    else
         ssgi_items<NT, CT, AL>(a, a.kernel, (const float*)eg);
+}
+
+// frames of a batch (see k_ssao_batch)
+template <typename NT, typename CT>
+__global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* T, int n) {
+    __shared__ float ks[3 * kLdsSamples];
+    __shared__ float eg[kMaxLevels * kEgStride];
+    __shared__ unsigned cbase[kMaxBatch + 1];
+    const bool staged = ssgi_stage<true>(T[0], ks, eg);
+    batch_chunk_bases(T, n, cbase);
+    const ChunkRange cr = chunk_range(cbase[n]);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        int f = 0;
+        for (int k = 1; k < n; ++k) f += c >= cbase[k] ? 1 : 0;
+        const SsgiArgs& a = T[f];
+        const ItemMap m = make_item_map(a.c);
+        const unsigned item = (c - cbase[f]) * 256u + threadIdx.x;
+        if (item >= item_total(m)) continue;
+        if (staged)
+            ssgi_item<NT, CT, true>(a, m, item, (const float*)ks, (const float*)eg);
+        else
+            ssgi_item<NT, CT, true>(a, m, item, a.kernel, (const float*)eg);
     }
+}
+
+hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int color_dtype, unsigned total_hint,
+                             hipStream_t s) {
+#define MR_GB(NT, CT) \
+    hipLaunchKernelGGL((k_ssgi_batch<NT, CT>), dim3(eval_blocks<k_ssgi_batch<NT, CT>>(total_hint)), dim3(256), 0, \
+                       s, T, n)
+    if (normal_dtype == MR_F16 && color_dtype == MR_F16)
+        MR_GB(_Float16, _Float16);
+    else if (normal_dtype == MR_F16)
+        MR_GB(_Float16, float);
+    else if (color_dtype == MR_F16)
+        MR_GB(float, _Float16);
+    else
+        MR_GB(float, float);
+#undef MR_GB
+    return hipGetLastError();
 }
 
 hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,

@@ -287,5 +287,21 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s);
 hipError_t launch_lean_level_map(const LeanMapArgs& a, hipStream_t s);
 hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s);
+bool merge4_applies(const LeanMergeArgs& a);
+
+// edge kernel tiling for an image (the choice launch_edges makes)
+void edges_grid(int W, int H, int num_levels, bool& wide, unsigned& tiles_x, unsigned& ntiles);
+
+// batched frames: argument tables in device memory, one launch per stage
+hipError_t launch_edges_batch(const EdgeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
+                              unsigned total, int normal_dtype, bool hard, bool wide, hipStream_t s);
+hipError_t launch_lean_masks_batch(const LeanArgs* T, const unsigned* blk_base, int n, unsigned total,
+                                   hipStream_t s);
+hipError_t launch_ssao_batch(const SsaoArgs* T, int n, int S, int normal_dtype, unsigned total_hint,
+                             hipStream_t s);
+hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int color_dtype, unsigned total_hint,
+                             hipStream_t s);
+hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
+                                   unsigned total, int C, bool c16, bool m4, hipStream_t s);
 
 }  // namespace mr

@@ -24,6 +24,8 @@ MR_F32, MR_F16 = 0, 1
 MR_EFFECT_SSAO, MR_EFFECT_SHADOW, MR_EFFECT_SSGI = 0, 1, 2
 MR_WS_MASKS = -1
 MR_FRAME_EVENTS = 4
+MR_MAX_BATCH = 64
+MR_BATCH_PLAN_BYTES = 512
 EFFECTS = {"ssao": MR_EFFECT_SSAO, "shadow": MR_EFFECT_SHADOW, "ssgi": MR_EFFECT_SSGI}
 
 c_float6 = ctypes.c_float * MR_MAX_LEVELS
@@ -103,6 +105,10 @@ SIGNATURES = {
     "mr_upsample_merge": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                          ctypes.POINTER(mr_masks), ctypes.POINTER(c_ptr6), ctypes.c_int, _P, _P]),
     "mr_frame": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P, ctypes.c_size_t, _P]),
+    "mr_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mr_frame_desc), ctypes.c_int]),
+    "mr_batch_setup": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), ctypes.c_int, _P, ctypes.c_size_t, _P,
+                                      ctypes.c_size_t, _P]),
+    "mr_batch_run": (ctypes.c_int, [_P, _P]),
     "mr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mr_last_error": (ctypes.c_char_p, []),
     "mr_version": (ctypes.c_int, []),
@@ -526,6 +532,54 @@ def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True
              level_map=None, stream=None, level_dtype=torch.float32):
     return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map,
                        level_dtype=level_dtype)(stream)
+
+
+class Batch:
+    """Frames of one effect (same mask and effect parameters, any sizes)
+    run with one launch per stage (mr_batch_setup / mr_batch_run).
+    frames: list of FrameRunner-style argument dicts:
+        dict(depth=, normal=, focal=, color=None, out=None)
+    The frame tensors must stay alive and at the same addresses."""
+
+    def __init__(self, effect, frames, mp: MaskParams, params, level_dtype=torch.float32, stream=None):
+        self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
+        n = len(frames)
+        descs = (mr_frame_desc * n)()
+        self.outs, self._keep = [], [params]
+        C = 3 if self.effect == MR_EFFECT_SSGI else 1
+        for k, f in enumerate(frames):
+            depth, normal, color = f["depth"], f["normal"], f.get("color")
+            H, W = depth.shape
+            out = f.get("out")
+            if out is None:
+                out = torch.empty((C, H, W) if C > 1 else (H, W), dtype=torch.float32, device=depth.device)
+            d = descs[k]
+            d.effect = self.effect
+            d.multires = 1
+            d.g = gbuffer(depth, normal, color)
+            d.cam = camera(W, H, f["focal"])
+            d.mp = mp.c()
+            if self.effect == MR_EFFECT_SSAO:
+                d.ssao = ctypes.pointer(params)
+            else:
+                d.ssgi = ctypes.pointer(params)
+            d.out = _ptr(out)
+            d.level_dtype = MR_F16 if level_dtype == torch.float16 else MR_F32
+            self.outs.append(out)
+            self._keep += [depth, normal, color]
+        self.descs = descs
+        nws = lib().mr_batch_workspace_bytes(descs, n)
+        if nws == 0:
+            _check(MR_E_PARAM)
+        self.workspace = torch.empty(nws, dtype=torch.uint8, device=frames[0]["depth"].device)
+        self.plan = (ctypes.c_uint8 * MR_BATCH_PLAN_BYTES)()
+        _check(lib().mr_batch_setup(descs, n, _ptr(self.workspace), nws, ctypes.cast(self.plan, ctypes.c_void_p),
+                                    MR_BATCH_PLAN_BYTES, _stream(stream)))
+        self._run = lib().mr_batch_run
+
+    def __call__(self, stream=None):
+        _check(self._run(ctypes.cast(self.plan, ctypes.c_void_p), _stream(stream)))
+        return self.outs
 
 
 class Prepared:

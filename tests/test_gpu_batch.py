@@ -1,0 +1,180 @@
+"""Batches of uneven frames (one launch per stage for all frames): every
+frame's output is bit-identical to the same frame run alone through mr_frame
+(which the parity tests tie to the oracle), one frame is also checked against
+the oracle directly, inputs may change between runs, and a HIP graph of a
+batch run replays to the eager result."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from paper_1906_04576_amd import mr
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+COS25 = float(np.float32(math.cos(math.radians(25.0))))
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# uneven sizes, all on the compact path (width divisible by 128), ragged
+# heights (not multiples of the 16-row merge and rank tiles)
+SIZES = ((640, 360), (384, 200), (1280, 720), (256, 128), (128, 64), (512, 296))
+_scenes = {}
+
+
+def scene(W, H, k):
+    key = (W, H, k)
+    if key not in _scenes:
+        s = scenegen.make_scene(20 + k, 60, 15)
+        gb = scenegen.render_gbuffer(s, scenegen.orbit_view(k % 8), W, H)
+        col = scenegen.lambert_color(s, gb)
+        _scenes[key] = dict(gb=gb, col=col, depth=torch.from_numpy(gb.depth).to(DEV),
+                            normal=torch.from_numpy(gb.normal).to(DEV), color=torch.from_numpy(col).to(DEV))
+    return _scenes[key]
+
+
+def mask_params(effect, lib=mr):
+    t = scenegen.TABLE1[effect]
+    en = 0b1101 if effect == "ssgi" else 0b1111  # Table 1: SSGI leaves level 2 out
+    return lib.MaskParams(num_levels=4, level_enable=en, sigma2=t["sigma2"], weight=t["weight"], normal_cos=COS25)
+
+
+def effect_params(effect, S=16):
+    K = scenegen.ssao_kernel(S)
+    r = 1.0 if effect == "ssao" else 2.0
+    return K, r, mr.ssao_params(torch.from_numpy(K).to(DEV), r, 0.02)
+
+
+def frames_for(effect, sizes, f16_normals=False):
+    fr = []
+    for k, (W, H) in enumerate(sizes):
+        sc = scene(W, H, k)
+        n = sc["normal"].half() if f16_normals else sc["normal"]
+        fr.append(dict(depth=sc["depth"], normal=n, focal=float(sc["gb"].focal),
+                       color=sc["color"] if effect == "ssgi" else None))
+    return fr
+
+
+def alone(effect, f, mp, params, level_dtype=torch.float32):
+    out = mr.mr_frame(effect, f["depth"], f["normal"], f["focal"], mp, params, multires=True, color=f.get("color"),
+                      level_dtype=level_dtype)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("effect,level_dtype,f16n", [("ssao", torch.float32, False), ("ssgi", torch.float32, False),
+                                                     ("ssao", torch.float16, True), ("ssgi", torch.float16, False)])
+def test_batch_equals_frames_alone(effect, level_dtype, f16n):
+    mp = mask_params(effect)
+    _, _, p = effect_params(effect)
+    fr = frames_for(effect, SIZES, f16n)
+    log(f"[gpu] batch {effect} {level_dtype} f16 normals={f16n} sizes {SIZES}")
+    b = mr.Batch(effect, fr, mp, p, level_dtype=level_dtype)
+    outs = b()
+    torch.cuda.synchronize()
+    for f, o, sz in zip(fr, outs, SIZES):
+        ref = alone(effect, f, mp, p, level_dtype)
+        assert torch.isfinite(o).all()
+        assert torch.equal(o, ref), (effect, sz, (o - ref).abs().max().item())
+
+
+def test_batch_frame_matches_oracle():
+    """The 384x200 frame of an SSGI batch against the oracle's frame."""
+    effect = "ssgi"
+    mp = mask_params(effect)
+    K, r, p = effect_params(effect)
+    fr = frames_for(effect, SIZES)
+    log("[gpu] batch ssgi vs oracle")
+    outs = mr.Batch(effect, fr, mp, p)()
+    torch.cuda.synchronize()
+    sc = scene(384, 200, 1)
+    gb = sc["gb"]
+    ref = oracle.frame(effect, gb.depth, gb.normal, gb.focal, mask_params(effect, oracle), oracle.SSGIParams(K, r, 0.02),
+                       color=sc["col"].astype(np.float32), dtype=np.float32)
+    got = outs[1].cpu().numpy()
+    assert np.abs(got - ref.out).max() <= 1e-4
+    assert np.array_equal(got, ref.out)
+
+
+def test_inputs_may_change_between_runs():
+    effect = "ssao"
+    mp = mask_params(effect)
+    _, _, p = effect_params(effect)
+    sizes = ((384, 200), (640, 360))
+    depth = [scene(W, H, k)["depth"].clone() for k, (W, H) in enumerate(sizes)]
+    normal = [scene(W, H, k)["normal"].clone() for k, (W, H) in enumerate(sizes)]
+    fr = [dict(depth=d, normal=n, focal=float(scene(W, H, k)["gb"].focal)) for k, ((W, H), d, n) in
+          enumerate(zip(sizes, depth, normal))]
+    log("[gpu] batch with changing inputs")
+    b = mr.Batch(effect, fr, mp, p)
+    first = [o.clone() for o in b()]
+    # new content at the same addresses: another view of frame 0's size
+    other = scene(384, 200, 5)
+    depth[0].copy_(other["depth"])
+    normal[0].copy_(other["normal"])
+    second = b()
+    torch.cuda.synchronize()
+    assert torch.equal(second[0], alone(effect, fr[0], mp, p))
+    assert torch.equal(second[1], first[1])
+    assert not torch.equal(second[0], first[0])
+
+
+def test_max_batch():
+    """MR_MAX_BATCH frames of mixed small sizes (several share inputs)."""
+    effect = "ssao"
+    mp = mask_params(effect)
+    _, _, p = effect_params(effect, S=8)
+    small = ((128, 64), (256, 64), (128, 128), (384, 40), (256, 136))
+    base = frames_for(effect, small)
+    fr = [dict(base[k % len(small)]) for k in range(mr.MR_MAX_BATCH)]
+    log(f"[gpu] batch of {len(fr)} frames")
+    outs = mr.Batch(effect, fr, mp, p)()
+    torch.cuda.synchronize()
+    refs = [alone(effect, f, mp, p) for f in base]
+    for k, o in enumerate(outs):
+        assert torch.equal(o, refs[k % len(small)]), k
+
+
+def test_graph_capture_replays_to_eager():
+    """A HIP graph of one batch run, replayed several times with eager work
+    and input changes in between; every replay equals the eager run on the
+    same inputs."""
+    effect = "ssgi"
+    mp = mask_params(effect)
+    _, _, p = effect_params(effect)
+    sizes = ((640, 360), (256, 128), (384, 200))
+    depth = [scene(W, H, k)["depth"].clone() for k, (W, H) in enumerate(sizes)]
+    fr = [dict(depth=d, normal=scene(W, H, k)["normal"], focal=float(scene(W, H, k)["gb"].focal),
+               color=scene(W, H, k)["color"]) for k, ((W, H), d) in enumerate(zip(sizes, depth))]
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        b = mr.Batch(effect, fr, mp, p, stream=st)
+        b(st)  # warm-up outside the capture
+    st.synchronize()
+    log("[gpu] capturing a batch run")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        b(st)
+    views = (0, 3, 6, 1)
+    for rep, v in enumerate(views):
+        W, H = sizes[0]
+        depth[0].copy_(scene(W, H, v)["depth"] if v else scene(W, H, 0)["depth"])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [o.clone() for o in b.outs]
+        b()  # eager run on the same inputs
+        torch.cuda.synchronize()
+        for k in range(len(sizes)):
+            assert torch.equal(got[k], b.outs[k]), (rep, k)
+        # and frame 0 equals that frame alone
+        assert torch.equal(got[0], alone(effect, fr[0], mp, p)), rep
