@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-stages", action="store_true")
     ap.add_argument("--streams", type=int, default=2,
                     help="also report throughput with frames spread over this many streams (1 = off)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched uneven-frame SSGI measurement (24 frames, 640x360..3840x2160)")
     ap.add_argument("--no-quality", action="store_true", help="profile helper: skip the multi vs naive comparison")
     ap.add_argument("--plain", action="store_true", help="profile helper: time only the naive pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -272,6 +274,14 @@ def main():
                     "launch_ms": stages["multi_eval_ms"]}
         log("[bench] stages (ms): " + ", ".join(f"{k}={v}" for k, v in stages.items() if k.endswith("_ms")))
 
+    # ---------------- batched uneven SSGI frames (graph-replayed batch) ----------------
+    batched = None
+    if not args.no_batch:
+        from paper_1906_04576_amd import batched as batched_mod
+        batched = batched_mod.measure(steps=20, device=dev)
+        log(f"[bench] batched SSGI: {batched['mpixels_s']} Mpixels/s, {batched['speedup_vs_plain']}x naive, "
+            f"{batched['speedup_vs_sequential']}x one after another")
+
     # ---------------- CPU oracle on a bounded sample ----------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -323,6 +333,7 @@ def main():
         "concurrent": conc,
         "stages": stages,
         "roofline": roofline,
+        "batched_ssgi": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

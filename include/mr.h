@@ -315,6 +315,42 @@ MR_API int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t w
                           size_t plan_bytes, void* stream);
 MR_API int mr_batch_run(const void* plan, void* stream);
 
+/* How a batch's launches are shaped.  mr_batch_setup puts the defaults (all
+ * zero) in the plan.  Every choice gives bit-identical outputs; only the time
+ * differs.
+ *   edge_tile           0: 256x8-pixel edge tiles (frames of at most 4
+ *                          levels; 64x32 otherwise), 1: 64x32
+ *   eval_queue          0: each evaluation block takes a fixed stride of
+ *                          chunks of its XCD's share of the item space;
+ *                          1: the blocks of an XCD take chunks one at a time
+ *                          from a counter in the workspace
+ *   eval_blocks_per_cu  cap on evaluation blocks per CU, 0..64; 0: as many
+ *                       as can be resident
+ *   merge_generic       0: the four-level merge with fixed tap geometry
+ *                          where it applies (levels 1..4 all enabled),
+ *                       1: the general merge */
+typedef struct mr_batch_config {
+    int edge_tile;
+    int eval_queue;
+    int eval_blocks_per_cu;
+    int merge_generic;
+} mr_batch_config;
+
+/* Read or replace a filled plan's configuration (MR_E_PARAM for a plan not
+ * filled by mr_batch_setup or a value out of range; the plan is unchanged
+ * then). */
+MR_API int mr_batch_get_config(const void* plan, mr_batch_config* cfg);
+MR_API int mr_batch_set_config(void* plan, const mr_batch_config* cfg);
+
+/* Autotuner: times the batch (one warm-up run, then `reps` runs, 1..1000) on
+ * `stream` under candidate configurations, one choice at a time (the
+ * evaluation's schedule and grid cap first, then the edge tile shape, then
+ * the merge kernel), keeps the fastest in the plan and, when best is not
+ * NULL, in *best.  It runs the batch on its current inputs and waits for the
+ * stream: not for use under graph capture.  Outputs after it are those of a
+ * plain run. */
+MR_API int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream);
+
 /* Host helpers. */
 MR_API const char* mr_status_string(int status);
 MR_API const char* mr_last_error(void);

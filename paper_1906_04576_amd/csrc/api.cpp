@@ -854,15 +854,22 @@ constexpr uint32_t kBatchMagic = 0x3142524du;  // "MRB1"
 struct BatchPlan {
     uint32_t magic;
     int n, effect, ndt, cdt, S, C;
-    bool hard, wide, c16, m4;
+    bool c16, m4_ok, wide_ok;
+    mr_batch_config cfg;
     const EdgeArgs* te;
     const LeanArgs* tl;
     const void* tv;  // SsaoArgs or SsgiArgs
     const LeanMergeArgs* tm;
-    const unsigned *edge_base, *edge_tx, *rank_base, *merge_base, *merge_tx;
-    unsigned edge_total, rank_total, eval_hint, merge_total;
+    const unsigned *edge_base[2], *edge_tx[2], *rank_base, *merge_base, *merge_tx;
+    unsigned* queue;
+    unsigned edge_total[2], rank_total, eval_hint, merge_total;
 };
 static_assert(sizeof(BatchPlan) <= MR_BATCH_PLAN_BYTES, "batch plan exceeds MR_BATCH_PLAN_BYTES");
+
+// per-frame tables in the batch workspace: edge tile bases and tiles per row
+// for both edge tile shapes, rank block bases, merge tile bases and tiles per
+// row; then the evaluation's work-queue counters
+constexpr int kBatchTables = 7;
 
 struct BatchLayout {
     size_t te, tl, tv, tm, bases, frames[MR_MAX_BATCH], bytes;
@@ -917,10 +924,50 @@ BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos) {
     L.tl = take(sizeof(LeanArgs) * n);
     L.tv = take((fr[0].effect == MR_EFFECT_SSAO ? sizeof(SsaoArgs) : sizeof(SsgiArgs)) * n);
     L.tm = take(sizeof(LeanMergeArgs) * n);
-    L.bases = take(sizeof(unsigned) * 5 * (MR_MAX_BATCH + 1));
+    L.bases = take(sizeof(unsigned) * (kBatchTables * (MR_MAX_BATCH + 1) + kQueueCounters));
     for (int k = 0; k < n; ++k) L.frames[k] = take(lean_layout(geos[k], fr[k].effect).bytes);
     L.bytes = off;
     return L;
+}
+
+int load_plan(const void* plan, BatchPlan& P) {
+    if (!plan) return fail(MR_E_NULL, "plan is NULL");
+    memcpy(&P, plan, sizeof(P));
+    if (P.magic != kBatchMagic || P.n < 1 || P.n > MR_MAX_BATCH)
+        return fail(MR_E_PARAM, "plan was not filled by mr_batch_setup");
+    return MR_OK;
+}
+
+int check_config(const mr_batch_config& c) {
+    if (c.edge_tile != 0 && c.edge_tile != 1) return fail(MR_E_PARAM, "edge_tile %d not 0 or 1", c.edge_tile);
+    if (c.eval_queue != 0 && c.eval_queue != 1) return fail(MR_E_PARAM, "eval_queue %d not 0 or 1", c.eval_queue);
+    if (c.eval_blocks_per_cu < 0 || c.eval_blocks_per_cu > 64)
+        return fail(MR_E_PARAM, "eval_blocks_per_cu %d outside [0, 64]", c.eval_blocks_per_cu);
+    if (c.merge_generic != 0 && c.merge_generic != 1)
+        return fail(MR_E_PARAM, "merge_generic %d not 0 or 1", c.merge_generic);
+    return MR_OK;
+}
+
+int run_plan(const BatchPlan& P, hipStream_t s) {
+    const mr_batch_config& c = P.cfg;
+    const int et = c.edge_tile;
+    const bool wide = et == 0 && P.wide_ok;
+    if (launch_edges_batch(P.te, P.edge_base[et], P.edge_tx[et], P.n, P.edge_total[et], P.ndt, false, wide,
+                           P.queue, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "batched edge kernel launch failed");
+    if (launch_lean_masks_batch(P.tl, P.rank_base, P.n, P.rank_total, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "batched rank kernel launch failed");
+    const BatchSchedule bs{c.eval_queue != 0, c.eval_blocks_per_cu, P.queue};
+    hipError_t e;
+    if (P.effect == MR_EFFECT_SSAO)
+        e = launch_ssao_batch(static_cast<const SsaoArgs*>(P.tv), P.n, P.S, P.ndt, P.eval_hint, bs, s);
+    else
+        e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.ndt, P.cdt, P.eval_hint, bs, s);
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "batched evaluation kernel launch failed");
+    if (launch_lean_merge_batch(P.tm, P.merge_base, P.merge_tx, P.n, P.merge_total, P.C, P.c16,
+                                P.m4_ok && !c.merge_generic, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "batched merge kernel launch failed");
+    return MR_OK;
 }
 
 }  // namespace
@@ -1156,11 +1203,12 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     SsgiArgs* tgi = reinterpret_cast<SsgiArgs*>(host.data() + BL.tv);
     LeanMergeArgs* tm = reinterpret_cast<LeanMergeArgs*>(host.data() + BL.tm);
     unsigned* bases = reinterpret_cast<unsigned*>(host.data() + BL.bases);
-    unsigned* edge_base = bases;
-    unsigned* edge_tx = bases + (MR_MAX_BATCH + 1);
-    unsigned* rank_base = bases + 2 * (MR_MAX_BATCH + 1);
-    unsigned* merge_base = bases + 3 * (MR_MAX_BATCH + 1);
-    unsigned* merge_tx = bases + 4 * (MR_MAX_BATCH + 1);
+    auto table = [&](int t) { return bases + t * (MR_MAX_BATCH + 1); };
+    unsigned* edge_base[2] = {table(0), table(1)};
+    unsigned* edge_tx[2] = {table(2), table(3)};
+    unsigned* rank_base = table(4);
+    unsigned* merge_base = table(5);
+    unsigned* merge_tx = table(6);  // the queue counters follow, zero
     BatchPlan P{};
     P.magic = kBatchMagic;
     P.n = n;
@@ -1169,7 +1217,8 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     P.cdt = frames[0].g.color_dtype;
     P.C = effect == MR_EFFECT_SSGI ? 3 : 1;
     P.c16 = frames[0].level_dtype == MR_F16;
-    unsigned et = 0, rt = 0, mt = 0, hint = 0;
+    unsigned et[2] = {0, 0}, rt = 0, mt = 0, hint = 0;
+    bool wide = false;
     for (int k = 0; k < n; ++k) {
         const mr_frame_desc& d = frames[k];
         const void* params = effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
@@ -1182,13 +1231,17 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
         else
             tgi[k] = L.ev.gi;
         tm[k] = L.ma;
+        // both tile shapes: table 0 the default one (wide with at most 4
+        // levels: the same for all frames), table 1 the narrow one
         unsigned tx, nt;
-        bool wide;
         edges_grid(geos[k].W, geos[k].H, geos[k].N, wide, tx, nt);
-        P.wide = wide;  // the same for all frames (same number of levels)
-        edge_base[k] = et;
-        edge_tx[k] = tx;
-        et += nt;
+        edge_base[0][k] = et[0];
+        edge_tx[0][k] = tx;
+        et[0] += nt;
+        edges_tiles(geos[k].W, geos[k].H, false, tx, nt);
+        edge_base[1][k] = et[1];
+        edge_tx[1][k] = tx;
+        et[1] += nt;
         rank_base[k] = rt;
         rt += L.la.nblk;
         const unsigned mx = (unsigned)((geos[k].W + kMergeTW - 1) / kMergeTW);
@@ -1197,27 +1250,35 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
         mt += mx * (unsigned)((geos[k].H + kMergeTH - 1) / kMergeTH);
         hint += L.ev.hint + 1024u;  // + padding of the levels' and frame's item ranges
         if (k == 0) {
-            P.m4 = merge4_applies(L.ma);
+            P.m4_ok = merge4_applies(L.ma);
             P.S = effect == MR_EFFECT_SSAO ? L.ev.sa.S : L.ev.gi.S;
         }
     }
-    edge_base[n] = et;
+    edge_base[0][n] = et[0];
+    edge_base[1][n] = et[1];
     rank_base[n] = rt;
     merge_base[n] = mt;
-    P.edge_total = et;
+    P.edge_total[0] = et[0];
+    P.edge_total[1] = et[1];
     P.rank_total = rt;
     P.merge_total = mt;
     P.eval_hint = hint;
+    P.wide_ok = wide;
+    P.cfg = mr_batch_config{0, 0, 0, 0};
     P.te = reinterpret_cast<const EdgeArgs*>(b + BL.te);
     P.tl = reinterpret_cast<const LeanArgs*>(b + BL.tl);
     P.tv = b + BL.tv;
     P.tm = reinterpret_cast<const LeanMergeArgs*>(b + BL.tm);
-    const unsigned* db = reinterpret_cast<const unsigned*>(b + BL.bases);
-    P.edge_base = db;
-    P.edge_tx = db + (MR_MAX_BATCH + 1);
-    P.rank_base = db + 2 * (MR_MAX_BATCH + 1);
-    P.merge_base = db + 3 * (MR_MAX_BATCH + 1);
-    P.merge_tx = db + 4 * (MR_MAX_BATCH + 1);
+    unsigned* db = reinterpret_cast<unsigned*>(b + BL.bases);
+    auto dtable = [&](int t) { return db + t * (MR_MAX_BATCH + 1); };
+    P.edge_base[0] = dtable(0);
+    P.edge_base[1] = dtable(1);
+    P.edge_tx[0] = dtable(2);
+    P.edge_tx[1] = dtable(3);
+    P.rank_base = dtable(4);
+    P.merge_base = dtable(5);
+    P.merge_tx = dtable(6);
+    P.queue = dtable(kBatchTables);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(b, host.data(), host.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1227,25 +1288,92 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
 }
 
 int mr_batch_run(const void* plan, void* stream) {
-    if (!plan) return fail(MR_E_NULL, "plan is NULL");
     BatchPlan P;
-    memcpy(&P, plan, sizeof(P));
-    if (P.magic != kBatchMagic || P.n < 1 || P.n > MR_MAX_BATCH)
-        return fail(MR_E_PARAM, "plan was not filled by mr_batch_setup");
+    const int st = load_plan(plan, P);
+    return st ? st : run_plan(P, static_cast<hipStream_t>(stream));
+}
+
+int mr_batch_get_config(const void* plan, mr_batch_config* cfg) {
+    if (!cfg) return fail(MR_E_NULL, "config is NULL");
+    BatchPlan P;
+    const int st = load_plan(plan, P);
+    if (st) return st;
+    *cfg = P.cfg;
+    return MR_OK;
+}
+
+int mr_batch_set_config(void* plan, const mr_batch_config* cfg) {
+    if (!cfg) return fail(MR_E_NULL, "config is NULL");
+    BatchPlan P;
+    int st = load_plan(plan, P);
+    if (!st) st = check_config(*cfg);
+    if (st) return st;
+    P.cfg = *cfg;
+    memcpy(plan, &P, sizeof(P));
+    return MR_OK;
+}
+
+int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
+    BatchPlan P;
+    int st = load_plan(plan, P);
+    if (st) return st;
+    if (reps < 1 || reps > 1000) return fail(MR_E_PARAM, "reps %d outside [1, 1000]", reps);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (launch_edges_batch(P.te, P.edge_base, P.edge_tx, P.n, P.edge_total, P.ndt, false, P.wide, s) != hipSuccess)
-        return fail(MR_E_DEVICE, "batched edge kernel launch failed");
-    if (launch_lean_masks_batch(P.tl, P.rank_base, P.n, P.rank_total, s) != hipSuccess)
-        return fail(MR_E_DEVICE, "batched rank kernel launch failed");
-    hipError_t e;
-    if (P.effect == MR_EFFECT_SSAO)
-        e = launch_ssao_batch(static_cast<const SsaoArgs*>(P.tv), P.n, P.S, P.ndt, P.eval_hint, s);
-    else
-        e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.ndt, P.cdt, P.eval_hint, s);
-    if (e != hipSuccess) return fail(MR_E_DEVICE, "batched evaluation kernel launch failed");
-    if (launch_lean_merge_batch(P.tm, P.merge_base, P.merge_tx, P.n, P.merge_total, P.C, P.c16, P.m4, s) !=
-        hipSuccess)
-        return fail(MR_E_DEVICE, "batched merge kernel launch failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(MR_E_DEVICE, "event creation failed");
+    }
+    // time of reps runs with configuration c after one warm-up run
+    auto time_of = [&](const mr_batch_config& c, float& ms) -> int {
+        P.cfg = c;
+        int r = run_plan(P, s);
+        if (r) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(MR_E_DEVICE, "event record failed");
+        for (int i = 0; i < reps && !r; ++i) r = run_plan(P, s);
+        if (r) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(MR_E_DEVICE, "batch timing failed");
+        return MR_OK;
+    };
+    // one choice at a time, the evaluation's schedule first (it dominates)
+    mr_batch_config bc = P.cfg;
+    float bt = 0.f;
+    st = time_of(bc, bt);
+    auto consider = [&](mr_batch_config c) {
+        if (st || check_config(c) != MR_OK) return;
+        float t = 0.f;
+        st = time_of(c, t);
+        if (!st && t < bt) {
+            bt = t;
+            bc = c;
+        }
+    };
+    const mr_batch_config base = bc;
+    for (int q = 0; q < 2; ++q)
+        for (int bpc : {0, 8, 4, 2}) {
+            mr_batch_config c = bc;
+            c.eval_queue = q;
+            c.eval_blocks_per_cu = bpc;
+            if (c.eval_queue != base.eval_queue || c.eval_blocks_per_cu != base.eval_blocks_per_cu) consider(c);
+        }
+    for (int t = 0; t < 2; ++t) {
+        mr_batch_config c = bc;
+        c.edge_tile = t;
+        if (t != bc.edge_tile) consider(c);
+    }
+    if (P.m4_ok) {
+        mr_batch_config c = bc;
+        c.merge_generic = 1 - bc.merge_generic;
+        consider(c);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    P.cfg = bc;
+    memcpy(plan, &P, sizeof(P));
+    if (best) *best = bc;
     return MR_OK;
 }
 

@@ -81,6 +81,37 @@ __device__ __forceinline__ ChunkRange chunk_range(unsigned nchunks) {
     return {lo + k, hi, per};
 }
 
+// Chunks of a launch's item space handed to its blocks.  Q false: each block
+// takes a fixed stride of its XCD's region (chunk_range).  Q true: the blocks
+// of an XCD take that region's chunks one at a time from the XCD's counter
+// (queue[x], zero when the launch starts), so blocks that finish early take
+// more.  Both visit every chunk exactly once.  The body must not synchronise
+// the block.
+template <bool Q, typename F>
+__device__ __forceinline__ void for_each_chunk(unsigned nchunks, unsigned* queue, F&& body) {
+    if constexpr (!Q) {
+        const ChunkRange cr = chunk_range(nchunks);
+        for (unsigned c = cr.first; c < cr.end; c += cr.step) body(c);
+    } else {
+        __shared__ unsigned next;
+        const unsigned G = gridDim.x;
+        unsigned x = 0, lo = 0, hi = nchunks;
+        if (G >= 8) {
+            x = blockIdx.x & 7u;
+            lo = (unsigned)((unsigned long long)nchunks * x / 8u);
+            hi = (unsigned)((unsigned long long)nchunks * (x + 1u) / 8u);
+        }
+        for (;;) {
+            if (threadIdx.x == 0) next = lo + atomicAdd(queue + x, 1u);
+            __syncthreads();
+            const unsigned c = next;
+            __syncthreads();
+            if (c >= hi) break;
+            body(c);
+        }
+    }
+}
+
 // Frames of one batched launch at most.
 constexpr int kMaxBatch = 64;
 
@@ -232,6 +263,28 @@ __host__ inline unsigned eval_blocks(unsigned total_hint) {
     const unsigned cap = resident_blocks<Kernel>();
     if (b > cap) b = cap;
     if (b < 1) b = 1;
+    return b;
+}
+
+__host__ inline unsigned cu_count() {
+    static const unsigned n = [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            return 256u;
+        return (unsigned)cus;
+    }();
+    return n;
+}
+
+// eval_blocks capped at blocks_per_cu blocks on every CU (0: no cap)
+template <auto Kernel>
+__host__ inline unsigned eval_blocks_capped(unsigned total_hint, int blocks_per_cu) {
+    unsigned b = eval_blocks<Kernel>(total_hint);
+    if (blocks_per_cu > 0) {
+        const unsigned cap = cu_count() * (unsigned)blocks_per_cu;
+        if (b > cap) b = cap;
+    }
     return b;
 }
 

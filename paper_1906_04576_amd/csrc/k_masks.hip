@@ -538,7 +538,8 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
 // tile of frame f, tile_base[n] = total); tiles_x[f] per frame.
 template <typename NT, bool HARD, bool BITS, bool WIDE>
 __global__ __launch_bounds__(256) void k_edges_batch(const EdgeArgs* T, const unsigned* tile_base,
-                                                     const unsigned* tiles_x, int n) {
+                                                     const unsigned* tiles_x, int n, unsigned* queue) {
+    if (blockIdx.x == 0 && threadIdx.x < kQueueCounters) queue[threadIdx.x] = 0u;
     const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
     int f = 0;
     for (int k = 1; k < n; ++k) f += g >= tile_base[k] ? 1 : 0;
@@ -547,10 +548,12 @@ __global__ __launch_bounds__(256) void k_edges_batch(const EdgeArgs* T, const un
 }
 
 hipError_t launch_edges_batch(const EdgeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
-                              unsigned total, int normal_dtype, bool hard, bool wide, hipStream_t s) {
+                              unsigned total, int normal_dtype, bool hard, bool wide, unsigned* queue,
+                              hipStream_t s) {
     // compact frame path only: bit-packed edges (BITS) and widths divisible by 4
-#define MR_EB(NT, HD, WD) \
-    hipLaunchKernelGGL((k_edges_batch<NT, HD, true, WD>), dim3(total), dim3(256), 0, s, T, tile_base, tiles_x, n)
+#define MR_EB(NT, HD, WD)                                                                                  \
+    hipLaunchKernelGGL((k_edges_batch<NT, HD, true, WD>), dim3(total), dim3(256), 0, s, T, tile_base, tiles_x, n, \
+                       queue)
     const bool f16 = normal_dtype == MR_F16;
     if (wide) {
         if (f16 && hard) MR_EB(_Float16, true, true);
@@ -569,6 +572,10 @@ hipError_t launch_edges_batch(const EdgeArgs* T, const unsigned* tile_base, cons
 
 void edges_grid(int W, int H, int num_levels, bool& wide, unsigned& tiles_x, unsigned& ntiles) {
     wide = num_levels <= 4;
+    edges_tiles(W, H, wide, tiles_x, ntiles);
+}
+
+void edges_tiles(int W, int H, bool wide, unsigned& tiles_x, unsigned& ntiles) {
     if (wide) {
         tiles_x = (unsigned)((W + 4 * kEdgeTW - 1) / (4 * kEdgeTW));
         ntiles = tiles_x * (unsigned)((H + 7) / 8);

@@ -194,38 +194,46 @@ __global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
 // Frames of a batch (same samples, mask and effect parameters): one item
 // space over all frames, each frame's range padded to whole chunks of 256,
 // swept by a resident grid like the single-frame launch.
-template <typename NT, bool AL, bool KLDS>
-__global__ __launch_bounds__(256) void k_ssao_batch(const SsaoArgs* T, int n) {
+template <typename NT, bool AL, bool KLDS, bool Q>
+__global__ __launch_bounds__(256) void k_ssao_batch(const SsaoArgs* T, int n, unsigned* queue) {
     __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
     __shared__ unsigned cbase[kMaxBatch + 1];
     const float kmax = ssao_stage<AL, KLDS>(T[0], ks, eg);
     batch_chunk_bases(T, n, cbase);
-    const ChunkRange cr = chunk_range(cbase[n]);
-    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+    for_each_chunk<Q>(cbase[n], queue, [&](unsigned c) {
         int f = 0;
         for (int k = 1; k < n; ++k) f += c >= cbase[k] ? 1 : 0;
         const SsaoArgs& a = T[f];
         const ItemMap m = make_item_map(a.c);
         const unsigned item = (c - cbase[f]) * 256u + threadIdx.x;
         if (item < item_total(m)) ssao_item<NT, KLDS, AL>(a, m, item, ks, eg, kmax);
-    }
+    });
 }
 
 hipError_t launch_ssao_batch(const SsaoArgs* T, int n, int S, int normal_dtype, unsigned total_hint,
-                             hipStream_t s) {
+                             const BatchSchedule& bs, hipStream_t s) {
     // the compact frame path fuses a_i into the evaluation
     const bool lds = S <= kLdsSamples;
-#define MR_SB(NT, KL) \
-    hipLaunchKernelGGL((k_ssao_batch<NT, true, KL>), dim3(eval_blocks<k_ssao_batch<NT, true, KL>>(total_hint)), \
-                       dim3(256), 0, s, T, n)
+#define MR_SB(NT, KL, Q)                                                                                    \
+    hipLaunchKernelGGL((k_ssao_batch<NT, true, KL, Q>),                                                     \
+                       dim3(eval_blocks_capped<k_ssao_batch<NT, true, KL, Q>>(total_hint, bs.blocks_per_cu)), \
+                       dim3(256), 0, s, T, n, bs.queue)
+#define MR_SBQ(NT, KL)            \
+    do {                          \
+        if (bs.queue_mode)        \
+            MR_SB(NT, KL, true);  \
+        else                      \
+            MR_SB(NT, KL, false); \
+    } while (0)
     if (normal_dtype == MR_F16) {
-        if (lds) MR_SB(_Float16, true);
-        else MR_SB(_Float16, false);
+        if (lds) MR_SBQ(_Float16, true);
+        else MR_SBQ(_Float16, false);
     } else {
-        if (lds) MR_SB(float, true);
-        else MR_SB(float, false);
+        if (lds) MR_SBQ(float, true);
+        else MR_SBQ(float, false);
     }
+#undef MR_SBQ
 #undef MR_SB
     return hipGetLastError();
 }

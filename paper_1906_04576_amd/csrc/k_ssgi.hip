@@ -116,41 +116,49 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
 }
 
 // frames of a batch (see k_ssao_batch)
-template <typename NT, typename CT>
-__global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* T, int n) {
+template <typename NT, typename CT, bool Q>
+__global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* T, int n, unsigned* queue) {
     __shared__ float ks[3 * kLdsSamples];
     __shared__ float eg[kMaxLevels * kEgStride];
     __shared__ unsigned cbase[kMaxBatch + 1];
     const bool staged = ssgi_stage<true>(T[0], ks, eg);
     batch_chunk_bases(T, n, cbase);
-    const ChunkRange cr = chunk_range(cbase[n]);
-    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+    for_each_chunk<Q>(cbase[n], queue, [&](unsigned c) {
         int f = 0;
         for (int k = 1; k < n; ++k) f += c >= cbase[k] ? 1 : 0;
         const SsgiArgs& a = T[f];
         const ItemMap m = make_item_map(a.c);
         const unsigned item = (c - cbase[f]) * 256u + threadIdx.x;
-        if (item >= item_total(m)) continue;
+        if (item >= item_total(m)) return;
         if (staged)
             ssgi_item<NT, CT, true>(a, m, item, (const float*)ks, (const float*)eg);
         else
             ssgi_item<NT, CT, true>(a, m, item, a.kernel, (const float*)eg);
-    }
+    });
 }
 
 hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int color_dtype, unsigned total_hint,
-                             hipStream_t s) {
-#define MR_GB(NT, CT) \
-    hipLaunchKernelGGL((k_ssgi_batch<NT, CT>), dim3(eval_blocks<k_ssgi_batch<NT, CT>>(total_hint)), dim3(256), 0, \
-                       s, T, n)
+                             const BatchSchedule& bs, hipStream_t s) {
+#define MR_GB(NT, CT, Q)                                                                                  \
+    hipLaunchKernelGGL((k_ssgi_batch<NT, CT, Q>),                                                         \
+                       dim3(eval_blocks_capped<k_ssgi_batch<NT, CT, Q>>(total_hint, bs.blocks_per_cu)), \
+                       dim3(256), 0, s, T, n, bs.queue)
+#define MR_GBQ(NT, CT)            \
+    do {                          \
+        if (bs.queue_mode)        \
+            MR_GB(NT, CT, true);  \
+        else                      \
+            MR_GB(NT, CT, false); \
+    } while (0)
     if (normal_dtype == MR_F16 && color_dtype == MR_F16)
-        MR_GB(_Float16, _Float16);
+        MR_GBQ(_Float16, _Float16);
     else if (normal_dtype == MR_F16)
-        MR_GB(_Float16, float);
+        MR_GBQ(_Float16, float);
     else if (color_dtype == MR_F16)
-        MR_GB(float, _Float16);
+        MR_GBQ(float, _Float16);
     else
-        MR_GB(float, float);
+        MR_GBQ(float, float);
+#undef MR_GBQ
 #undef MR_GB
     return hipGetLastError();
 }

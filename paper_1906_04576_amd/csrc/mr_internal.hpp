@@ -291,16 +291,27 @@ bool merge4_applies(const LeanMergeArgs& a);
 
 // edge kernel tiling for an image (the choice launch_edges makes)
 void edges_grid(int W, int H, int num_levels, bool& wide, unsigned& tiles_x, unsigned& ntiles);
+// tiling for one tile shape: 256x8 pixels (wide, at most 4 levels) or 64x32
+void edges_tiles(int W, int H, bool wide, unsigned& tiles_x, unsigned& ntiles);
 
-// batched frames: argument tables in device memory, one launch per stage
+// batched frames: argument tables in device memory, one launch per stage.
+// The edge launch also zeroes `queue` (the evaluation's per-XCD counters).
 hipError_t launch_edges_batch(const EdgeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
-                              unsigned total, int normal_dtype, bool hard, bool wide, hipStream_t s);
+                              unsigned total, int normal_dtype, bool hard, bool wide, unsigned* queue,
+                              hipStream_t s);
 hipError_t launch_lean_masks_batch(const LeanArgs* T, const unsigned* blk_base, int n, unsigned total,
                                    hipStream_t s);
+// how a batched evaluation hands out its chunks
+constexpr int kQueueCounters = 8;  // work-queue counters: one per XCD
+struct BatchSchedule {
+    bool queue_mode;    // per-XCD work queues instead of fixed strides
+    int blocks_per_cu;  // grid cap per CU, 0: as many blocks as are resident
+    unsigned* queue;    // kQueueCounters counters, zeroed by the edge launch
+};
 hipError_t launch_ssao_batch(const SsaoArgs* T, int n, int S, int normal_dtype, unsigned total_hint,
-                             hipStream_t s);
+                             const BatchSchedule& bs, hipStream_t s);
 hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int color_dtype, unsigned total_hint,
-                             hipStream_t s);
+                             const BatchSchedule& bs, hipStream_t s);
 hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
                                    unsigned total, int C, bool c16, bool m4, hipStream_t s);
 

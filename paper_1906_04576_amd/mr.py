@@ -84,6 +84,14 @@ class mr_frame_desc(ctypes.Structure):
                 ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS)]
 
 
+class mr_batch_config(ctypes.Structure):
+    _fields_ = [("edge_tile", ctypes.c_int), ("eval_queue", ctypes.c_int), ("eval_blocks_per_cu", ctypes.c_int),
+                ("merge_generic", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # entry points and their ctypes signatures (also used by the export test)
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -109,6 +117,9 @@ SIGNATURES = {
     "mr_batch_setup": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), ctypes.c_int, _P, ctypes.c_size_t, _P,
                                       ctypes.c_size_t, _P]),
     "mr_batch_run": (ctypes.c_int, [_P, _P]),
+    "mr_batch_get_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
+    "mr_batch_set_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
+    "mr_batch_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mr_batch_config), _P]),
     "mr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mr_last_error": (ctypes.c_char_p, []),
     "mr_version": (ctypes.c_int, []),
@@ -580,6 +591,28 @@ class Batch:
     def __call__(self, stream=None):
         _check(self._run(ctypes.cast(self.plan, ctypes.c_void_p), _stream(stream)))
         return self.outs
+
+    @property
+    def config(self) -> dict:
+        c = mr_batch_config()
+        _check(lib().mr_batch_get_config(ctypes.cast(self.plan, ctypes.c_void_p), ctypes.byref(c)))
+        return c.as_dict()
+
+    @config.setter
+    def config(self, cfg: dict):
+        c = mr_batch_config()
+        lib().mr_batch_get_config(ctypes.cast(self.plan, ctypes.c_void_p), ctypes.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, int(v))
+        _check(lib().mr_batch_set_config(ctypes.cast(self.plan, ctypes.c_void_p), ctypes.byref(c)))
+
+    def tune(self, reps=5, stream=None) -> dict:
+        """Autotune the plan's launch configuration on the current inputs
+        (mr_batch_tune); returns the configuration kept."""
+        c = mr_batch_config()
+        _check(lib().mr_batch_tune(ctypes.cast(self.plan, ctypes.c_void_p), int(reps), ctypes.byref(c),
+                                   _stream(stream)))
+        return c.as_dict()
 
 
 class Prepared:

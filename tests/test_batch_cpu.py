@@ -107,3 +107,17 @@ def test_setup_checks_workspace_and_plan_before_any_copy():
     # a plan that mr_batch_setup did not fill is refused without a launch
     assert L.mr_batch_run(pp, None) == mr.MR_E_PARAM and "mr_batch_setup" in mr.mr_last_error()
     assert L.mr_batch_run(None, None) == mr.MR_E_NULL
+
+
+def test_config_calls_need_a_filled_plan():
+    L = mr.lib()
+    plan = (ctypes.c_uint8 * mr.MR_BATCH_PLAN_BYTES)()
+    pp = ctypes.cast(plan, ctypes.c_void_p)
+    c = mr.mr_batch_config()
+    assert L.mr_batch_get_config(pp, ctypes.byref(c)) == mr.MR_E_PARAM
+    assert L.mr_batch_set_config(pp, ctypes.byref(c)) == mr.MR_E_PARAM
+    assert L.mr_batch_tune(pp, 3, ctypes.byref(c), None) == mr.MR_E_PARAM
+    assert L.mr_batch_get_config(None, ctypes.byref(c)) == mr.MR_E_NULL
+    assert L.mr_batch_get_config(pp, None) == mr.MR_E_NULL
+    assert L.mr_batch_set_config(pp, None) == mr.MR_E_NULL
+    assert L.mr_batch_tune(None, 3, None, None) == mr.MR_E_NULL

@@ -178,3 +178,62 @@ def test_graph_capture_replays_to_eager():
             assert torch.equal(got[k], b.outs[k]), (rep, k)
         # and frame 0 equals that frame alone
         assert torch.equal(got[0], alone(effect, fr[0], mp, p)), rep
+
+
+CONFIGS = [dict(edge_tile=t, eval_queue=q, eval_blocks_per_cu=b, merge_generic=m)
+           for t, q, b, m in ((0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 1, 2, 0), (0, 0, 1, 0), (0, 0, 0, 1),
+                              (1, 1, 3, 1))]
+
+
+@pytest.mark.parametrize("effect", ["ssao", "ssgi"])
+def test_every_configuration_is_bit_identical(effect):
+    mp = mask_params(effect)
+    _, _, p = effect_params(effect)
+    fr = frames_for(effect, SIZES)
+    b = mr.Batch(effect, fr, mp, p)
+    assert b.config == CONFIGS[0]  # the defaults
+    ref = [o.clone() for o in b()]
+    torch.cuda.synchronize()
+    for cfg in CONFIGS[1:]:
+        log(f"[gpu] batch {effect} config {cfg}")
+        b.config = cfg
+        assert b.config == cfg
+        for o in b.outs:
+            o.fill_(float("nan"))
+        b()
+        b()  # the queue counters start from zero on every run
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(b.outs, ref)):
+            assert torch.equal(o, r), (cfg, SIZES[k])
+
+
+def test_config_rejects_out_of_range_values():
+    mp = mask_params("ssao")
+    _, _, p = effect_params("ssao")
+    b = mr.Batch("ssao", frames_for("ssao", SIZES[:2]), mp, p)
+    for bad in (dict(edge_tile=2), dict(eval_queue=-1), dict(eval_blocks_per_cu=65), dict(merge_generic=3)):
+        with pytest.raises(mr.MRError) as e:
+            b.config = bad
+        assert e.value.status == mr.MR_E_PARAM
+        assert b.config == CONFIGS[0]
+
+
+def test_tuner_keeps_a_valid_configuration_and_the_outputs():
+    effect = "ssgi"
+    mp = mask_params(effect)
+    _, _, p = effect_params(effect)
+    fr = frames_for(effect, SIZES)
+    b = mr.Batch(effect, fr, mp, p)
+    ref = [o.clone() for o in b()]
+    log("[gpu] tuning a batch")
+    cfg = b.tune(reps=2)
+    log(f"[gpu] tuned {cfg}")
+    assert b.config == cfg
+    assert cfg["edge_tile"] in (0, 1) and cfg["eval_queue"] in (0, 1) and 0 <= cfg["eval_blocks_per_cu"] <= 64
+    torch.cuda.synchronize()
+    for o, r in zip(b.outs, ref):
+        assert torch.equal(o, r)
+    b()
+    torch.cuda.synchronize()
+    for o, r in zip(b.outs, ref):
+        assert torch.equal(o, r)
