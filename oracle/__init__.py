@@ -23,6 +23,8 @@ for Computationally Expensive Lighting Effects", arXiv 1906.04576):
 * ``shadow``  - Sec. 2.4 / 3.1: shadow-map hard test, shadow edges added to the
                 mask, percentage-closer soft shadows.
 * ``ssgi``    - Sec. 2.4: one-bounce screen-space indirect light.
+* ``bilateral`` - Sec. 4.1: optional depth-aware blur of SSAO sub-images
+                inside each level's stencil.
 * ``frame``   - the whole per-frame pipeline for one effect.
 
 Arithmetic contract (so the GPU path can be compared bit for bit): every
@@ -41,6 +43,7 @@ from .ssao import SSAOParams, ssao_texels, ssao_level, ssao_plain
 from .merge import upsample_merge
 from .shadow import ShadowParams, light_coords, hard_shadow, shadow_edges, pcss_texels, pcss_level
 from .ssgi import SSGIParams, ssgi_texels, ssgi_level
+from .bilateral import BilateralParams, binomial_weights, bilateral_level
 from .frame import frame, Frame
 
 __all__ = [
@@ -48,5 +51,5 @@ __all__ = [
     "Pyramid", "level_sample", "work_lists", "level_dims", "SSAOParams", "ssao_texels",
     "ssao_level", "ssao_plain", "upsample_merge", "ShadowParams", "light_coords", "hard_shadow",
     "shadow_edges", "pcss_texels", "pcss_level", "SSGIParams", "ssgi_texels", "ssgi_level",
-    "frame", "Frame",
+    "BilateralParams", "binomial_weights", "bilateral_level", "frame", "Frame",
 ]

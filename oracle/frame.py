@@ -15,6 +15,7 @@ from .ssao import SSAOParams, ssao_level
 from .merge import upsample_merge
 from .shadow import ShadowParams, hard_shadow, shadow_edges, pcss_level
 from .ssgi import SSGIParams, ssgi_level
+from .bilateral import BilateralParams, bilateral_level
 
 
 @dataclass
@@ -25,12 +26,14 @@ class Frame:
 
 
 def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None,
-          dtype=np.float32, level_dtype=None) -> Frame:
+          dtype=np.float32, level_dtype=None, bilateral: BilateralParams = None) -> Frame:
     """effect in {"ssao", "shadow", "ssgi"}; params the matching *Params.
 
     multires=False is the naive full-resolution pass.  level_dtype (e.g.
     np.float16) stores every sub-image value in that type (rounded to
-    nearest) between the evaluation and the merge."""
+    nearest) between the evaluation and the merge.  bilateral (SSAO only)
+    blurs the sub-images of its levels before the merge (Sec. 4.1); the
+    blurred values are stored in level_dtype too."""
     H, W = depth.shape
     channels = 3 if effect == "ssgi" else 1
 
@@ -59,9 +62,14 @@ def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, c
     L = pyr.levels[-1]
     lo = {}
     for i in pyr.levels:
-        lo[i] = evaluate(i, None if i == L else pyr.stencil[i])
+        st = None if i == L else pyr.stencil[i]
+        lo[i] = evaluate(i, st)
         if level_dtype is not None:
             lo[i] = lo[i].astype(level_dtype).astype(dtype)
+        if bilateral is not None and effect == "ssao" and bilateral.levels >> (i - 1) & 1:
+            lo[i] = bilateral_level(lo[i], level_sample(depth, i), st, bilateral, dtype)
+            if level_dtype is not None:
+                lo[i] = lo[i].astype(level_dtype).astype(dtype)
     weights = {i: mp.weight[i - 1] for i in pyr.levels}
     out = upsample_merge(W, H, pyr.levels, weights, pyr.alpha, pyr.stencil, lo, channels, dtype)
     return Frame(out=out, pyramid=pyr, level_out=lo)
