@@ -206,6 +206,24 @@ typedef struct {
     float bias_rel;
 } mr_ssgi_params;
 
+/* Bilateral blur of SSAO sub-images before the merge (Sec. 4.1: smooths the
+ * variance of few samples without carrying values from texels a level did
+ * not render).  For every rendered texel p of a chosen level with valid
+ * depth: the (2r+1)^2 window of taps q inside the level that the level
+ * rendered (stencil 1) and whose depth is valid, weight
+ *   w = b[dy] * b[dx] * max(0, 1 - |z_q - z_p| / (depth_rel * z_p)),
+ * b the binomial weights of order 2r (1 2 1 / 4, 1 4 6 4 1 / 16), z the
+ * level's point-sampled depth; result sum(w c) / sum(w), both summed in
+ * window order (rows top to bottom, left to right), FP32.
+ * levels     bit i-1 blurs level i (enabled levels only); 0 = off.
+ * radius     1 or 2.
+ * depth_rel  > 0, finite (0.05 is the edge detector's depth ratio). */
+typedef struct {
+    uint32_t levels;
+    int radius;
+    float depth_rel;
+} mr_bilateral_params;
+
 /* Whole-frame descriptor for mr_frame.
  * effect     MR_EFFECT_*; the matching params pointer must be non-NULL (host).
  * multires   0 = naive full-resolution pass (masks unused), 1 = multi-res.
@@ -222,7 +240,10 @@ typedef struct {
  *            path), [2] after the per-level evaluation, [3] after the merge.
  *            They are owned by the caller and must have been created on the
  *            stream's device; event [k+1] minus event [k] is the GPU time of
- *            that stage. */
+ *            that stage.
+ * bilateral  optional blur of the SSAO sub-images (levels = 0: off); needs
+ *            MR_EFFECT_SSAO, multires = 1 and the compact frame path, else
+ *            MR_E_PARAM.  Counted in the evaluation stage. */
 typedef struct {
     int effect;
     int multires;
@@ -236,6 +257,7 @@ typedef struct {
     uint8_t* level_map;
     int level_dtype;
     void* stage_events[MR_FRAME_EVENTS];
+    mr_bilateral_params bilateral;
 } mr_frame_desc;
 
 /* Workspace bytes needed by mr_frame for `effect` (MR_EFFECT_*) or by
@@ -298,7 +320,8 @@ MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* str
  * ranks and work lists, per-level evaluation over one item space of all
  * frames by a resident grid, merge).  Every frame must take the compact path
  * (coarsest level <= 4, width divisible by 128, blur radii <= 8), have
- * multires = 1 and level_map = NULL; stage_events are not recorded.
+ * multires = 1, level_map = NULL and no bilateral blur; stage_events are not
+ * recorded.
  *
  * mr_batch_setup validates the frames, lays them out in ws (at least
  * mr_batch_workspace_bytes) and copies the kernel argument tables there; it

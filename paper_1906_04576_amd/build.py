@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libmr.so")
 
 SOURCES = ["api.cpp", "k_masks.hip", "k_compact.hip", "k_ssao.hip", "k_shadow.hip", "k_ssgi.hip",
            "k_merge.hip",
-           "k_lean.hip"]
+           "k_lean.hip", "k_bilateral.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

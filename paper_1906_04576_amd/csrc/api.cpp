@@ -327,6 +327,7 @@ unsigned lean_tiles(int wpr, int H) {
 struct LeanLayout {
     size_t count = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, ac[3] = {}, cc[3] = {};
     size_t zi[kMaxLevels] = {}, cL = 0, hard = 0;
+    size_t bc[3] = {}, bL = 0;  // SSAO: bilaterally blurred values
     unsigned nblk = 0;
     size_t bytes = 0;
 };
@@ -359,6 +360,13 @@ LeanLayout lean_layout(const Geo& g, int effect) {
     }
     f.cL = take(4 * (size_t)g.n(g.L) * C);
     if (effect == MR_EFFECT_SHADOW) f.hard = take((size_t)g.W * g.H);
+    if (effect == MR_EFFECT_SSAO) {
+        for (int j = 0; j + 1 < g.nlev; ++j) {
+            const int i = g.levels[j];
+            f.bc[i - 1] = take(4 * (size_t)g.n(i));
+        }
+        f.bL = take(4 * (size_t)g.n(g.L));
+    }
     f.bytes = off;
     return f;
 }
@@ -684,10 +692,28 @@ int mark(const mr_frame_desc* d, int k, hipStream_t s) {
     return MR_OK;
 }
 
+int check_bilateral(const mr_frame_desc* d, const Geo& g) {
+    const mr_bilateral_params& p = d->bilateral;
+    if (!p.levels) return MR_OK;
+    if (d->effect != MR_EFFECT_SSAO) return fail(MR_E_PARAM, "the bilateral blur applies to MR_EFFECT_SSAO only");
+    if (!lean_ok(g, &d->mp))
+        return fail(MR_E_PARAM, "the bilateral blur needs the compact frame path (coarsest level <= 4, width "
+                                "divisible by 128, blur radii <= 8)");
+    uint32_t enabled = 0;
+    for (int j = 0; j < g.nlev; ++j) enabled |= 1u << (g.levels[j] - 1);
+    if (p.levels & ~enabled)
+        return fail(MR_E_PARAM, "bilateral levels 0x%x name levels that are not enabled (0x%x)", p.levels, enabled);
+    if (p.radius != 1 && p.radius != 2) return fail(MR_E_PARAM, "bilateral radius %d is not 1 or 2", p.radius);
+    if (!(p.depth_rel > 0.0f) || !isfinite(p.depth_rel))
+        return fail(MR_E_PARAM, "bilateral depth_rel %g is not finite and > 0", (double)p.depth_rel);
+    return MR_OK;
+}
+
 // Kernel arguments of one frame on the compact path, laid out in the
 // frame's workspace b.
 struct LeanPlan {
-    bool has_hard = false, has_map = false;
+    bool has_hard = false, has_map = false, has_bl = false;
+    BilateralArgs bl{};
     HardArgs ha{};
     EdgeArgs ea{};
     LeanArgs la{};
@@ -794,6 +820,41 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         }
     }
     build_eval(effect, &d->g, &d->cam, g, &m, params, lo, /*compact=*/true, &la, d->level_dtype == MR_F16, P.ev);
+    // bilateral blur of chosen SSAO levels into their second buffers
+    void* merged[kMaxLevels] = {};
+    for (int j = 0; j < g.nlev; ++j) merged[g.levels[j] - 1] = lo[g.levels[j] - 1];
+    if (effect == MR_EFFECT_SSAO && d->bilateral.levels) {
+        BilateralArgs& bl = P.bl;
+        bl.counts = count;
+        bl.R = d->bilateral.radius;
+        bl.drel = d->bilateral.depth_rel;
+        bl.c16 = d->level_dtype == MR_F16 ? 1 : 0;
+        for (int k = 0; k <= 2 * bl.R; ++k) {
+            int binom = 1;  // C(2R, k)
+            for (int q = 0; q < k; ++q) binom = binom * (2 * bl.R - q) / (q + 1);
+            bl.wb[k] = (float)binom / (float)(1 << (2 * bl.R));
+        }
+        for (int j = 0; j < g.nlev; ++j) {
+            const int i = g.levels[j];
+            if (!((d->bilateral.levels >> (i - 1)) & 1u)) continue;
+            BilateralLevel& B = bl.lv[bl.nlev++];
+            B.z = i == 1 ? d->g.depth : reinterpret_cast<const float*>(b + f.zi[i - 1]);
+            B.c = lo[i - 1];
+            B.out = b + (i < g.L ? f.bc[i - 1] : f.bL);
+            B.W = g.Wi[i - 1];
+            B.H = g.Hi[i - 1];
+            B.dense_n = (unsigned)g.n(i);
+            if (i < g.L) {
+                B.list = la.lv[j].list;
+                B.Sb = la.lv[j].Sb;
+                B.woff = la.lv[j].woff;
+                B.wpr = la.lv[j].wpr;
+                B.count_idx = la.lv[j].count_idx;
+            }
+            merged[i - 1] = B.out;
+        }
+        P.has_bl = bl.nlev > 0;
+    }
     // merge by rank
     LeanMergeArgs& ma = P.ma;
     ma.nlev = g.nlev;
@@ -811,7 +872,7 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         L.W = g.Wi[i - 1];
         L.H = g.Hi[i - 1];
         L.w = d->mp.weight[i - 1];
-        L.c = lo[i - 1];
+        L.c = merged[i - 1];
         L.c_plane = g.n(i);
         if (i < g.L) {
             L.Sb = la.lv[j].Sb;
@@ -841,6 +902,8 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         return fail(MR_E_DEVICE, "level map kernel launch failed");
     if ((st = mark(d, 1, s))) return st;
     if ((st = launch_eval(P.ev, d->g.normal_dtype, d->g.color_dtype, s))) return st;
+    if (P.has_bl && launch_bilateral(P.bl, P.ev.hint, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "bilateral blur kernel launch failed");
     if ((st = mark(d, 2, s))) return st;
     if (launch_lean_merge(P.ma, s) != hipSuccess) return fail(MR_E_DEVICE, "merge kernel launch failed");
     return mark(d, 3, s);
@@ -886,6 +949,7 @@ int check_batch(const mr_frame_desc* fr, int n, Geo* geos) {
         if (d.effect != f0.effect) return fail(MR_E_PARAM, "frame %d: effect differs from frame 0", k);
         if (!d.multires) return fail(MR_E_PARAM, "frame %d: batches are multi-resolution only", k);
         if (d.level_map) return fail(MR_E_PARAM, "frame %d: level_map is not produced in batches", k);
+        if (d.bilateral.levels) return fail(MR_E_PARAM, "frame %d: batches do not apply the bilateral blur", k);
         const void* p = d.effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
         const void* p0 = f0.effect == MR_EFFECT_SSAO ? (const void*)f0.ssao : (const void*)f0.ssgi;
         int st = check_effect_params(d.effect, d.ssao, d.shadow, d.ssgi);
@@ -1107,6 +1171,7 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if (d->level_dtype != MR_F32 && d->level_dtype != MR_F16)
         return fail(MR_E_DTYPE, "level_dtype %d is neither MR_F32 nor MR_F16", d->level_dtype);
     if (!d->multires) {
+        if (d->bilateral.levels) return fail(MR_E_PARAM, "the bilateral blur needs multires = 1");
         Geo g;
         st = check_geo(&d->cam, nullptr, g);
         if (!st) st = check_gbuffer(&d->g, effect != MR_EFFECT_SHADOW, effect == MR_EFFECT_SSGI);
@@ -1123,6 +1188,7 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if (!st) st = check_gbuffer(&d->g, true, effect == MR_EFFECT_SSGI);
     if (st) return st;
     if (d->level_map && misaligned(d->level_map)) return fail(MR_E_PARAM, "level_map is not 16-byte aligned");
+    if ((st = check_bilateral(d, g))) return st;
     const FrameLayout f = frame_layout(g, effect);
     const size_t lean_bytes = lean_layout(g, effect).bytes;
     const size_t need = f.bytes > lean_bytes ? f.bytes : lean_bytes;

@@ -268,6 +268,29 @@ struct LeanMergeArgs {
     float* out;
 };
 
+// bilateral blur of SSAO sub-images (compact frame path): levels below the
+// coarsest hold their values by rank, the coarsest densely
+struct BilateralLevel {
+    const float* z;        // level depth, dense W x H
+    const void* c;         // values (f32, or f16 when c16)
+    void* out;             // blurred values, same layout and type
+    const uint32_t* list;  // rendered texels by rank; null: dense level
+    const uint32_t* Sb;    // stencil bits (list levels)
+    const uint32_t* woff;  // rank of each stencil word's first texel
+    int W, H, wpr, count_idx;
+    unsigned dense_n;
+};
+
+struct BilateralArgs {
+    BilateralLevel lv[kMaxLevels];  // the blurred levels, ascending
+    int nlev;
+    const uint32_t* counts;
+    int R;
+    float wb[5];  // binomial weights of order 2R
+    float drel;
+    int c16;
+};
+
 // ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 // ---------------------------------------------------------------------------
@@ -287,6 +310,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s);
 hipError_t launch_lean_level_map(const LeanMapArgs& a, hipStream_t s);
 hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s);
+hipError_t launch_bilateral(const BilateralArgs& a, unsigned total_hint, hipStream_t s);
 bool merge4_applies(const LeanMergeArgs& a);
 
 // edge kernel tiling for an image (the choice launch_edges makes)

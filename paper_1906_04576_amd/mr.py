@@ -75,13 +75,30 @@ class mr_shadow_params(ctypes.Structure):
                 ("n_blocker", ctypes.c_int), ("n_pcf", ctypes.c_int)]
 
 
+class mr_bilateral_params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("radius", ctypes.c_int), ("depth_rel", ctypes.c_float)]
+
+
+@dataclass
+class Bilateral:
+    """Bilateral blur of SSAO sub-images before the merge: bit i-1 of
+    `levels` blurs level i; (2 radius + 1)^2 window; depth tolerance
+    depth_rel relative to the centre depth."""
+    levels: int = 0b1110
+    radius: int = 2
+    depth_rel: float = 0.05
+
+    def c(self) -> mr_bilateral_params:
+        return mr_bilateral_params(int(self.levels), int(self.radius), float(self.depth_rel))
+
+
 class mr_frame_desc(ctypes.Structure):
     _fields_ = [("effect", ctypes.c_int), ("multires", ctypes.c_int), ("g", mr_gbuffer),
                 ("cam", mr_camera), ("mp", mr_mask_params),
                 ("ssao", ctypes.POINTER(mr_ssao_params)), ("shadow", ctypes.POINTER(mr_shadow_params)),
                 ("ssgi", ctypes.POINTER(mr_ssgi_params)), ("out", ctypes.c_void_p),
                 ("level_map", ctypes.c_void_p), ("level_dtype", ctypes.c_int),
-                ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS)]
+                ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS), ("bilateral", mr_bilateral_params)]
 
 
 class mr_batch_config(ctypes.Structure):
@@ -481,7 +498,7 @@ class FrameRunner:
     once so that repeated calls cost one ctypes call each."""
 
     def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
-                 out=None, level_map=None, workspace=None, level_dtype=torch.float32):
+                 out=None, level_map=None, workspace=None, level_dtype=torch.float32, bilateral: Bilateral = None):
         self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         H, W = depth.shape
         C = 3 if self.effect == MR_EFFECT_SSGI else 1
@@ -503,6 +520,8 @@ class FrameRunner:
         d.out = _ptr(self.out)
         d.level_map = _ptr(level_map)
         d.level_dtype = MR_F16 if level_dtype == torch.float16 else MR_F32
+        if bilateral is not None:
+            d.bilateral = bilateral.c()
         self.desc = d
         self._keep = (depth, normal, color, level_map)
         nws = mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0
@@ -540,9 +559,9 @@ class FrameRunner:
 
 
 def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,
-             level_map=None, stream=None, level_dtype=torch.float32):
+             level_map=None, stream=None, level_dtype=torch.float32, bilateral: Bilateral = None):
     return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map,
-                       level_dtype=level_dtype)(stream)
+                       level_dtype=level_dtype, bilateral=bilateral)(stream)
 
 
 class Batch:

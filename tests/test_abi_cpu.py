@@ -43,7 +43,7 @@ def test_struct_sizes_match_header_layout():
 
 
 STRUCTS = ["mr_gbuffer", "mr_camera", "mr_fovea", "mr_mask_params", "mr_masks", "mr_ssao_params", "mr_shadow_params",
-           "mr_ssgi_params", "mr_frame_desc", "mr_batch_config"]
+           "mr_ssgi_params", "mr_frame_desc", "mr_batch_config", "mr_bilateral_params"]
 
 
 @pytest.mark.skipif(not shutil.which("gcc"), reason="needs a C compiler")

@@ -121,3 +121,32 @@ def test_config_calls_need_a_filled_plan():
     assert L.mr_batch_get_config(pp, None) == mr.MR_E_NULL
     assert L.mr_batch_set_config(pp, None) == mr.MR_E_NULL
     assert L.mr_batch_tune(None, 3, None, None) == mr.MR_E_NULL
+
+
+@pytest.mark.parametrize("mutate,text", [
+    (lambda d: setattr(d, "effect", mr.MR_EFFECT_SSGI), "MR_EFFECT_SSAO only"),
+    (lambda d: setattr(d.cam, "width", 320), "compact frame path"),
+    (lambda d: setattr(d.bilateral, "levels", 0b10001), "not enabled"),
+    (lambda d: setattr(d.bilateral, "radius", 3), "radius"),
+    (lambda d: setattr(d.bilateral, "depth_rel", 0.0), "depth_rel"),
+    (lambda d: setattr(d.bilateral, "depth_rel", float("nan")), "depth_rel"),
+    (lambda d: setattr(d, "multires", 0), "multires"),
+])
+def test_frame_rejects_bilateral_misuse(mutate, text):
+    """Validation of the bilateral blur happens before anything is enqueued
+    (the stand-in addresses are never touched)."""
+    d = desc(256, 128)
+    d.bilateral = mr.Bilateral(levels=0b1110, radius=2).c()
+    if "SSGI" in text or "MR_EFFECT_SSAO" in text:
+        d.ssgi = d.ssao
+        d.g.color = FAKE * 3
+    mutate(d)
+    st = mr.lib().mr_frame(ctypes.byref(d), FAKE, 1 << 40, None)
+    assert st == mr.MR_E_PARAM, (st, mr.mr_last_error())
+    assert text in mr.mr_last_error(), mr.mr_last_error()
+
+
+def test_batch_rejects_bilateral():
+    d = desc(256, 128)
+    d.bilateral = mr.Bilateral().c()
+    assert ws_bytes(arr(desc(), d)) == 0 and "bilateral" in mr.mr_last_error()
