@@ -25,6 +25,8 @@ for Computationally Expensive Lighting Effects", arXiv 1906.04576):
 * ``ssgi``    - Sec. 2.4: one-bounce screen-space indirect light.
 * ``bilateral`` - Sec. 4.1: optional depth-aware blur of SSAO sub-images
                 inside each level's stencil.
+* ``frame_fullres_levels`` - Sec. 6: sub-images realised at full resolution
+                with fewer samples, blended with the masks' alpha.
 * ``frame``   - the whole per-frame pipeline for one effect.
 
 Arithmetic contract (so the GPU path can be compared bit for bit): every
@@ -40,16 +42,17 @@ reading is marked "reading:" at the place it is used.
 from .masks import (MaskParams, edge_image, foveate, gaussian_weights, blur_radius, or_pool,
                     build_pyramid, Pyramid, level_sample, work_lists, level_dims)
 from .ssao import SSAOParams, ssao_texels, ssao_level, ssao_plain
-from .merge import upsample_merge
+from .merge import upsample_merge, upsampled_alpha
 from .shadow import ShadowParams, light_coords, hard_shadow, shadow_edges, pcss_texels, pcss_level
 from .ssgi import SSGIParams, ssgi_texels, ssgi_level
 from .bilateral import BilateralParams, binomial_weights, bilateral_level
-from .frame import frame, Frame
+from .frame import frame, frame_fullres_levels, Frame
 
 __all__ = [
     "MaskParams", "edge_image", "foveate", "gaussian_weights", "blur_radius", "or_pool", "build_pyramid",
     "Pyramid", "level_sample", "work_lists", "level_dims", "SSAOParams", "ssao_texels",
     "ssao_level", "ssao_plain", "upsample_merge", "ShadowParams", "light_coords", "hard_shadow",
     "shadow_edges", "pcss_texels", "pcss_level", "SSGIParams", "ssgi_texels", "ssgi_level",
-    "BilateralParams", "binomial_weights", "bilateral_level", "frame", "Frame",
+    "BilateralParams", "binomial_weights", "bilateral_level", "frame", "frame_fullres_levels", "Frame",
+    "upsampled_alpha",
 ]

@@ -12,7 +12,7 @@ import numpy as np
 
 from .masks import MaskParams, edge_image, foveate, build_pyramid, level_sample, Pyramid
 from .ssao import SSAOParams, ssao_level
-from .merge import upsample_merge
+from .merge import upsample_merge, upsampled_alpha
 from .shadow import ShadowParams, hard_shadow, shadow_edges, pcss_level
 from .ssgi import SSGIParams, ssgi_level
 from .bilateral import BilateralParams, bilateral_level
@@ -72,4 +72,29 @@ def frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, c
                 lo[i] = lo[i].astype(level_dtype).astype(dtype)
     weights = {i: mp.weight[i - 1] for i in pyr.levels}
     out = upsample_merge(W, H, pyr.levels, weights, pyr.alpha, pyr.stencil, lo, channels, dtype)
+    return Frame(out=out, pyramid=pyr, level_out=lo)
+
+
+def frame_fullres_levels(depth, normal, focal, mp: MaskParams, level_params: dict, dtype=np.float32) -> Frame:
+    """SSAO with the sub-images realised at full resolution with fewer
+    samples instead of at a lower resolution (Sec. 6).
+
+    reading: every enabled level keeps its mask (stencil, a_i and the Eq. 1
+    blend weight alpha_i at full resolution, exactly as in the merge), but
+    its value at a pixel is the SSAO of that full-resolution pixel with the
+    level's own sample set level_params[i] (an SSAOParams, typically with
+    fewer samples for coarser levels).  The blend is Eq. 1 from the coarsest
+    level: out = c_L; out = c_i alpha_i + out (1 - alpha_i) for the finer
+    levels, coarse to fine."""
+    H, W = depth.shape
+    E = edge_image(depth, normal, mp.depth_ratio, mp.normal_cos, dtype)
+    E = foveate(E, mp.fovea)
+    pyr = build_pyramid(E, mp, dtype)
+    L = pyr.levels[-1]
+    one = dtype(1)
+    lo = {i: ssao_level(depth, normal, focal, 1, level_params[i], None, dtype) for i in pyr.levels}
+    out = lo[L]
+    for i in reversed(pyr.levels[:-1]):
+        a = upsampled_alpha(W, H, i, mp.weight[i - 1], pyr.alpha[i], pyr.stencil[i], dtype)
+        out = (lo[i] * a + out * (one - a)).astype(dtype)
     return Frame(out=out, pyramid=pyr, level_out=lo)

@@ -36,6 +36,33 @@ def _bilinear_setup(n_full, s, n_level, dtype):
     return i0, i1, fx
 
 
+def upsampled_alpha(width, height, level, weight, alpha_i, stencil_i, dtype=np.float32):
+    """alpha_i at every full-resolution pixel, as the merge blends with it:
+    min(A w, 1) with A the bilinear of a_i over the four taps, and 0 where
+    none of the taps lies in the stencil (den = 0)."""
+    one = dtype(1.0)
+    zero = dtype(0.0)
+    s = 1 << (level - 1)
+    Si = np.asarray(stencil_i).astype(bool)
+    Hi, Wi = Si.shape
+    xi0, xi1, fx = _bilinear_setup(width, s, Wi, dtype)
+    yi0, yi1, fy = _bilinear_setup(height, s, Hi, dtype)
+    FX = fx[None, :]
+    FY = fy[:, None]
+    b = [(one - FX) * (one - FY), FX * (one - FY), (one - FX) * FY, FX * FY]
+    taps = [(yi0[:, None], xi0[None, :]), (yi0[:, None], xi1[None, :]),
+            (yi1[:, None], xi0[None, :]), (yi1[:, None], xi1[None, :])]
+    den = np.zeros((height, width), dtype)
+    for t, (ty, tx) in enumerate(taps):
+        den = den + np.where(Si[ty, tx], b[t], zero)
+    ai = np.asarray(alpha_i).astype(dtype)
+    A = np.zeros((height, width), dtype)
+    for t, (ty, tx) in enumerate(taps):
+        A = A + b[t] * ai[ty, tx]
+    al = np.minimum(A * dtype(weight), one)
+    return np.where(den > zero, al, zero)
+
+
 def upsample_merge(width, height, levels, weights, alpha, stencil, level_out, channels=1,
                    dtype=np.float32):
     """Final image [C][H][W] (or [H][W] when channels == 1).
