@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-stages", action="store_true")
     ap.add_argument("--streams", type=int, default=2,
                     help="also report throughput with frames spread over this many streams (1 = off)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the paper variants (bilateral blur, foveated mask, fewer samples at full resolution)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched uneven-frame SSGI measurement (24 frames, 640x360..3840x2160)")
     ap.add_argument("--no-quality", action="store_true", help="profile helper: skip the multi vs naive comparison")
@@ -175,6 +177,61 @@ def main():
         conc = {"streams": args.streams, "mpixels_s": round(npx / tm2 / 1e6, 2),
                 "plain_mpixels_s": round(npx / tp2 / 1e6, 2), "speedup_vs_plain": round(tp2 / tm2, 3)}
         log(f"[bench] {args.streams} streams: multi-res {tm2 * 1e3:.3f} ms/frame, plain {tp2 * 1e3:.3f} ms/frame")
+
+    # ---------------- paper variants on the same frames ----------------
+    # bilateral blur of the SSAO sub-images, a foveated mask (gaze at the
+    # centre), and the sub-images at full resolution with fewer samples
+    # (S, S/2, S/4, S/8 per level) from the dense masks
+    variants = None
+    if not args.no_variants:
+        def wall(runners, steps):
+            for k in range(4):
+                runners[k % nf]()
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for k in range(steps):
+                runners[k % nf]()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t_start) / steps
+
+        vsteps = max(24, args.steps // 4)
+        variants = {}
+        for name, bl in (("bilateral_levels_2_4", mr.Bilateral(levels=0b1110, radius=2)),
+                         ("bilateral_all_levels", mr.Bilateral(levels=0b1111, radius=2))):
+            rs = [mr.FrameRunner("ssao", f["d"], f["n"], focal, mp, True, params=sp, workspace=ws, bilateral=bl)
+                  for f in frames]
+            variants[name + "_ms"] = round(wall(rs, vsteps) * 1e3, 5)
+        fmp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=mp.sigma2, weight=mp.weight,
+                            fovea=(W / 2, H / 2, 0.15 * H, 0.45 * H))
+        rs = [mr.FrameRunner("ssao", f["d"], f["n"], focal, fmp, True, params=sp, workspace=ws) for f in frames]
+        variants["fovea_ms"] = round(wall(rs, vsteps) * 1e3, 5)
+        Kl = {i: scenegen.ssao_kernel(max(1, S >> (i - 1)), seed=70 + i) for i in (1, 2, 3, 4)}
+        Kd = {i: torch.from_numpy(Kl[i]).to(dev) for i in Kl}
+        lp = {i: mr.ssao_params(Kd[i], args.radius, 0.02) for i in Kl}
+        dmasks = mr.alloc_masks(W, H, focal, mp, dev, level_map=False)
+        fr_out = torch.empty((H, W), dtype=torch.float32, device=dev)
+
+        class _Full:
+            def __init__(self, f):
+                self.m = mr.prepare_build_masks(f["d"], f["n"], focal, mp, dmasks)
+                self.e = mr.FullresRunner(f["d"], f["n"], focal, mp, dmasks, lp, out=fr_out)
+
+            def __call__(self):
+                self.m()
+                return self.e()
+
+        rs = [_Full(f) for f in frames]
+        t_full = wall(rs, vsteps)
+        mad_full = []
+        for k in range(0 if args.no_quality else min(nf, 8)):
+            a = rs[k]().clone()
+            b = plain[k]()
+            mad_full.append(float((a - b).double().abs().mean()))
+        variants.update({"fullres_fewer_samples_ms": round(t_full * 1e3, 5),
+                         "fullres_fewer_samples_mpixels_s": round(npx / t_full / 1e6, 2),
+                         "fullres_fewer_samples_samples": [int(max(1, S >> (i - 1))) for i in (1, 2, 3, 4)],
+                         "fullres_fewer_samples_mad_vs_plain": round(float(np.mean(mad_full)), 6) if mad_full else None})
+        log("[bench] variants: " + ", ".join(f"{k}={v}" for k, v in variants.items()))
 
     # ---------------- quality: multi-res vs naive on every configuration ----------------
     mads, rmss = [], []
@@ -333,6 +390,7 @@ def main():
         "concurrent": conc,
         "stages": stages,
         "roofline": roofline,
+        "variants": variants,
         "batched_ssgi": batched,
         "cpu_baseline": cpu,
     }

@@ -309,6 +309,23 @@ MR_API int mr_upsample_merge(const mr_camera* cam, const mr_mask_params* mp, con
                              const float* const level_out[MR_MAX_LEVELS], int channels, float* out,
                              void* stream);
 
+/* SSAO with the sub-images realised at full resolution with fewer samples
+ * instead of at a lower resolution (Sec. 6).  Every enabled level keeps its
+ * mask from mr_build_masks (alpha and stencil of every enabled level below
+ * the coarsest are read), but its value at a pixel is the SSAO of that
+ * full-resolution pixel with the level's own sample set level_params[i-1]
+ * (each as in mr_eval_ssao, typically fewer samples for coarser levels; at
+ * most 1024 samples over the enabled levels; entries of disabled levels are
+ * ignored).  The levels are blended per pixel with Eq. 1 from the coarsest:
+ * out = c_L, then out = c_i alpha_i + out (1 - alpha_i) for the finer levels,
+ * alpha_i = min(A w_i, 1) with A the bilinear of a_i as in mr_upsample_merge
+ * (0 where no tap is in the stencil).  A level's evaluation is skipped where
+ * alpha_i = 0 and the coarser ones below a level with alpha_i = 1; neither
+ * changes a bit of the result.  out: f32 [H][W]; background pixels 0. */
+MR_API int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp,
+                                const mr_masks* masks, const mr_ssao_params* const level_params[MR_MAX_LEVELS],
+                                float* out, void* stream);
+
 /* Whole frame for one effect: masks (with shadow edges for MR_EFFECT_SHADOW),
  * per-level evaluation and merge, or the naive pass when multires == 0.
  * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */

@@ -1157,6 +1157,58 @@ int mr_upsample_merge(const mr_camera* cam, const mr_mask_params* mp, const mr_m
     return do_merge(g, mp, m, level_out, channels, out, static_cast<hipStream_t>(stream));
 }
 
+int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, const mr_mask_params* mp, const mr_masks* m,
+                         const mr_ssao_params* const level_params[MR_MAX_LEVELS], float* out, void* stream) {
+    if (!mp) return fail(MR_E_NULL, "mask params are NULL");
+    if (!level_params) return fail(MR_E_NULL, "level_params is NULL");
+    Geo g;
+    int st = check_geo(cam, mp, g);
+    if (!st) st = check_mask_params(mp, g);
+    if (!st) st = check_gbuffer(gb, true, false);
+    if (!st) st = check_masks(m, g, true, false);
+    if (st) return st;
+    if (!out) return fail(MR_E_NULL, "out is NULL");
+    if (misaligned(out)) return fail(MR_E_PARAM, "out is not 16-byte aligned");
+    FullresArgs A{};
+    int koff = 0;
+    for (int j = 0; j < g.nlev; ++j) {
+        const int i = g.levels[j];
+        const mr_ssao_params* p = level_params[i - 1];
+        if (!p) return fail(MR_E_NULL, "level_params[%d] is NULL (level %d is enabled)", i - 1, i);
+        if ((st = check_effect_params(MR_EFFECT_SSAO, p, nullptr, nullptr))) return st;
+        FullresLevel& V = A.lv[j];
+        if (i != g.L) {
+            V.a = m->alpha[i - 1];
+            V.S = m->stencil[i - 1];
+        }
+        V.W = g.Wi[i - 1];
+        V.H = g.Hi[i - 1];
+        V.sh = i - 1;
+        V.w = mp->weight[i - 1];
+        V.p = SsaoSampling{p->kernel, p->samples, p->radius, p->bias_rel};
+        V.koff = koff;
+        koff += p->samples;
+    }
+    if (koff > kFullresMaxSamples)
+        return fail(MR_E_PARAM, "%d samples over the levels > %d", koff, kFullresMaxSamples);
+    A.nlev = g.nlev;
+    // full-resolution geometry of the naive pass
+    Geo gp;
+    if ((st = check_geo(cam, nullptr, gp))) return st;
+    EvalPlan E;
+    float* o[kMaxLevels] = {out};
+    build_eval(MR_EFFECT_SSAO, gb, cam, gp, nullptr, level_params[g.levels[0] - 1], o, false, nullptr, false, E);
+    A.L = E.sa.c.lv[0];
+    A.normal = E.sa.c.normal;
+    A.plane = E.sa.c.plane;
+    A.out = out;
+    A.W = g.W;
+    A.H = g.H;
+    if (launch_ssao_fullres(A, gb->normal_dtype, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(MR_E_DEVICE, "full-resolution level kernel launch failed");
+    return MR_OK;
+}
+
 int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);

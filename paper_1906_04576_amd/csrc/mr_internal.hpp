@@ -291,6 +291,34 @@ struct BilateralArgs {
     int c16;
 };
 
+// sub-images at full resolution with fewer samples
+constexpr int kFullresMaxSamples = 1024;  // samples over all levels (staged in LDS)
+
+struct SsaoSampling {
+    const float* kernel;
+    int S;
+    float r, b;
+};
+
+struct FullresLevel {
+    const float* a;    // a_i, dense level image (null for the coarsest)
+    const uint8_t* S;  // stencil, dense level image (null for the coarsest)
+    int W, H, sh;
+    float w;           // blend weight w_i
+    SsaoSampling p;    // the level's samples
+    int koff;          // first sample in the block's LDS copy
+};
+
+struct FullresArgs {
+    FullresLevel lv[kMaxLevels];  // enabled levels ascending; last = coarsest
+    int nlev;
+    EvalLevel L;  // full-resolution geometry
+    const void* normal;
+    long long plane;
+    float* out;
+    int W, H;
+};
+
 // ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 // ---------------------------------------------------------------------------
@@ -311,6 +339,7 @@ hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s);
 hipError_t launch_lean_level_map(const LeanMapArgs& a, hipStream_t s);
 hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s);
 hipError_t launch_bilateral(const BilateralArgs& a, unsigned total_hint, hipStream_t s);
+hipError_t launch_ssao_fullres(const FullresArgs& a, int normal_dtype, hipStream_t s);
 bool merge4_applies(const LeanMergeArgs& a);
 
 // edge kernel tiling for an image (the choice launch_edges makes)

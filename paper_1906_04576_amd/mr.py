@@ -130,6 +130,10 @@ SIGNATURES = {
     "mr_upsample_merge": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                          ctypes.POINTER(mr_masks), ctypes.POINTER(c_ptr6), ctypes.c_int, _P, _P]),
     "mr_frame": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P, ctypes.c_size_t, _P]),
+    "mr_eval_ssao_fullres": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
+                                            ctypes.POINTER(mr_mask_params), ctypes.POINTER(mr_masks),
+                                            ctypes.POINTER(ctypes.POINTER(mr_ssao_params) * MR_MAX_LEVELS),
+                                            _P, _P]),
     "mr_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mr_frame_desc), ctypes.c_int]),
     "mr_batch_setup": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), ctypes.c_int, _P, ctypes.c_size_t, _P,
                                       ctypes.c_size_t, _P]),
@@ -354,6 +358,36 @@ def _eval(name, g, W, H, focal, mp, masks, params_c, C, out, stream):
               ctypes.byref(cm) if cm is not None else None, ctypes.byref(params_c), ctypes.byref(arr),
               _stream(stream)))
     return out
+
+
+class FullresRunner:
+    """Pre-marshalled mr_eval_ssao_fullres call: SSAO with every level's
+    sub-image at full resolution with its own sample set.  level_params:
+    {level: mr_ssao_params} for every enabled level; masks from
+    mr_build_masks of the same frame."""
+
+    def __init__(self, depth, normal, focal, mp: MaskParams, masks: "Masks", level_params: dict, out=None):
+        H, W = depth.shape
+        self.out = out if out is not None else torch.empty((H, W), dtype=torch.float32, device=depth.device)
+        self.g = gbuffer(depth, normal)
+        self.cam = camera(W, H, focal)
+        self.cmp = mp.c()
+        self.cm = masks.c()
+        self.lp = (ctypes.POINTER(mr_ssao_params) * MR_MAX_LEVELS)()
+        for i, p in level_params.items():
+            self.lp[i - 1] = ctypes.pointer(p)
+        self._keep = (depth, normal, masks, level_params)
+        self._fn = lib().mr_eval_ssao_fullres
+
+    def __call__(self, stream=None):
+        _check(self._fn(ctypes.byref(self.g), ctypes.byref(self.cam), ctypes.byref(self.cmp), ctypes.byref(self.cm),
+                        ctypes.byref(self.lp), _ptr(self.out), _stream(stream)))
+        return self.out
+
+
+def mr_eval_ssao_fullres(depth, normal, focal, mp: MaskParams, masks: "Masks", level_params: dict, out=None,
+                         stream=None):
+    return FullresRunner(depth, normal, focal, mp, masks, level_params, out)(stream)
 
 
 def g_device(g):

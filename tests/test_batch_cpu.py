@@ -150,3 +150,26 @@ def test_batch_rejects_bilateral():
     d = desc(256, 128)
     d.bilateral = mr.Bilateral().c()
     assert ws_bytes(arr(desc(), d)) == 0 and "bilateral" in mr.mr_last_error()
+
+
+def test_fullres_levels_validation():
+    """mr_eval_ssao_fullres checks its level sample sets before any launch."""
+    L = mr.lib()
+    g = mr.mr_gbuffer(FAKE, FAKE * 2, mr.MR_F32, None, mr.MR_F32)
+    cam = mr.mr_camera(256, 128, 200.0)
+    mp = mr.MaskParams(num_levels=4).c()
+    m = mr.mr_masks()
+    for i in range(3):
+        m.alpha[i] = FAKE * (8 + i)
+        m.stencil[i] = FAKE * (12 + i)
+    ps = [mr.mr_ssao_params(FAKE * 4, 300, 1.0, 0.02) for _ in range(4)]
+    lp = (ctypes.POINTER(mr.mr_ssao_params) * mr.MR_MAX_LEVELS)()
+    for i in range(3):
+        lp[i] = ctypes.pointer(ps[i])
+    args = lambda: (ctypes.byref(g), ctypes.byref(cam), ctypes.byref(mp), ctypes.byref(m), ctypes.byref(lp),
+                    FAKE * 16, None)
+    assert L.mr_eval_ssao_fullres(*args()) == mr.MR_E_NULL and "level_params[3]" in mr.mr_last_error()
+    lp[3] = ctypes.pointer(ps[3])
+    assert L.mr_eval_ssao_fullres(*args()) == mr.MR_E_PARAM and "1024" in mr.mr_last_error()
+    m.alpha[1] = None
+    assert L.mr_eval_ssao_fullres(*args()) == mr.MR_E_NULL and "alpha[1]" in mr.mr_last_error()
