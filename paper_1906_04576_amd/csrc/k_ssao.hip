@@ -10,7 +10,7 @@ namespace mr {
 // Occluding samples of one texel.  Branch-free: every sample computes its
 // projection and gathers (texel 0 when it is off-screen or behind the eye),
 // and counts only if all tests pass; the count is the same as skipping the
-// sample.  Samples go in groups of kSsaoGroup whose gathers are issued back
+// sample.  Samples go in groups of G whose gathers are issued back
 // to back, so that several are in flight per wave.  FAST: 1/d by
 // recip_fast, which the caller has shown to equal 1.0f / d for every sample
 // of the texel.
@@ -19,7 +19,10 @@ struct SsaoTexel {
     float rtx, rty, rtz, rbx, rby, rbz, rnx, rny, rnz;
 };
 
-constexpr int kSsaoGroup = 4;
+// group sizes (measured): the naive pass over every pixel, and the
+// multi-resolution launches, whose lists are shorter and whose blocks also
+// compute a_i
+constexpr int kGroupPlain = 8, kGroupMulti = 2;
 
 template <bool FAST, typename KP>
 __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, const SsaoTexel& T, unsigned zpy,
@@ -40,12 +43,11 @@ __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, co
     off = __umul24(sy, zpy) + __umul24(sx, zpx);  // element offset
 }
 
-// GROUPED: gathers of a group of samples issued together, one projection
-// at a time (low register use, full occupancy: best when every SIMD has
-// many waves, as in the naive pass); else a plain unrolled loop that the
-// compiler interleaves (more instruction-level parallelism per wave: best
-// for the shorter multi-resolution launch, whose last waves run nearly alone)
-template <bool FAST, bool GROUPED, typename SA, typename KP>
+// Gathers of a group of G samples are issued together, one projection at a
+// time (sched_barrier: interleaving the projections buys little ILP and costs
+// registers, i.e. occupancy); the group size sets how many gathers of a wave
+// are in flight.
+template <bool FAST, int G, typename SA, typename KP>
 __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K, const SsaoTexel& T) {
     const float r = a.r, b = a.b;
     const int S = a.S;
@@ -59,32 +61,21 @@ __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K,
     };
     int occ = 0;
     int s = 0;
-    if (!GROUPED) {
-#pragma unroll 4
-        for (; s < S; ++s) {
-            bool on;
-            float d;
-            unsigned off;
-            ssao_project<FAST>(L, K, s, T, zpy, zpx, on, d, off);
-            occ += occluded(on, d, L.z[off]);
-        }
-        return occ;
-    }
-    for (; s + kSsaoGroup <= S; s += kSsaoGroup) {
-        bool on[kSsaoGroup];
-        float d[kSsaoGroup], zs[kSsaoGroup];
-        unsigned off[kSsaoGroup];
+    for (; s + G <= S; s += G) {
+        bool on[G];
+        float d[G], zs[G];
+        unsigned off[G];
 #pragma unroll
-        for (int k = 0; k < kSsaoGroup; ++k) {
+        for (int k = 0; k < G; ++k) {
             ssao_project<FAST>(L, K, s + k, T, zpy, zpx, on[k], d[k], off[k]);
             // one projection at a time: interleaving them buys little ILP
             // and costs registers (occupancy)
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int k = 0; k < kSsaoGroup; ++k) zs[k] = buf_f1(rz, off[k] * 4u);
+        for (int k = 0; k < G; ++k) zs[k] = buf_f1(rz, off[k] * 4u);
 #pragma unroll
-        for (int k = 0; k < kSsaoGroup; ++k) occ += occluded(on[k], d[k], zs[k]);
+        for (int k = 0; k < G; ++k) occ += occluded(on[k], d[k], zs[k]);
     }
     for (; s < S; ++s) {
         bool on;
@@ -99,7 +90,7 @@ __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K,
 // occlusion of one texel; K points to LDS (staged samples) or global memory;
 // kmax = the largest |component| over the samples (+inf when unknown); a
 // holds the sampling parameters r, b and S (SsaoArgs or SsaoSampling)
-template <typename NT, bool GROUPED, typename SA, typename KP>
+template <typename NT, int G, typename SA, typename KP>
 __device__ __forceinline__ float ssao_texel(const SA& a, const EvalLevel& L, const NT* nrm, unsigned plane,
                                             KP K, float kmax, int x, int y, float z) {
     const float r = a.r;
@@ -118,7 +109,7 @@ __device__ __forceinline__ float ssao_texel(const SA& a, const EvalLevel& L, con
     // these margins all d are in [2^-126, 2^126), where recip_fast is exact.
     const float B0 = kmax * ((fabsf(T.rtz) + fabsf(T.rbz)) + fabsf(T.rnz));
     const bool safe = (z * 0.999f > B0 * 1.001f + 1e-37f) && ((z + B0) * 1.001f < 0x1p125f);
-    const int occ = __ballot(!safe) == 0 ? ssao_count<true, GROUPED>(a, L, K, T) : ssao_count<false, GROUPED>(a, L, K, T);
+    const int occ = __ballot(!safe) == 0 ? ssao_count<true, G>(a, L, K, T) : ssao_count<false, G>(a, L, K, T);
     return (float)occ / (float)a.S;
 }
 
@@ -140,9 +131,9 @@ __device__ __forceinline__ void ssao_item(const SsaoArgs& a, const ItemMap& m, u
     float res = 0.0f;
     if (valid_depth(z)) {
         if (KLDS)
-            res = ssao_texel<NT, !AL>(a, L, nrm, plane, ks, kmax, x, y, z);
+            res = ssao_texel<NT, AL ? kGroupMulti : kGroupPlain>(a, L, nrm, plane, ks, kmax, x, y, z);
         else
-            res = ssao_texel<NT, !AL>(a, L, nrm, plane, a.kernel, kmax, x, y, z);
+            res = ssao_texel<NT, AL ? kGroupMulti : kGroupPlain>(a, L, nrm, plane, a.kernel, kmax, x, y, z);
     }
     store_out(L, L.compact ? local : (unsigned)y * (unsigned)L.W + (unsigned)x, res);
 }
@@ -334,7 +325,7 @@ __global__ __launch_bounds__(256) void k_ssao_fullres(FullresArgs a) {
             const bool need = geo && (j == k || (j < k && alj > 0.0f));
             if (__ballot(need) == 0) continue;
             if (need) {
-                const float v = ssao_texel<NT, true>(sp[j], L, nrm, plane, (const float*)ks + 3 * skoff[j],
+                const float v = ssao_texel<NT, kGroupPlain>(sp[j], L, nrm, plane, (const float*)ks + 3 * skoff[j],
                                                      __uint_as_float(kmax_bits[j]), x, y, z);
                 c = j == k ? v : v * alj + c * (1.0f - alj);
             }
