@@ -336,15 +336,19 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
     for (int r = 0; r < 4; ++r) ro[r] = (unsigned)min(max(yb - 1 + r, 0), H - 1) * (unsigned)W;
     // Side columns xb - 1 and xb + 4 are the neighbouring lanes' pixels (the
     // 16 lanes of a DPP row cover the wave's 64 columns of one row pair);
-    // only the wave's outer columns x0 - 1 and x0 + 64 are loaded, by every
-    // lane of the row from the same address (one cache line).
+    // only the wave's outer columns x0 - 1 and x0 + 64 come from elsewhere.
     const unsigned xl = (unsigned)max(x0 - 1, 0), xr = (unsigned)min(x0 + 64, W - 1);
 
     float z[4][4], n[4][4][3];
     float zs[2][2], ns[2][2][3];
     unsigned hrow[4] = {0, 0, 0, 0}, hside[2][2] = {{0, 0}, {0, 0}};
+    // Rows yb - 1 .. yb + 2: a lane loads its own rows yb, yb + 1; the row
+    // above is the second own row of the lane 16 below (the wave's row pairs
+    // are consecutive) and the row below the first own row of the lane 16
+    // above, except for the wave's first and last row pair, which load the
+    // wave's halo rows.  Every row of the wave is read once.
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 1; r <= 2; ++r) {
         const unsigned e = ro[r] + (unsigned)xc;
         const float4 zv = buf_f4(rz, e * 4u);
         z[r][0] = zv.x;
@@ -363,19 +367,103 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
         }
         if (HARD) hrow[r] = __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0);
     }
+    const bool top = rp == 0, bot = rp == 3;
+    float hz[4] = {0.0f, 0.0f, 0.0f, 0.0f}, hn[4][3] = {};
+    unsigned hh = 0u;
+    if (top || bot) {
+        const unsigned e = (top ? ro[0] : ro[3]) + (unsigned)xc;
+        const float4 zv = buf_f4(rz, e * 4u);
+        hz[0] = zv.x;
+        hz[1] = zv.y;
+        hz[2] = zv.z;
+        hz[3] = zv.w;
+        float t0[4], t1[4], t2[4];
+        NormalRow<NT>::load4(rn0, e, t0);
+        NormalRow<NT>::load4(rn1, e, t1);
+        NormalRow<NT>::load4(rn2, e, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            hn[k][0] = t0[k];
+            hn[k][1] = t1[k];
+            hn[k][2] = t2[k];
+        }
+        if (HARD) hh = __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0);
+    }
+    const int lup = (lane + 48) & 63, ldn = (lane + 16) & 63;  // lanes 16 below / above
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float za = __shfl(z[2][k], lup, 64), zb = __shfl(z[1][k], ldn, 64);
+        z[0][k] = top ? hz[k] : za;
+        z[3][k] = bot ? hz[k] : zb;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float na = __shfl(n[2][k][c], lup, 64), nb_ = __shfl(n[1][k][c], ldn, 64);
+            n[0][k][c] = top ? hn[k][c] : na;
+            n[3][k][c] = bot ? hn[k][c] : nb_;
+        }
+    }
+    if (HARD) {
+        const unsigned ha = (unsigned)__shfl((int)hrow[2], lup, 64), hb = (unsigned)__shfl((int)hrow[1], ldn, 64);
+        hrow[0] = top ? hh : ha;
+        hrow[3] = bot ? hh : hb;
+    }
+    // Side columns x0 - 1 and x0 + 64 of the own rows.  With WIDE the four
+    // waves of the block sit side by side: a wave's side column is a
+    // neighbouring wave's first or last column, passed through LDS; only
+    // the block's outer columns are loaded.  Otherwise every lane of a row
+    // loads them from the same address (one cache line).
+    auto load_side = [&](int r, int sd) {
+        const unsigned e = ro[r + 1] + (sd ? xr : xl);
+        zs[r][sd] = buf_f1(rz, e * 4u);
+        ns[r][sd][0] = NormalRow<NT>::load1(rn0, e);
+        ns[r][sd][1] = NormalRow<NT>::load1(rn1, e);
+        ns[r][sd][2] = NormalRow<NT>::load1(rn2, e);
+        if (HARD) hside[r][sd] = __builtin_amdgcn_raw_buffer_load_b8(rh, e, 0, 0);
+    };
+    if (WIDE) {
+        __shared__ float sidex[4][2][8][5];  // [wave][first / last column][row][z, n, hard bits]
+        const int rr = 2 * rp;
+        if (cg == 0 || cg == 15) {
+            const int sd = cg == 15 ? 1 : 0, k = sd ? 3 : 0;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                float* o = sidex[wave][sd][rr + r];
+                o[0] = z[r + 1][k];
+                o[1] = n[r + 1][k][0];
+                o[2] = n[r + 1][k][1];
+                o[3] = n[r + 1][k][2];
+                o[4] = __uint_as_float(HARD ? (hrow[r + 1] >> (8 * k)) & 0xFFu : 0u);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) {
+                const int nw = sd ? wave + 1 : wave - 1;  // the neighbouring wave (uniform)
+                if (nw < 0 || nw > 3) {
+                    load_side(r, sd);
+                } else {
+                    const float* i = sidex[nw][1 - sd][rr + r];
+                    zs[r][sd] = i[0];
+                    ns[r][sd][0] = i[1];
+                    ns[r][sd][1] = i[2];
+                    ns[r][sd][2] = i[3];
+                    hside[r][sd] = __float_as_uint(i[4]);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            load_side(r, 0);
+            load_side(r, 1);
+        }
+    }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int sd = 0; sd < 2; ++sd) {
-            const unsigned e = ro[r + 1] + (sd ? xr : xl);
-            zs[r][sd] = buf_f1(rz, e * 4u);
-            ns[r][sd][0] = NormalRow<NT>::load1(rn0, e);
-            ns[r][sd][1] = NormalRow<NT>::load1(rn1, e);
-            ns[r][sd][2] = NormalRow<NT>::load1(rn2, e);
-            if (HARD) hside[r][sd] = __builtin_amdgcn_raw_buffer_load_b8(rh, e, 0, 0);
-        }
         // lane cg takes column xb - 1 from lane cg - 1 and xb + 4 from lane
-        // cg + 1; lanes 0 and 15 of the row keep the loaded outer columns
+        // cg + 1; lanes 0 and 15 of the row keep the side columns
         zs[r][0] = dpp_shr1(zs[r][0], z[r + 1][3]);
         zs[r][1] = dpp_shl1(zs[r][1], z[r + 1][0]);
 #pragma unroll
