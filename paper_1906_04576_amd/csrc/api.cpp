@@ -1026,7 +1026,7 @@ int run_plan(const BatchPlan& P, hipStream_t s) {
     if (P.effect == MR_EFFECT_SSAO)
         e = launch_ssao_batch(static_cast<const SsaoArgs*>(P.tv), P.n, P.S, P.ndt, P.eval_hint, bs, s);
     else
-        e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.ndt, P.cdt, P.eval_hint, bs, s);
+        e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.S, P.ndt, P.cdt, P.eval_hint, bs, s);
     if (e != hipSuccess) return fail(MR_E_DEVICE, "batched evaluation kernel launch failed");
     if (launch_lean_merge_batch(P.tm, P.merge_base, P.merge_tx, P.n, P.merge_total, P.C, P.c16,
                                 P.m4_ok && !c.merge_generic, s) != hipSuccess)

@@ -9,6 +9,9 @@
 
 namespace mr {
 
+// depth gathers in flight per sample group of the naive pass (measured)
+constexpr int kSsgiGroup = 8;
+
 // one item (a listed texel, or a texel of a dense level)
 template <typename NT, typename CT, bool AL, typename KP>
 __device__ __forceinline__ void ssgi_item(const SsgiArgs& a, const ItemMap& m, unsigned item, KP K,
@@ -42,38 +45,125 @@ __device__ __forceinline__ void ssgi_item(const SsgiArgs& a, const ItemMap& m, u
             const float rtx = r * tx, rty = r * ty, rtz = r * tz;
             const float rbx = r * bx, rby = r * by, rbz = r * bz;
             const float rnx = r * nx, rny = r * ny, rnz = r * nz;
-            const float Wf = (float)L.W, Hf = (float)L.H;
-            for (int s = 0; s < S; ++s) {
-                const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
-                const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
-                const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
-                const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
-                const float d = -qz;
-                if (!(d > 0.0f)) continue;
-                const float inv = recip_pos(d);  // = 1.0f / d (d > 0)
-                const float u = L.cx + (qx * inv) * L.f;
-                const float v = L.cy - (qy * inv) * L.f;
-                if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
-                const int sx = (int)floorf(u), sy = (int)floorf(v);
-                const float zs = L.z[(unsigned)sy * L.zpy + (unsigned)sx * L.zpx];
-                if (!valid_depth(zs)) continue;
-                if (!(zs < d - (b * d) && fabsf(z - zs) < r)) continue;
-                float hx, hy, hz;
-                view_pos(sx, sy, zs, L.f, L.cx, L.cy, hx, hy, hz);
-                const float vx = hx - px, vy = hy - py, vz = hz - pz;
-                const float dd = ((vx * vx) + (vy * vy)) + (vz * vz);
-                if (!(dd > 0.0f)) continue;
-                const float dist2 = fmaxf(dd, rmin2);
-                const float il = rsqrt_pos(dd);  // = 1.0f / sqrtf(dd) (dd > 0)
-                const float vhx = vx * il, vhy = vy * il, vhz = vz * il;
-                const long long gt = L.goff + (long long)sy * L.gpy + (long long)sx * L.gpx;
-                const float mx = ld(nrm, gt), my = ld(nrm, plane + gt), mz = ld(nrm, 2 * plane + gt);
-                const float cr = fmaxf(0.0f, ((nx * vhx) + (ny * vhy)) + (nz * vhz));
-                const float ce = fmaxf(0.0f, -(((mx * vhx) + (my * vhy)) + (mz * vhz)));
-                const float w = (cr * ce) / dist2;
-                acc0 = acc0 + ld(col, gt) * w;
-                acc1 = acc1 + ld(col, plane + gt) * w;
-                acc2 = acc2 + ld(col, 2 * plane + gt) * w;
+            if constexpr (AL) {
+                // multi-resolution launches: one pass over the samples (their
+                // texels sit near edges, where many samples occlude)
+                const float Wf = (float)L.W, Hf = (float)L.H;
+                for (int s = 0; s < S; ++s) {
+                    const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
+                    const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
+                    const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
+                    const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
+                    const float d = -qz;
+                    if (!(d > 0.0f)) continue;
+                    const float inv = recip_pos(d);  // = 1.0f / d (d > 0)
+                    const float u = L.cx + (qx * inv) * L.f;
+                    const float v = L.cy - (qy * inv) * L.f;
+                    if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
+                    const int sx = (int)floorf(u), sy = (int)floorf(v);
+                    const float zs = L.z[(unsigned)sy * L.zpy + (unsigned)sx * L.zpx];
+                    if (!valid_depth(zs)) continue;
+                    if (!(zs < d - (b * d) && fabsf(z - zs) < r)) continue;
+                    float hx, hy, hz;
+                    view_pos(sx, sy, zs, L.f, L.cx, L.cy, hx, hy, hz);
+                    const float vx = hx - px, vy = hy - py, vz = hz - pz;
+                    const float dd = ((vx * vx) + (vy * vy)) + (vz * vz);
+                    if (!(dd > 0.0f)) continue;
+                    const float dist2 = fmaxf(dd, rmin2);
+                    const float il = rsqrt_pos(dd);  // = 1.0f / sqrtf(dd) (dd > 0)
+                    const float vhx = vx * il, vhy = vy * il, vhz = vz * il;
+                    const long long gt = L.goff + (long long)sy * L.gpy + (long long)sx * L.gpx;
+                    const float mx = ld(nrm, gt), my = ld(nrm, plane + gt), mz = ld(nrm, 2 * plane + gt);
+                    const float cr = fmaxf(0.0f, ((nx * vhx) + (ny * vhy)) + (nz * vhz));
+                    const float ce = fmaxf(0.0f, -(((mx * vhx) + (my * vhy)) + (mz * vhz)));
+                    const float w = (cr * ce) / dist2;
+                    acc0 = acc0 + ld(col, gt) * w;
+                    acc1 = acc1 + ld(col, plane + gt) * w;
+                    acc2 = acc2 + ld(col, 2 * plane + gt) * w;
+                }
+            } else {
+                const float Wf = (float)L.W, Hf = (float)L.H;
+                // sample s: its point, depth d, and the texel it projects to
+                auto project = [&](int s, float& d, bool& on, int& sx, int& sy) {
+                    const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
+                    const float qx = ((px + kx * rtx) + ky * rbx) + kz * rnx;
+                    const float qy = ((py + kx * rty) + ky * rby) + kz * rny;
+                    const float qz = ((pz + kx * rtz) + ky * rbz) + kz * rnz;
+                    d = -qz;
+                    const float inv = recip_pos(d);  // = 1.0f / d when d > 0 (else unused)
+                    const float u = L.cx + (qx * inv) * L.f;
+                    const float v = L.cy - (qy * inv) * L.f;
+                    on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
+                    sx = (int)(on ? u : 0.0f);  // u, v >= 0 when on: truncation is floor
+                    sy = (int)(on ? v : 0.0f);
+                };
+                // L is wave-uniform: the depth plane as a buffer resource
+                const unsigned zpy = (unsigned)L.zpy, zpx = (unsigned)L.zpx;
+                const __amdgpu_buffer_rsrc_t rz =
+                    buf_rsrc(L.z, ((unsigned)(L.H - 1) * zpy + (unsigned)(L.W - 1) * zpx + 1u) * 4u);
+                // a sample adds light iff it occludes: on screen, valid depth
+                // z_s below the biased sample depth and within the radius
+                auto occludes = [&](bool on, float d, float zs) {
+                    return on & (zs > 0.0f) & (zs < d - (b * d)) & (fabsf(z - zs) < r);
+                };
+                // Per block of 32 samples: first which samples occlude (the
+                // depth gathers of kSsgiGroup samples in flight together), then
+                // the light of exactly those samples in sample order, so that
+                // the sums are the ones of one pass over the samples.
+                for (int s0 = 0; s0 < S; s0 += 32) {
+                    const int ns = min(32, S - s0);
+                    unsigned hits = 0u;
+                    int k0 = 0;
+                    for (; k0 + kSsgiGroup <= ns; k0 += kSsgiGroup) {
+                        float d[kSsgiGroup], zs[kSsgiGroup];
+                        bool on[kSsgiGroup];
+                        unsigned off[kSsgiGroup];
+    #pragma unroll
+                        for (int k = 0; k < kSsgiGroup; ++k) {
+                            int sx, sy;
+                            project(s0 + k0 + k, d[k], on[k], sx, sy);
+                            off[k] = __umul24((unsigned)sy, zpy) + __umul24((unsigned)sx, zpx);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+    #pragma unroll
+                        for (int k = 0; k < kSsgiGroup; ++k) zs[k] = buf_f1(rz, off[k] * 4u);
+    #pragma unroll
+                        for (int k = 0; k < kSsgiGroup; ++k) hits |= occludes(on[k], d[k], zs[k]) ? 1u << (k0 + k) : 0u;
+                    }
+                    for (; k0 < ns; ++k0) {
+                        float d;
+                        bool on;
+                        int sx, sy;
+                        project(s0 + k0, d, on, sx, sy);
+                        const float zs = buf_f1(rz, (__umul24((unsigned)sy, zpy) + __umul24((unsigned)sx, zpx)) * 4u);
+                        hits |= occludes(on, d, zs) ? 1u << k0 : 0u;
+                    }
+                    while (hits) {
+                        const int k = __builtin_ctz(hits);
+                        hits &= hits - 1;
+                        float d;
+                        bool on;
+                        int sx, sy;
+                        project(s0 + k, d, on, sx, sy);
+                        const float zs = L.z[(unsigned)sy * zpy + (unsigned)sx * zpx];
+                        float hx, hy, hz;
+                        view_pos(sx, sy, zs, L.f, L.cx, L.cy, hx, hy, hz);
+                        const float vx = hx - px, vy = hy - py, vz = hz - pz;
+                        const float dd = ((vx * vx) + (vy * vy)) + (vz * vz);
+                        if (!(dd > 0.0f)) continue;
+                        const float dist2 = fmaxf(dd, rmin2);
+                        const float il = rsqrt_pos(dd);  // = 1.0f / sqrtf(dd) (dd > 0)
+                        const float vhx = vx * il, vhy = vy * il, vhz = vz * il;
+                        const long long gt = L.goff + (long long)sy * L.gpy + (long long)sx * L.gpx;
+                        const float mx = ld(nrm, gt), my = ld(nrm, plane + gt), mz = ld(nrm, 2 * plane + gt);
+                        const float cr = fmaxf(0.0f, ((nx * vhx) + (ny * vhy)) + (nz * vhz));
+                        const float ce = fmaxf(0.0f, -(((mx * vhx) + (my * vhy)) + (mz * vhz)));
+                        const float w = (cr * ce) / dist2;
+                        acc0 = acc0 + ld(col, gt) * w;
+                        acc1 = acc1 + ld(col, plane + gt) * w;
+                        acc2 = acc2 + ld(col, 2 * plane + gt) * w;
+                    }
+                }
             }
         }
         const long long o = L.compact ? (long long)local : (long long)y * L.W + x;
@@ -94,34 +184,35 @@ __device__ __forceinline__ void ssgi_items(const SsgiArgs& a, KP K, const float*
     }
 }
 
-// per block: blur taps (AL) and the samples when S <= kLdsSamples; true when staged
-template <bool AL>
-__device__ __forceinline__ bool ssgi_stage(const SsgiArgs& a, float* ks, float* eg) {
+// per block: blur taps (AL) and, KLDS, the samples (S <= kLdsSamples)
+template <bool AL, bool KLDS>
+__device__ __forceinline__ void ssgi_stage(const SsgiArgs& a, float* ks, float* eg) {
     if (AL) stage_taps(a.c, eg);
-    const bool staged = a.S <= kLdsSamples;  // uniform
-    if (staged)
+    if (KLDS)
         for (int i = threadIdx.x; i < 3 * a.S; i += 256) ks[i] = a.kernel[i];
     __syncthreads();
-    return staged;
 }
 
-template <typename NT, typename CT, bool AL>
+// KLDS: the samples are staged in LDS (S <= kLdsSamples), else read from
+// global memory; one instance each keeps the sample loop inlined once
+template <typename NT, typename CT, bool AL, bool KLDS>
 __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
-    __shared__ float ks[3 * kLdsSamples];
+    __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
-    if (ssgi_stage<AL>(a, ks, eg))
+    ssgi_stage<AL, KLDS>(a, ks, eg);
+    if (KLDS)
         ssgi_items<NT, CT, AL>(a, (const float*)ks, (const float*)eg);
     else
         ssgi_items<NT, CT, AL>(a, a.kernel, (const float*)eg);
 }
 
 // frames of a batch (see k_ssao_batch)
-template <typename NT, typename CT, bool Q>
+template <typename NT, typename CT, bool Q, bool KLDS>
 __global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* T, int n, unsigned* queue) {
-    __shared__ float ks[3 * kLdsSamples];
+    __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
     __shared__ unsigned cbase[kMaxBatch + 1];
-    const bool staged = ssgi_stage<true>(T[0], ks, eg);
+    ssgi_stage<true, KLDS>(T[0], ks, eg);
     batch_chunk_bases(T, n, cbase);
     for_each_chunk<Q>(cbase[n], queue, [&](unsigned c) {
         int f = 0;
@@ -130,25 +221,33 @@ __global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* T, int n, un
         const ItemMap m = make_item_map(a.c);
         const unsigned item = (c - cbase[f]) * 256u + threadIdx.x;
         if (item >= item_total(m)) return;
-        if (staged)
+        if (KLDS)
             ssgi_item<NT, CT, true>(a, m, item, (const float*)ks, (const float*)eg);
         else
-            ssgi_item<NT, CT, true>(a, m, item, a.kernel, (const float*)eg);
+            ssgi_item<NT, CT, true>(a, m, item, T[0].kernel, (const float*)eg);
     });
 }
 
-hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int color_dtype, unsigned total_hint,
-                             const BatchSchedule& bs, hipStream_t s) {
-#define MR_GB(NT, CT, Q)                                                                                  \
-    hipLaunchKernelGGL((k_ssgi_batch<NT, CT, Q>),                                                         \
-                       dim3(eval_blocks_capped<k_ssgi_batch<NT, CT, Q>>(total_hint, bs.blocks_per_cu)), \
+hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int S, int normal_dtype, int color_dtype,
+                             unsigned total_hint, const BatchSchedule& bs, hipStream_t s) {
+    const bool lds = S <= kLdsSamples;
+#define MR_GB(NT, CT, Q, KL)                                                                                   \
+    hipLaunchKernelGGL((k_ssgi_batch<NT, CT, Q, KL>),                                                          \
+                       dim3(eval_blocks_capped<k_ssgi_batch<NT, CT, Q, KL>>(total_hint, bs.blocks_per_cu)), \
                        dim3(256), 0, s, T, n, bs.queue)
-#define MR_GBQ(NT, CT)            \
-    do {                          \
-        if (bs.queue_mode)        \
-            MR_GB(NT, CT, true);  \
-        else                      \
-            MR_GB(NT, CT, false); \
+#define MR_GBQ(NT, CT)                   \
+    do {                                 \
+        if (bs.queue_mode) {             \
+            if (lds)                     \
+                MR_GB(NT, CT, true, true);  \
+            else                         \
+                MR_GB(NT, CT, true, false); \
+        } else {                         \
+            if (lds)                     \
+                MR_GB(NT, CT, false, true); \
+            else                         \
+                MR_GB(NT, CT, false, false); \
+        }                                \
     } while (0)
     if (normal_dtype == MR_F16 && color_dtype == MR_F16)
         MR_GBQ(_Float16, _Float16);
@@ -165,15 +264,22 @@ hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int col
 
 hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, unsigned total_hint,
                        hipStream_t s) {
-    const bool al = fused_alpha(a.c);
-#define MR_SSGI(NT, CT)                                                                                   \
-    do {                                                                                                  \
-        if (al)                                                                                           \
-            hipLaunchKernelGGL((k_ssgi<NT, CT, true>), dim3(eval_blocks<k_ssgi<NT, CT, true>>(total_hint)), \
-                               dim3(256), 0, s, a);                                                       \
-        else                                                                                              \
-            hipLaunchKernelGGL((k_ssgi<NT, CT, false>),                                                   \
-                               dim3(eval_blocks<k_ssgi<NT, CT, false>>(total_hint)), dim3(256), 0, s, a); \
+    const bool al = fused_alpha(a.c), lds = a.S <= kLdsSamples;
+#define MR_SK(NT, CT, AL, KL) \
+    hipLaunchKernelGGL((k_ssgi<NT, CT, AL, KL>), dim3(eval_blocks<k_ssgi<NT, CT, AL, KL>>(total_hint)), dim3(256), 0, s, a)
+#define MR_SSGI(NT, CT)                \
+    do {                               \
+        if (al) {                      \
+            if (lds)                   \
+                MR_SK(NT, CT, true, true);  \
+            else                       \
+                MR_SK(NT, CT, true, false); \
+        } else {                       \
+            if (lds)                   \
+                MR_SK(NT, CT, false, true); \
+            else                       \
+                MR_SK(NT, CT, false, false); \
+        }                              \
     } while (0)
     if (normal_dtype == MR_F16 && color_dtype == MR_F16)
         MR_SSGI(_Float16, _Float16);
@@ -184,6 +290,7 @@ hipError_t launch_ssgi(const SsgiArgs& a, int normal_dtype, int color_dtype, uns
     else
         MR_SSGI(float, float);
 #undef MR_SSGI
+#undef MR_SK
     return hipGetLastError();
 }
 

@@ -363,8 +363,8 @@ struct BatchSchedule {
 };
 hipError_t launch_ssao_batch(const SsaoArgs* T, int n, int S, int normal_dtype, unsigned total_hint,
                              const BatchSchedule& bs, hipStream_t s);
-hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int normal_dtype, int color_dtype, unsigned total_hint,
-                             const BatchSchedule& bs, hipStream_t s);
+hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int S, int normal_dtype, int color_dtype,
+                             unsigned total_hint, const BatchSchedule& bs, hipStream_t s);
 hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
                                    unsigned total, int C, bool c16, bool m4, hipStream_t s);
 
