@@ -5,10 +5,10 @@
 // value is found from the stencil bits: its rank is the rank of its stencil
 // word's first texel plus the set bits before it, so values stay stored by
 // rank and the merge reads the blurred values exactly where it read the
-// unblurred ones.  Taps outside the level, outside the stencil or with
-// invalid depth are skipped (they would add w = 0); a tap whose range weight
-// is not positive adds +0 to both sums and is skipped as well, which leaves
-// the sums bit-identical to the full window order.
+// unblurred ones.  Taps outside the level, outside the stencil, with invalid
+// depth or with a range weight that is not positive add w = +0 (times a
+// finite value) to both sums, which leaves them bit-identical to sums over
+// the taking-part taps alone in window order.
 #include "eval_common.hpp"
 
 namespace mr {
@@ -51,29 +51,48 @@ __device__ __forceinline__ void bilateral_item(const BilateralArgs& a, const Bil
     float res = static_cast<float>(c[own]);
     if (valid_depth(zp)) {
         const float d = a.drel * zp;
+        // Branch-free window: every tap loads (a tap that does not take part
+        // reads the centre texel) and takes weight +0, which leaves both sums
+        // unchanged, so all loads of a row can be in flight together.  The
+        // window spans at most two stencil words per row (R < 32).
+        constexpr int N = 2 * R + 1;
+        const int wa = max(x - R, 0) >> 5, wz_ = min(x + R, L.W - 1) >> 5;
+        unsigned sb[N][2], so[N][2];
+        if (L.list) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int qy = min(max(y - R + k, 0), L.H - 1);
+                const unsigned r0 = (unsigned)qy * (unsigned)L.wpr;
+                sb[k][0] = L.Sb[r0 + (unsigned)wa];
+                sb[k][1] = L.Sb[r0 + (unsigned)wz_];
+                so[k][0] = L.woff[r0 + (unsigned)wa];
+                so[k][1] = L.woff[r0 + (unsigned)wz_];
+            }
+        }
         float num = 0.0f, den = 0.0f;
 #pragma unroll
         for (int dy = -R; dy <= R; ++dy) {
             const int qy = y + dy;
-            if (qy < 0 || qy >= L.H) continue;
+            const bool rok = qy >= 0 && qy < L.H;
 #pragma unroll
             for (int dx = -R; dx <= R; ++dx) {
                 const int qx = x + dx;
-                if (qx < 0 || qx >= L.W) continue;
-                const unsigned qt = (unsigned)qy * (unsigned)L.W + (unsigned)qx;
+                bool ok = rok && qx >= 0 && qx < L.W;
+                const unsigned qt = ok ? (unsigned)qy * (unsigned)L.W + (unsigned)qx : t;
                 unsigned qo = qt;
                 if (L.list) {
-                    const unsigned wi = (unsigned)qy * (unsigned)L.wpr + ((unsigned)qx >> 5);
-                    const unsigned bits = L.Sb[wi], b = (unsigned)qx & 31u;
-                    if (!((bits >> b) & 1u)) continue;
-                    qo = L.woff[wi] + (unsigned)__popc(bits & ((1u << b) - 1u));
+                    const int h = ((unsigned)qx >> 5) == (unsigned)wa ? 0 : 1;
+                    const unsigned bits = sb[dy + R][h], b = (unsigned)qx & 31u;
+                    ok = ok && ((bits >> b) & 1u);
+                    qo = so[dy + R][h] + (unsigned)__popc(bits & ((1u << b) - 1u));
                 }
-                const float zq = L.z[qt];
-                if (!valid_depth(zq)) continue;
+                qo = ok ? qo : own;
+                const float zq = L.z[ok ? qt : t];
+                const float v = static_cast<float>(c[qo]);
                 const float wz = 1.0f - fabsf(zq - zp) / d;
-                if (!(wz > 0.0f)) continue;
-                const float w = (a.wb[dy + R] * a.wb[dx + R]) * wz;
-                num = num + w * static_cast<float>(c[qo]);
+                ok = ok && valid_depth(zq) && wz > 0.0f;
+                const float w = ok ? (a.wb[dy + R] * a.wb[dx + R]) * wz : 0.0f;
+                num = num + w * v;
                 den = den + w;
             }
         }
