@@ -30,8 +30,8 @@ __device__ __forceinline__ int lean_level(const LeanArgs& A, unsigned b) {
 }
 
 // Words are ranked tile by tile (kLeanTileWords words x kLeanTileRows rows,
-// one 256-thread block per tile, row-major inside a tile, tiles row-major),
-// so that consecutive work-list entries lie close together on screen and the
+// one thread per word, row-major inside a tile, tiles row-major), so that
+// consecutive work-list entries lie close together on screen and the
 // evaluation's sample gathers of one wave touch a compact region.  The rank
 // of a texel is still woff[word] + popcount of the lower bits of its word.
 struct TileWord {
@@ -56,6 +56,10 @@ __device__ __forceinline__ TileWord tile_word(const LeanLevel& L, unsigned b, un
 // staged in LDS, dilated horizontally per row, then ORed over 2R + 1 rows.
 // Words outside the level are 0 (no edges), as the blur's zero padding.
 constexpr int kStageCols = kLeanTileWords + 2, kStageRows = kLeanTileRows + 2 * kBlurFusedMaxRadiusC;
+// One thread per word of a tile.  Larger tiles mean fewer list-base atomics
+// on each level's counter (1024 ranking blocks of level 1 at 4K with 256-word
+// tiles contended for one address).
+constexpr int kRankThreads = kLeanTileWords * kLeanTileRows;
 
 template <int R>
 __device__ __forceinline__ unsigned stencil_tile(const LeanLevel& L, unsigned b, unsigned (*eb)[kStageCols],
@@ -64,14 +68,14 @@ __device__ __forceinline__ unsigned stencil_tile(const LeanLevel& L, unsigned b,
     const unsigned ty = bl / (unsigned)L.tiles_x, tx = bl - ty * (unsigned)L.tiles_x;
     const int yw0 = (int)(ty * kLeanTileRows) - R, xw0 = (int)(tx * kLeanTileWords) - 1;
     constexpr int rows = kLeanTileRows + 2 * R, n = rows * kStageCols;
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += kRankThreads) {
         const int r = i / kStageCols, c = i - r * kStageCols;
         const int y = yw0 + r, xw = xw0 + c;
         eb[r][c] = (y >= 0 && y < L.H && xw >= 0 && xw < L.wpr) ? L.Eb[(unsigned)y * (unsigned)L.wpr + (unsigned)xw]
                                                                 : 0u;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < rows * kLeanTileWords; i += 256) {
+    for (int i = threadIdx.x; i < rows * kLeanTileWords; i += kRankThreads) {
         const int r = i / kLeanTileWords, c = i - r * kLeanTileWords;
         hd[r][c] = hdilate(eb[r][c], eb[r][c + 1], eb[r][c + 2], R);
     }
@@ -100,7 +104,7 @@ __device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
 // which is all the merge needs, and each texel's result does not depend on
 // where in the list it sits.  The counts are zeroed by the edge kernel.
 __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
-    __shared__ unsigned wtot[4];
+    __shared__ unsigned wtot[kRankThreads / 64];
     __shared__ unsigned tile_base;
     const int l = lean_level(A, b);
     const LeanLevel& L = A.lv[l];
@@ -123,7 +127,9 @@ __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
     if (__lane_id() == 63) wtot[wv] = inc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        unsigned total = 0;
+#pragma unroll
+        for (int k = 0; k < kRankThreads / 64; ++k) total += wtot[k];
         tile_base = total ? atomicAdd(A.count + L.count_idx, total) : 0u;
     }
     __syncthreads();
@@ -141,23 +147,23 @@ __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_lean_rank(LeanArgs A) { rank_block(A, blockIdx.x); }
+__global__ __launch_bounds__(kRankThreads) void k_lean_rank(LeanArgs A) { rank_block(A, blockIdx.x); }
 
 // frames of a batch: blk_base[f] = first block of frame f, blk_base[n] = total
-__global__ __launch_bounds__(256) void k_lean_rank_batch(const LeanArgs* T, const unsigned* blk_base, int n) {
+__global__ __launch_bounds__(kRankThreads) void k_lean_rank_batch(const LeanArgs* T, const unsigned* blk_base, int n) {
     int f = 0;
     for (int k = 1; k < n; ++k) f += blockIdx.x >= blk_base[k] ? 1 : 0;
     rank_block(T[f], blockIdx.x - blk_base[f]);
 }
 
 hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s) {
-    if (a.nblk) hipLaunchKernelGGL(k_lean_rank, dim3(a.nblk), dim3(256), 0, s, a);
+    if (a.nblk) hipLaunchKernelGGL(k_lean_rank, dim3(a.nblk), dim3(kRankThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_lean_masks_batch(const LeanArgs* T, const unsigned* blk_base, int n, unsigned total,
                                    hipStream_t s) {
-    if (total) hipLaunchKernelGGL(k_lean_rank_batch, dim3(total), dim3(256), 0, s, T, blk_base, n);
+    if (total) hipLaunchKernelGGL(k_lean_rank_batch, dim3(total), dim3(kRankThreads), 0, s, T, blk_base, n);
     return hipGetLastError();
 }
 

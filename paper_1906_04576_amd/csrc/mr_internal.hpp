@@ -214,7 +214,7 @@ constexpr int kMergeLDS = 640;  // >= sum of rw * rh over levels 2..6 (518)
 // ---------------------------------------------------------------------------
 // lean frame path (bit-packed stencils, values stored by rank)
 // ---------------------------------------------------------------------------
-constexpr int kLeanTileWords = 16, kLeanTileRows = 16;  // 256 words per ranking tile
+constexpr int kLeanTileWords = 16, kLeanTileRows = 32;  // 512 words per ranking tile (measured)
 
 struct LeanLevel {
     const uint32_t* Eb;  // edge bits
