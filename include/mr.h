@@ -15,7 +15,13 @@
  *                      pass of Sec. 5.
  *   mr_upsample_merge  Sec. 3.3 / 4.2, Eq. 1: bilinear upsampling and the
  *                      sequential blend from the coarsest level.
- *   mr_frame           the whole pipeline for one effect.
+ *   mr_frame           the whole pipeline for one effect (optionally with
+ *                      FP16 sub-image storage, the bilateral blur of SSAO
+ *                      sub-images of Sec. 4.1 and the foveated mask of
+ *                      Sec. 6).
+ *   mr_eval_ssao_fullres  Sec. 6: sub-images at full resolution with fewer
+ *                      samples instead of a lower resolution.
+ *   mr_batch_*         frames of uneven sizes with one launch per stage.
  *
  * Conventions (all functions):
  *  - Every array argument is DEVICE memory owned by the caller, unless the
@@ -27,8 +33,9 @@
  *    W_i = W / s_i, H_i = H / s_i; W and H must be divisible by 2^(N-1).
  *  - `stream` is a hipStream_t (NULL = the null stream).  Every call only
  *    enqueues work on it and returns; there is no host synchronisation and
- *    work-list counts stay on the device.  Device faults surface at the
- *    caller's next synchronisation.
+ *    work-list counts stay on the device (except mr_batch_setup and
+ *    mr_batch_tune, which wait for the stream).  Device faults surface at
+ *    the caller's next synchronisation.
  *  - Every call validates all arguments before it enqueues anything; on
  *    error it returns a negative MR_E_* code, enqueues nothing, leaves the
  *    outputs untouched and sets a thread-local message (mr_last_error).
