@@ -498,27 +498,45 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
             v0[c][j] = lc[c][r0 + col[j]];
             v1[c][j] = lc[c][r1 + col[j]];
         }
+    // C_i = num / den, with the division only where a tap lies off the
+    // stencil (den < 1); a wave whose pixels all have den = 1 skips it
+    float Ci[C][4], alpha[4], den[4];
+    bool part[4], need = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int ja = XT::cofs(k), jb = ja + 1;
         const float fx = XT::fx(k, XQ), gx = 1.0f - fx;
         const float b0 = gx * gy, b1 = fx * gy, b2 = gx * fy, b3 = fx * fy;
-        float den = a0[ja] > 0.0f ? b0 : 0.0f;
-        den = den + (a0[jb] > 0.0f ? b1 : 0.0f);
-        den = den + (a1[ja] > 0.0f ? b2 : 0.0f);
-        den = den + (a1[jb] > 0.0f ? b3 : 0.0f);
-        const bool use = A[k] != 0.0f && den > 0.0f;
-        const float alpha = use ? fminf(A[k] * L.w, 1.0f) : 0.0f;
-        const float om = 1.0f - alpha;
+        float d = a0[ja] > 0.0f ? b0 : 0.0f;
+        d = d + (a0[jb] > 0.0f ? b1 : 0.0f);
+        d = d + (a1[ja] > 0.0f ? b2 : 0.0f);
+        d = d + (a1[jb] > 0.0f ? b3 : 0.0f);
+        const bool use = A[k] != 0.0f && d > 0.0f;
+        alpha[k] = use ? fminf(A[k] * L.w, 1.0f) : 0.0f;
+        den[k] = d;
+        part[k] = use && d != 1.0f;
+        need = need || part[k];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             float num = b0 * v0[c][ja];
             num = num + b1 * v0[c][jb];
             num = num + b2 * v1[c][ja];
             num = num + b3 * v1[c][jb];
-            const float Ci = use ? (den == 1.0f ? num : num / den) : 0.0f;
-            out[c][k] = Ci * alpha + out[c][k] * om;
+            Ci[c][k] = use ? num : 0.0f;
         }
+    }
+    if (__ballot(need)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (part[k]) Ci[c][k] = Ci[c][k] / den[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float om = 1.0f - alpha[k];
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c][k] = Ci[c][k] * alpha[k] + out[c][k] * om;
     }
 }
 

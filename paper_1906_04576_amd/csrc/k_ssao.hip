@@ -8,8 +8,8 @@
 namespace mr {
 
 // Occluding samples of one texel.  Branch-free: every sample computes its
-// projection and gathers (texel 0 when it is off-screen or behind the eye),
-// and counts only if all tests pass; the count is the same as skipping the
+// projection and gathers (a texel of the depth plane also when it is
+// off-screen or behind the eye), and counts only if all tests pass; the count is the same as skipping the
 // sample.  Samples go in groups of G whose gathers are issued back
 // to back, so that several are in flight per wave.  FAST: 1/d by
 // recip_fast, which the caller has shown to equal 1.0f / d for every sample
@@ -24,9 +24,16 @@ struct SsaoTexel {
 // compute a_i
 constexpr int kGroupPlain = 8, kGroupMulti = 2;
 
-template <bool FAST, typename KP>
+// off: offset of the sample's texel in the depth plane, in bytes when CLAMP,
+// else in elements (element pitches zpy, zpx; last = byte offset of the
+// plane's last texel).  Two exact forms:
+// CLAMP tests 0 <= u < W and 0 <= v < H as unsigned compares of the bit
+// patterns and clamps the offset to last, four instructions fewer per sample
+// than selecting texel 0 off screen; with groups of 8 samples in flight the
+// second form keeps register use at full occupancy (measured).
+template <bool FAST, bool CLAMP, typename KP>
 __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, const SsaoTexel& T, unsigned zpy,
-                                             unsigned zpx, bool& on, float& d, unsigned& off) {
+                                             unsigned zpx, unsigned last, bool& on, float& d, unsigned& off) {
     const float Wf = (float)L.W, Hf = (float)L.H;
     const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
     const float qz = ((T.pz + kx * T.rtz) + ky * T.rbz) + kz * T.rnz;
@@ -36,11 +43,23 @@ __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, co
     const float inv = FAST ? recip_fast(d) : 1.0f / d;
     const float u = L.cx + (qx * inv) * L.f;
     const float v = L.cy - (qy * inv) * L.f;
-    on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
-    // u, v >= 0 when on, so truncation is floor; rows < 2^14 and pitches
-    // < 2^20 keep the offset products within 24 bits
-    const unsigned sx = (unsigned)(int)(on ? u : 0.0f), sy = (unsigned)(int)(on ? v : 0.0f);
-    off = __umul24(sy, zpy) + __umul24(sx, zpx);  // element offset
+    if (CLAMP) {
+        // exact for every u other than -0: u = cx + t and v = cy - t' are
+        // never -0 because cx, cy > 0 (a sum is -0 only when both terms are)
+        on = (d > 0.0f) & (__float_as_uint(u) < __float_as_uint(Wf)) & (__float_as_uint(v) < __float_as_uint(Hf));
+        // u, v >= 0 when on, so truncation is floor.  Coordinates < 2^14 and
+        // byte pitches < 2^22 fit the 24-bit products; on screen the offset
+        // is at most last, so the clamp leaves it unchanged, and off screen
+        // it keeps the gather inside the plane (its value is not used).
+        const unsigned sx = (unsigned)cvt_i32_sat(u), sy = (unsigned)cvt_i32_sat(v);
+        off = __builtin_elementwise_min((unsigned)__umul24(sy, 4u * zpy) + (unsigned)__umul24(sx, 4u * zpx), last);
+    } else {
+        on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
+        // u, v >= 0 when on, so truncation is floor; rows < 2^14 and pitches
+        // < 2^20 keep the offset products within 24 bits
+        const unsigned sx = (unsigned)(int)(on ? u : 0.0f), sy = (unsigned)(int)(on ? v : 0.0f);
+        off = __umul24(sy, zpy) + __umul24(sx, zpx);
+    }
 }
 
 // Gathers of a group of G samples are issued together, one projection at a
@@ -49,12 +68,13 @@ __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, co
 // are in flight.
 template <bool FAST, int G, typename SA, typename KP>
 __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K, const SsaoTexel& T) {
+    constexpr bool CLAMP = G <= 2;
     const float r = a.r, b = a.b;
     const int S = a.S;
     // L is wave-uniform here: the depth plane is a buffer resource
     const unsigned zpy = (unsigned)L.zpy, zpx = (unsigned)L.zpx;
-    const __amdgpu_buffer_rsrc_t rz =
-        buf_rsrc(L.z, ((unsigned)(L.H - 1) * zpy + (unsigned)(L.W - 1) * zpx + 1u) * 4u);
+    const unsigned last = ((unsigned)(L.H - 1) * zpy + (unsigned)(L.W - 1) * zpx) * 4u;
+    const __amdgpu_buffer_rsrc_t rz = buf_rsrc(L.z, last + 4u);
     // z_s <= 0 must not count; +inf and NaN fail the depth test
     auto occluded = [&](bool on, float d, float zs) {
         return (on & (zs > 0.0f) & (zs < d - (b * d)) & (fabsf(T.z - zs) < r)) ? 1 : 0;
@@ -67,13 +87,13 @@ __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K,
         unsigned off[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            ssao_project<FAST>(L, K, s + k, T, zpy, zpx, on[k], d[k], off[k]);
+            ssao_project<FAST, CLAMP>(L, K, s + k, T, zpy, zpx, last, on[k], d[k], off[k]);
             // one projection at a time: interleaving them buys little ILP
             // and costs registers (occupancy)
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int k = 0; k < G; ++k) zs[k] = buf_f1(rz, off[k] * 4u);
+        for (int k = 0; k < G; ++k) zs[k] = buf_f1(rz, CLAMP ? off[k] : off[k] * 4u);
 #pragma unroll
         for (int k = 0; k < G; ++k) occ += occluded(on[k], d[k], zs[k]);
     }
@@ -81,8 +101,8 @@ __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K,
         bool on;
         float d;
         unsigned off;
-        ssao_project<FAST>(L, K, s, T, zpy, zpx, on, d, off);
-        occ += occluded(on, d, buf_f1(rz, off * 4u));
+        ssao_project<FAST, CLAMP>(L, K, s, T, zpy, zpx, last, on, d, off);
+        occ += occluded(on, d, buf_f1(rz, CLAMP ? off : off * 4u));
     }
     return occ;
 }

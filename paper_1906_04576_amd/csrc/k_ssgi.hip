@@ -59,8 +59,12 @@ __device__ __forceinline__ void ssgi_item(const SsgiArgs& a, const ItemMap& m, u
                     const float inv = recip_pos(d);  // = 1.0f / d (d > 0)
                     const float u = L.cx + (qx * inv) * L.f;
                     const float v = L.cy - (qy * inv) * L.f;
-                    if (!(u >= 0.0f && u < Wf && v >= 0.0f && v < Hf)) continue;
-                    const int sx = (int)floorf(u), sy = (int)floorf(v);
+                    // 0 <= u < W and 0 <= v < H as unsigned compares of the
+                    // bit patterns: exact, as u = cx + t and v = cy - t' are
+                    // never -0 (cx, cy > 0)
+                    if (!((__float_as_uint(u) < __float_as_uint(Wf)) & (__float_as_uint(v) < __float_as_uint(Hf))))
+                        continue;
+                    const int sx = (int)u, sy = (int)v;  // u, v >= 0: truncation is floor
                     const float zs = L.z[(unsigned)sy * L.zpy + (unsigned)sx * L.zpx];
                     if (!valid_depth(zs)) continue;
                     if (!(zs < d - (b * d) && fabsf(z - zs) < r)) continue;

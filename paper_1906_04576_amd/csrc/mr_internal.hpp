@@ -22,6 +22,15 @@ __device__ __forceinline__ bool valid_depth(float z) {
     return z > 0.0f && z < __builtin_inff();
 }
 
+// float -> int32 with the conversion instruction's own result for every
+// input (truncation; NaN gives 0, values out of range saturate), where a
+// C++ conversion of such a value is undefined
+__device__ __forceinline__ int cvt_i32_sat(float x) {
+    int r;
+    asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 template <typename T>
 __device__ __forceinline__ float ld(const T* p, long long i) {
     return static_cast<float>(p[i]);
