@@ -540,6 +540,36 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
     }
 }
 
+// one staged texel: index k of the (kMergeTW >> SH) + 2 columns wide region
+// of level LV (scale 2^SH) around the tile at (x0, y0), clamped to the level;
+// LV = 3 is dense, the others are read by rank (a = 0 and values 0 off the
+// stencil)
+template <int LV, int SH, int RW, int C, typename VT>
+__device__ __forceinline__ void stage4(const LeanMergeArgs& a, int k, int x0, int y0, float& av, float (&cv)[C]) {
+    const LeanMergeLevel& L = a.lv[LV];
+    const int yy = k / RW, xx = k - yy * RW;
+    const int Xl = min(max((x0 >> SH) - 1 + xx, 0), L.W - 1);
+    const int Yl = min(max((y0 >> SH) - 1 + yy, 0), L.H - 1);
+    av = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) cv[c] = 0.0f;
+    if (LV == 3) {
+        const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
+#pragma unroll
+        for (int c = 0; c < C; ++c) cv[c] = cval<VT>(L.c, c * L.c_plane + p);
+    } else {
+        const unsigned wi = (unsigned)Yl * (unsigned)L.wpr + (unsigned)(Xl >> 5);
+        const unsigned word = L.Sb[wi];
+        const unsigned bit = (unsigned)Xl & 31u;
+        if ((word >> bit) & 1u) {
+            const unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
+            av = L.ac[rank];
+#pragma unroll
+            for (int c = 0; c < C; ++c) cv[c] = cval<VT>(L.c, c * L.c_plane + rank);
+        }
+    }
+}
+
 template <int C, typename VT>
 __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned tile, unsigned tiles_x) {
     using R2 = Region4<1>;
@@ -554,43 +584,23 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
     if (t == 0) any2 = any3 = 0;
     __syncthreads();
     // ---- stage levels 2, 3 (by rank, 0 off the stencil) and 4 (dense) ----
-    constexpr int kSlots = (R2::n + R3::n + R4::n + 255) / 256;
-    float av[kSlots], cv[kSlots][C];
+    // Every thread stages texel t of level 2 and at most one more: level 2's
+    // remaining texels on threads [0, nB), level 4 on [nB, nB + n4), level 3
+    // on [128, 128 + n3).  Each slot's level is fixed at compile time, so its
+    // parameters are scalar and its divisions by the region width constant.
+    constexpr int nB = R2::n - 256;
+    static_assert(nB > 0 && nB + R4::n <= 128 && 128 + R3::n <= 256, "merge staging layout");
+    float av[2], cv[2][C];
+    stage4<1, 1, R2::rw, C, VT>(a, t, x0, y0, av[0], cv[0]);
+    av[1] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j) {
-        const int idx = t + 256 * j;
-        av[j] = 0.0f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) cv[j][c] = 0.0f;
-        if (idx >= R2::n + R3::n + R4::n) continue;
-        int lv, k, rw, sh;
-        if (idx < R2::n) {
-            lv = 1, k = idx, rw = R2::rw, sh = 1;
-        } else if (idx < R2::n + R3::n) {
-            lv = 2, k = idx - R2::n, rw = R3::rw, sh = 2;
-        } else {
-            lv = 3, k = idx - R2::n - R3::n, rw = R4::rw, sh = 3;
-        }
-        const LeanMergeLevel& L = a.lv[lv];
-        const int yy = k / rw, xx = k - yy * rw;
-        const int Xl = min(max((x0 >> sh) - 1 + xx, 0), L.W - 1);
-        const int Yl = min(max((y0 >> sh) - 1 + yy, 0), L.H - 1);
-        if (lv == 3) {
-            const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
-#pragma unroll
-            for (int c = 0; c < C; ++c) cv[j][c] = cval<VT>(L.c, c * L.c_plane + p);
-        } else {
-            const unsigned wi = (unsigned)Yl * (unsigned)L.wpr + (unsigned)(Xl >> 5);
-            const unsigned word = L.Sb[wi];
-            const unsigned bit = (unsigned)Xl & 31u;
-            if ((word >> bit) & 1u) {
-                const unsigned rank = L.woff[wi] + __popc(word & ((1u << bit) - 1u));
-                av[j] = L.ac[rank];
-#pragma unroll
-                for (int c = 0; c < C; ++c) cv[j][c] = cval<VT>(L.c, c * L.c_plane + rank);
-            }
-        }
-    }
+    for (int c = 0; c < C; ++c) cv[1][c] = 0.0f;
+    if (t < nB)
+        stage4<1, 1, R2::rw, C, VT>(a, 256 + t, x0, y0, av[1], cv[1]);
+    else if (t < nB + R4::n)
+        stage4<3, 3, R4::rw, C, VT>(a, t - nB, x0, y0, av[1], cv[1]);
+    else if (t >= 128 && t < 128 + R3::n)
+        stage4<2, 2, R3::rw, C, VT>(a, t - 128, x0, y0, av[1], cv[1]);
     const int q = t & 15, row = t >> 4;
     const int Y = y0 + row;
     const int XQ = x0 + 4 * q;
@@ -619,25 +629,26 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
             }
         }
     }
+    la2[t] = av[0];
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j) {
-        const int idx = t + 256 * j;
-        if (idx >= R2::n + R3::n + R4::n) continue;
-        if (idx < R2::n) {
-            la2[idx] = av[j];
+    for (int c = 0; c < C; ++c) lc2[c][t] = cv[0][c];
+    bool nz2 = av[0] != 0.0f, nz3 = false;
+    if (t < nB) {
+        la2[256 + t] = av[1];
 #pragma unroll
-            for (int c = 0; c < C; ++c) lc2[c][idx] = cv[j][c];
-            if (av[j] != 0.0f) any2 = 1;
-        } else if (idx < R2::n + R3::n) {
-            la3[idx - R2::n] = av[j];
+        for (int c = 0; c < C; ++c) lc2[c][256 + t] = cv[1][c];
+        nz2 = nz2 || av[1] != 0.0f;
+    } else if (t < nB + R4::n) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) lc3[c][idx - R2::n] = cv[j][c];
-            if (av[j] != 0.0f) any3 = 1;
-        } else {
+        for (int c = 0; c < C; ++c) lc4[c][t - nB] = cv[1][c];
+    } else if (t >= 128 && t < 128 + R3::n) {
+        la3[t - 128] = av[1];
 #pragma unroll
-            for (int c = 0; c < C; ++c) lc4[c][idx - R2::n - R3::n] = cv[j][c];
-        }
+        for (int c = 0; c < C; ++c) lc3[c][t - 128] = cv[1][c];
+        nz3 = av[1] != 0.0f;
     }
+    if (nz2) any2 = 1;
+    if (nz3) any3 = 1;
     __syncthreads();
     if (!active) return;
 
