@@ -103,9 +103,22 @@ __device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
 // the order they finish; the rank of every texel is stored with it (woff),
 // which is all the merge needs, and each texel's result does not depend on
 // where in the list it sits.  The counts are zeroed by the edge kernel.
+// A tile of at most kRankStage entries builds its run of the list in LDS
+// and stores it with consecutive threads at consecutive positions; the
+// entries of a word are kRankStage / 512 = 16 or more dwords apart, so
+// storing them straight from each thread would touch a separate cache line
+// per thread and entry.  LDS positions are padded by one word per 32, which
+// puts the threads' entries in distinct banks.  (Measured at 4K: ranking
+// 13.3 us with direct stores, 11.5 us staging up to 4096 entries, 10.4 us
+// up to 8192; the 40 KB of LDS still leaves every block of a 4K frame
+// resident.)
+constexpr unsigned kRankStage = 8192;
+__device__ __forceinline__ unsigned stage_slot(unsigned p) { return p + (p >> 5); }
+
 __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
     __shared__ unsigned wtot[kRankThreads / 64];
-    __shared__ unsigned tile_base;
+    __shared__ unsigned tile_base, tile_total;
+    __shared__ unsigned stg[kRankStage + kRankStage / 32];
     const int l = lean_level(A, b);
     const LeanLevel& L = A.lv[l];
     __shared__ unsigned eb[kStageRows][kStageCols];
@@ -130,21 +143,36 @@ __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
         unsigned total = 0;
 #pragma unroll
         for (int k = 0; k < kRankThreads / 64; ++k) total += wtot[k];
+        tile_total = total;
         tile_base = total ? atomicAdd(A.count + L.count_idx, total) : 0u;
     }
     __syncthreads();
-    if (!tw.ok) return;
-    unsigned pos = tile_base + inc - cnt;
-    for (int k = 0; k < wv; ++k) pos += wtot[k];
-    L.Sb[tw.w] = acc;
-    L.woff[tw.w] = pos;
+    const unsigned total = tile_total, tb = tile_base;
+    unsigned ex = inc - cnt;  // entries of the tile before this word
+    for (int k = 0; k < wv; ++k) ex += wtot[k];
+    if (tw.ok) {
+        L.Sb[tw.w] = acc;
+        L.woff[tw.w] = tb + ex;
+    }
     const unsigned base = (unsigned)tw.y * (unsigned)L.W + (unsigned)tw.xw * 32u;
-    unsigned m = acc;
+    unsigned m = acc;  // 0 outside the level
+    if (total > kRankStage) {  // uniform
+        unsigned pos = tb + ex;
+        while (m) {
+            const int bit = __builtin_ctz(m);
+            m &= m - 1;
+            L.list[pos++] = base + (unsigned)bit;
+        }
+        return;
+    }
+    unsigned q = ex;
     while (m) {
         const int bit = __builtin_ctz(m);
         m &= m - 1;
-        L.list[pos++] = base + (unsigned)bit;
+        stg[stage_slot(q++)] = base + (unsigned)bit;
     }
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < total; j += kRankThreads) L.list[tb + j] = stg[stage_slot(j)];
 }
 
 __global__ __launch_bounds__(kRankThreads) void k_lean_rank(LeanArgs A) { rank_block(A, blockIdx.x); }
