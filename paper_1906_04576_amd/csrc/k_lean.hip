@@ -68,11 +68,22 @@ __device__ __forceinline__ unsigned stencil_tile(const LeanLevel& L, unsigned b,
     const unsigned ty = bl / (unsigned)L.tiles_x, tx = bl - ty * (unsigned)L.tiles_x;
     const int yw0 = (int)(ty * kLeanTileRows) - R, xw0 = (int)(tx * kLeanTileWords) - 1;
     constexpr int rows = kLeanTileRows + 2 * R, n = rows * kStageCols;
-    for (int i = threadIdx.x; i < n; i += kRankThreads) {
+    // all of a thread's loads are issued before the first LDS store
+    constexpr int NI = (n + kRankThreads - 1) / kRankThreads;
+    unsigned v[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + k * kRankThreads;
         const int r = i / kStageCols, c = i - r * kStageCols;
         const int y = yw0 + r, xw = xw0 + c;
-        eb[r][c] = (y >= 0 && y < L.H && xw >= 0 && xw < L.wpr) ? L.Eb[(unsigned)y * (unsigned)L.wpr + (unsigned)xw]
-                                                                : 0u;
+        v[k] = (i < n && y >= 0 && y < L.H && xw >= 0 && xw < L.wpr) ? L.Eb[(unsigned)y * (unsigned)L.wpr + (unsigned)xw]
+                                                                     : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + k * kRankThreads;
+        const int r = i / kStageCols, c = i - r * kStageCols;
+        if (i < n) eb[r][c] = v[k];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < rows * kLeanTileWords; i += kRankThreads) {
