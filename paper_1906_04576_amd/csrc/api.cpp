@@ -521,6 +521,7 @@ unsigned make_eval_common(const mr_gbuffer* gb, const Geo& g, const mr_masks* m,
         L.gpx = sc;
         L.out = out[i - 1];
         L.out_plane = (long long)L.W * L.H;
+        L.stream = m ? 0 : 1;  // without masks the output is the full-resolution image
         const bool dense = !m || i == g.L;
         L.list = dense ? nullptr : m->worklist[i - 1];
         L.count_idx = i - 1;

@@ -201,6 +201,8 @@ __device__ __forceinline__ float alpha_dispatch(const EvalLevel& L, const float*
 __device__ __forceinline__ void store_out(const EvalLevel& L, unsigned idx, float v) {
     if (L.out16)
         reinterpret_cast<_Float16*>(L.out)[idx] = (_Float16)v;
+    else if (L.stream)  // a final image: nothing in the frame reads it again
+        __builtin_nontemporal_store(v, L.out + idx);
     else
         L.out[idx] = v;
 }

@@ -442,7 +442,7 @@ __device__ __forceinline__ void merge_tile(const LeanMergeArgs& a, unsigned tile
     const unsigned plane = (unsigned)a.W * (unsigned)a.H;
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
+        store_stream4(a.out + c * plane + p, out[c][0], out[c][1], out[c][2], out[c][3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -734,7 +734,7 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
     const unsigned plane = (unsigned)a.W * (unsigned)a.H;
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        *reinterpret_cast<float4*>(a.out + c * plane + p) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
+        store_stream4(a.out + c * plane + p, out[c][0], out[c][1], out[c][2], out[c][3]);
 }
 
 template <int C, typename VT>
