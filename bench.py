@@ -36,7 +36,7 @@ SSAO_OPS_PER_TEXEL = 40         # per evaluated texel outside the sample loop
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (profiles/), scaled by the copy-kernel calibration;
 # None until measured for the current kernel
-TRAFFIC_BYTES = {"k_ssao_multi": 77825573}
+TRAFFIC_BYTES = {"k_ssao_multi": 77367778}
 
 
 def log(*a):
