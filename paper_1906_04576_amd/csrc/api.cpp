@@ -886,7 +886,9 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
             L.rh = (kMergeTH + L.s - 1) / L.s + 2;
             L.roff = ma.staged;
             L.rmagic = (65536u + (unsigned)L.rw - 1) / (unsigned)L.rw;
-            ma.staged += L.rw * L.rh;
+            // each level's region starts on a whole wave of staging slots,
+            // so that a wave stages one level (its parameters are scalar)
+            ma.staged += (L.rw * L.rh + 63) & ~63;
         }
     }
 }

@@ -272,8 +272,11 @@ __device__ __forceinline__ void merge_tile(const LeanMergeArgs& a, unsigned tile
         int q = 0;
 #pragma unroll
         for (int k = 1; k < kMaxLevels; ++k) q += (k < nl && idx >= a.lv[k].roff) ? 1 : 0;
+        // the levels' regions start at multiples of 64 slots: one level per wave
+        q = __builtin_amdgcn_readfirstlane(q);
         const LeanMergeLevel& L = a.lv[q];
         const int k = idx - L.roff;
+        if (k >= L.rw * L.rh) continue;  // padding of the level's region
         const int yy = (int)(((unsigned)k * L.rmagic) >> 16), xx = k - yy * L.rw;
         const int Xl = min(max((x0 >> L.sh) - 1 + xx, 0), L.W - 1);
         const int Yl = min(max((y0 >> L.sh) - 1 + yy, 0), L.H - 1);

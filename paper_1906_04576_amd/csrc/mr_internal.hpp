@@ -229,7 +229,9 @@ struct MergeArgs {
 };
 
 constexpr int kMergeTW = 64, kMergeTH = 16;
-constexpr int kMergeLDS = 640;  // >= sum of rw * rh over levels 2..6 (518)
+// >= sum of rw * rh over levels 2..6 (518), and of those sums rounded up to
+// whole waves as the compact path lays them out (384 + 128 + 3 x 64 = 704)
+constexpr int kMergeLDS = 768;
 
 // ---------------------------------------------------------------------------
 // lean frame path (bit-packed stencils, values stored by rank)
