@@ -9,11 +9,11 @@ namespace mr {
 
 // Occluding samples of one texel.  Branch-free: every sample computes its
 // projection and gathers (a texel of the depth plane also when it is
-// off-screen or behind the eye), and counts only if all tests pass; the count is the same as skipping the
-// sample.  Samples go in groups of G whose gathers are issued back
-// to back, so that several are in flight per wave.  FAST: 1/d by
-// recip_fast, which the caller has shown to equal 1.0f / d for every sample
-// of the texel.
+// off-screen or behind the eye), and counts only if all tests pass; the
+// count is the same as skipping the sample.  Samples go in groups of G
+// whose gathers are issued back to back, so that several are in flight per
+// wave.  FAST: 1/d by recip_fast, which the caller has shown to equal
+// 1.0f / d for every sample of the texel.
 struct SsaoTexel {
     float px, py, pz, z;
     float rtx, rty, rtz, rbx, rby, rbz, rnx, rny, rnz;
