@@ -338,6 +338,36 @@ MR_API int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, cons
  * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */
 MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream);
 
+/* Where the compact frame path keeps its masks in the workspace, as byte
+ * offsets from ws (host; for callers and tests that read them after a
+ * frame has completed).  compact = 1 when mr_frame takes the compact path
+ * for these parameters (coarsest level <= 4, width divisible by 128, blur
+ * radii <= 8); the other fields are then set, else they are 0.  Index [i-1]
+ * is level i, for every enabled level i below the coarsest:
+ *   worklist      u32 [count[i-1]] the texels y*W_i + x with S_i = 1 (Sec.
+ *                 4.1), in ranking-tile order: tiles of tile_words x
+ *                 tile_rows stencil words (32 texels each) row-major over
+ *                 the level, words row-major inside a tile, texels left to
+ *                 right inside a word.  The order is fixed (the same on
+ *                 every run); sorting it gives the row-major list of
+ *                 mr_build_masks.
+ *   stencil_bits  u32 [H_i][W_i / 32] S_i, bit x % 32 of word x / 32
+ *   rank          u32 [H_i][W_i / 32] list position of each word's first
+ *                 stencil texel
+ *   count         u32 [MR_MAX_LEVELS] list lengths
+ * Returns MR_OK, or a negative code for invalid arguments. */
+typedef struct {
+    int compact;
+    int tile_words, tile_rows;
+    size_t count;
+    size_t worklist[MR_MAX_LEVELS];
+    size_t stencil_bits[MR_MAX_LEVELS];
+    size_t rank[MR_MAX_LEVELS];
+} mr_frame_layout;
+
+MR_API int mr_frame_workspace_layout(const mr_camera* cam, const mr_mask_params* mp, int effect,
+                                     mr_frame_layout* out);
+
 /* Batches: up to MR_MAX_BATCH frames of one effect (MR_EFFECT_SSAO or
  * MR_EFFECT_SSGI) with identical mask and effect parameters and input types
  * but any sizes, processed with one launch per stage for all frames (edges,
@@ -397,6 +427,7 @@ MR_API int mr_batch_set_config(void* plan, const mr_batch_config* cfg);
  * stream: not for use under graph capture.  Outputs after it are those of a
  * plain run. */
 MR_API int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream);
+
 
 /* Host helpers. */
 MR_API const char* mr_status_string(int status);

@@ -296,6 +296,11 @@ FrameLayout frame_layout(const Geo& g, int effect) {
 // Gaussian taps are all positive with no product of two taps underflowing
 // (then a_i > 0 exactly on the Chebyshev dilation of the pooled edges), and
 // radii for which the nesting step changes nothing (r_j >= ceil(r_i / k)).
+// ranking tiles of a level with wpr words per row and H rows
+unsigned lean_tiles(int wpr, int H) {
+    return (unsigned)((wpr + kLeanTileWords - 1) / kLeanTileWords) * (unsigned)((H + kLeanTileRows - 1) / kLeanTileRows);
+}
+
 bool lean_ok(const Geo& g, const mr_mask_params* mp) {
     if (g.L > 4 || g.nlev < 2 || g.W % 128 != 0) return false;
     int radius[kMaxLevels] = {};
@@ -319,13 +324,9 @@ bool lean_ok(const Geo& g, const mr_mask_params* mp) {
     return true;
 }
 
-// ranking tiles of a level with wpr words per row and H rows
-unsigned lean_tiles(int wpr, int H) {
-    return (unsigned)((wpr + kLeanTileWords - 1) / kLeanTileWords) * (unsigned)((H + kLeanTileRows - 1) / kLeanTileRows);
-}
 
 struct LeanLayout {
-    size_t count = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, ac[3] = {}, cc[3] = {};
+    size_t count = 0, tot = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, ac[3] = {}, cc[3] = {};
     size_t zi[kMaxLevels] = {}, cL = 0, hard = 0;
     size_t bc[3] = {}, bL = 0;  // SSAO: bilaterally blurred values
     unsigned nblk = 0;
@@ -341,7 +342,9 @@ LeanLayout lean_layout(const Geo& g, int effect) {
         off += align256(n);
         return o;
     };
+    for (int j = 0; j + 1 < g.nlev; ++j) f.nblk += lean_tiles(g.Wi[g.levels[j] - 1] / 32, g.Hi[g.levels[j] - 1]);
     f.count = take(4 * kMaxLevels);
+    f.tot = take(4 * (size_t)f.nblk);  // per ranking tile: its stencil texels
     for (int j = 0; j + 1 < g.nlev; ++j) {
         const int i = g.levels[j];
         const size_t n = (size_t)g.n(i);
@@ -352,7 +355,6 @@ LeanLayout lean_layout(const Geo& g, int effect) {
         f.list[i - 1] = take(4 * n);
         f.ac[i - 1] = take(4 * n);
         f.cc[i - 1] = take(4 * n * C);
-        f.nblk += lean_tiles(g.Wi[i - 1] / 32, g.Hi[i - 1]);
     }
     for (int j = 0; j < g.nlev; ++j) {
         const int i = g.levels[j];
@@ -767,11 +769,15 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
             ea.wpr[i - 1] = g.Wi[i - 1] / 32;
         }
     }
-    ea.zero_counts = count;
+    // the edge kernel zeroes the level counts (those of levels without a
+    // list stay 0; the ranking writes the others)
+    ea.zero = count;
+    ea.zero_n = kMaxLevels;
     // stencils, ranks, lists (a_i at listed texels comes with the evaluation)
     LeanArgs& la = P.la;
     la.nlev = g.nlev - 1;
     la.count = count;
+    la.tot = reinterpret_cast<uint32_t*>(b + f.tot);
     unsigned blk = 0;
     for (int j = 0; j + 1 < g.nlev; ++j) {
         const int i = g.levels[j];
@@ -788,8 +794,9 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         L.nwords = (unsigned)L.wpr * (unsigned)L.H;
         L.tiles_x = (L.wpr + kLeanTileWords - 1) / kLeanTileWords;
         L.blk_base = blk;
+        L.ntiles = lean_tiles(L.wpr, L.H);
         L.count_idx = i - 1;
-        blk += lean_tiles(L.wpr, L.H);
+        blk += L.ntiles;
     }
     la.nblk = blk;
     if (d->level_map) {
@@ -991,7 +998,7 @@ BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos) {
     L.tl = take(sizeof(LeanArgs) * n);
     L.tv = take((fr[0].effect == MR_EFFECT_SSAO ? sizeof(SsaoArgs) : sizeof(SsgiArgs)) * n);
     L.tm = take(sizeof(LeanMergeArgs) * n);
-    L.bases = take(sizeof(unsigned) * (kBatchTables * (MR_MAX_BATCH + 1) + kQueueCounters));
+    L.bases = take(sizeof(unsigned) * (kBatchTables * (MR_MAX_BATCH + 1) + kBatchCounters));
     for (int k = 0; k < n; ++k) L.frames[k] = take(lean_layout(geos[k], fr[k].effect).bytes);
     L.bytes = off;
     return L;
@@ -1212,9 +1219,11 @@ int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, const mr_ma
     return MR_OK;
 }
 
-int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
+// The whole frame; `path_only`: the workspace need only hold the layout of
+// the path these parameters take (the static-scratch entry point), else
+// that of either path (what mr_workspace_bytes reports).
+static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStream_t s, bool path_only) {
     if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const int effect = d->effect;
     int st = check_effect_params(effect, d->ssao, d->shadow, d->ssgi);
     if (st) return st;
@@ -1246,10 +1255,11 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     if ((st = check_bilateral(d, g))) return st;
     const FrameLayout f = frame_layout(g, effect);
     const size_t lean_bytes = lean_layout(g, effect).bytes;
-    const size_t need = f.bytes > lean_bytes ? f.bytes : lean_bytes;
+    const bool lean = lean_ok(g, &d->mp);
+    const size_t need = path_only ? (lean ? lean_bytes : f.bytes) : (f.bytes > lean_bytes ? f.bytes : lean_bytes);
     if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
-    if (lean_ok(g, &d->mp)) return do_frame_lean(d, g, params, static_cast<uint8_t*>(ws), s);
+    if (lean) return do_frame_lean(d, g, params, static_cast<uint8_t*>(ws), s);
     if (d->level_dtype == MR_F16)
         return fail(MR_E_DTYPE, "f16 sub-image storage needs the compact frame path (coarsest level <= 4, width "
                                 "divisible by 128, blur radii <= 8 with positive taps)");
@@ -1296,6 +1306,34 @@ int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     for (int k = 0; k < kMaxLevels; ++k) clo[k] = lo[k];
     if ((st = do_merge(g, &d->mp, &m, clo, C, d->out, s))) return st;
     return mark(d, 3, s);
+}
+
+int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
+    return frame_run(d, ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+}
+
+int mr_frame_workspace_layout(const mr_camera* cam, const mr_mask_params* mp, int effect, mr_frame_layout* out) {
+    if (!cam || !mp || !out) return fail(MR_E_NULL, "camera, mask parameters or output is NULL");
+    if (effect != MR_EFFECT_SSAO && effect != MR_EFFECT_SHADOW && effect != MR_EFFECT_SSGI)
+        return fail(MR_E_PARAM, "unknown effect %d", effect);
+    Geo g;
+    int st = check_geo(cam, mp, g);
+    if (!st) st = check_mask_params(mp, g);
+    if (st) return st;
+    *out = mr_frame_layout{};
+    if (!lean_ok(g, mp)) return MR_OK;
+    const LeanLayout f = lean_layout(g, effect);
+    out->compact = 1;
+    out->tile_words = kLeanTileWords;
+    out->tile_rows = kLeanTileRows;
+    out->count = f.count;
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        out->worklist[i - 1] = f.list[i - 1];
+        out->stencil_bits[i - 1] = f.Sb[i - 1];
+        out->rank[i - 1] = f.woff[i - 1];
+    }
+    return MR_OK;
 }
 
 size_t mr_batch_workspace_bytes(const mr_frame_desc* frames, int n) {

@@ -108,28 +108,23 @@ __device__ __forceinline__ unsigned wave_scan_incl(unsigned v) {
     return v;
 }
 
-// One block per ranking tile: the tile's stencil words (dilated edge bits),
-// their ranks and list entries.  The tile takes its run of list positions
-// with one atomic add on the level's count, so tiles land in the list in
-// the order they finish; the rank of every texel is stored with it (woff),
-// which is all the merge needs, and each texel's result does not depend on
-// where in the list it sits.  The counts are zeroed by the edge kernel.
-// A tile of at most kRankStage entries builds its run of the list in LDS
-// and stores it with consecutive threads at consecutive positions; the
-// entries of a word are kRankStage / 512 = 16 or more dwords apart, so
-// storing them straight from each thread would touch a separate cache line
-// per thread and entry.  LDS positions are padded by one word per 32, which
-// puts the threads' entries in distinct banks.  (Measured at 4K: ranking
-// 13.3 us with direct stores, 11.5 us staging up to 4096 entries, 10.4 us
-// up to 8192; the 40 KB of LDS still leaves every block of a 4K frame
-// resident.)
-constexpr unsigned kRankStage = 8192;
-__device__ __forceinline__ unsigned stage_slot(unsigned p) { return p + (p >> 5); }
-
-__device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
+// Ranking, in two launches over the ranking tiles (one block per tile).
+//
+// 1. k_lean_stencil: the tile's stencil words (dilated edge bits) and the
+//    tile's total of stencil texels.
+// 2. k_lean_list: the tile's first list position = the sum of the totals of
+//    the level's earlier tiles; the rank of every word (woff) and the tile's
+//    run of the list.
+//
+// A level's list holds its tiles' runs in tile order (tiles row-major,
+// words row-major inside a tile, bits ascending), so the list is the same on
+// every run: a fixed permutation of the row-major list of stencil texels.
+// The rank of every texel is stored with it (woff), which is all the merge
+// needs.  (A single launch that found each tile's list position by a
+// decoupled look-back over the earlier tiles' totals made the ranking about
+// 11 us slower at 4K: every tile waited for the slowest of its predecessors.)
+__device__ __forceinline__ void stencil_block(const LeanArgs& A, unsigned b) {
     __shared__ unsigned wtot[kRankThreads / 64];
-    __shared__ unsigned tile_base, tile_total;
-    __shared__ unsigned stg[kRankStage + kRankStage / 32];
     const int l = lean_level(A, b);
     const LeanLevel& L = A.lv[l];
     __shared__ unsigned eb[kStageRows][kStageCols];
@@ -144,27 +139,58 @@ __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
 #undef MR_STENCIL
         default: break;
     }
-    if (!tw.ok) acc = 0u;
-    const unsigned cnt = __popc(acc);
-    const unsigned inc = wave_scan_incl(cnt);
-    const int wv = threadIdx.x >> 6;
-    if (__lane_id() == 63) wtot[wv] = inc;
+    if (tw.ok) L.Sb[tw.w] = acc;
+    unsigned cnt = tw.ok ? __popc(acc) : 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    if (__lane_id() == 0) wtot[threadIdx.x >> 6] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned total = 0;
 #pragma unroll
         for (int k = 0; k < kRankThreads / 64; ++k) total += wtot[k];
-        tile_total = total;
-        tile_base = total ? atomicAdd(A.count + L.count_idx, total) : 0u;
+        A.tot[b] = total;
     }
+}
+
+// A tile of at most kRankStage entries builds its run of the list in LDS
+// and stores it with consecutive threads at consecutive positions; the
+// entries of a word are kRankStage / 512 = 16 or more dwords apart, so
+// storing them straight from each thread would touch a separate cache line
+// per thread and entry.  LDS positions are padded by one word per 32, which
+// puts the threads' entries in distinct banks.  (Measured at 4K with the
+// list built in one launch: 13.3 us with direct stores, 11.5 us staging up
+// to 4096 entries, 10.4 us up to 8192.)
+constexpr unsigned kRankStage = 8192;
+__device__ __forceinline__ unsigned stage_slot(unsigned p) { return p + (p >> 5); }
+
+__device__ __forceinline__ void list_block(const LeanArgs& A, unsigned b) {
+    __shared__ unsigned wtot[kRankThreads / 64], wpre[kRankThreads / 64];
+    __shared__ unsigned stg[kRankStage + kRankStage / 32];
+    const int l = lean_level(A, b);
+    const LeanLevel& L = A.lv[l];
+    const TileWord tw = tile_word(L, b, threadIdx.x);
+    const unsigned acc = tw.ok ? L.Sb[tw.w] : 0u;
+    // the level's earlier tiles: their totals summed by the block
+    unsigned pre = 0;
+    for (unsigned u = L.blk_base + threadIdx.x; u < b; u += kRankThreads) pre += A.tot[u];
+    const unsigned total = A.tot[b];
+    const unsigned cnt = __popc(acc);
+    const unsigned inc = wave_scan_incl(cnt);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) pre += __shfl_xor(pre, d, 64);
+    const int wv = threadIdx.x >> 6;
+    if (__lane_id() == 63) wtot[wv] = inc;
+    if (__lane_id() == 0) wpre[wv] = pre;
     __syncthreads();
-    const unsigned total = tile_total, tb = tile_base;
-    unsigned ex = inc - cnt;  // entries of the tile before this word
-    for (int k = 0; k < wv; ++k) ex += wtot[k];
-    if (tw.ok) {
-        L.Sb[tw.w] = acc;
-        L.woff[tw.w] = tb + ex;
+    unsigned tb = 0, ex = inc - cnt;  // entries of the tile before this word
+#pragma unroll
+    for (int k = 0; k < kRankThreads / 64; ++k) {
+        tb += wpre[k];
+        ex += k < wv ? wtot[k] : 0u;
     }
+    if (tw.ok) L.woff[tw.w] = tb + ex;
+    if (threadIdx.x == 0 && b == L.blk_base + L.ntiles - 1) A.count[L.count_idx] = tb + total;
     const unsigned base = (unsigned)tw.y * (unsigned)L.W + (unsigned)tw.xw * 32u;
     unsigned m = acc;  // 0 outside the level
     if (total > kRankStage) {  // uniform
@@ -186,23 +212,41 @@ __device__ __forceinline__ void rank_block(const LeanArgs& A, unsigned b) {
     for (unsigned j = threadIdx.x; j < total; j += kRankThreads) L.list[tb + j] = stg[stage_slot(j)];
 }
 
-__global__ __launch_bounds__(kRankThreads) void k_lean_rank(LeanArgs A) { rank_block(A, blockIdx.x); }
+__global__ __launch_bounds__(kRankThreads) void k_lean_stencil(LeanArgs A) { stencil_block(A, blockIdx.x); }
+__global__ __launch_bounds__(kRankThreads) void k_lean_list(LeanArgs A) { list_block(A, blockIdx.x); }
 
-// frames of a batch: blk_base[f] = first block of frame f, blk_base[n] = total
-__global__ __launch_bounds__(kRankThreads) void k_lean_rank_batch(const LeanArgs* T, const unsigned* blk_base, int n) {
+// frames of a batch: blk_base[f] = first tile of frame f, blk_base[n] = total
+__device__ __forceinline__ int batch_frame(const unsigned* blk_base, int n, unsigned g) {
     int f = 0;
-    for (int k = 1; k < n; ++k) f += blockIdx.x >= blk_base[k] ? 1 : 0;
-    rank_block(T[f], blockIdx.x - blk_base[f]);
+    for (int k = 1; k < n; ++k) f += g >= blk_base[k] ? 1 : 0;
+    return f;
+}
+
+__global__ __launch_bounds__(kRankThreads) void k_lean_stencil_batch(const LeanArgs* T, const unsigned* blk_base,
+                                                                     int n) {
+    const int f = batch_frame(blk_base, n, blockIdx.x);
+    stencil_block(T[f], blockIdx.x - blk_base[f]);
+}
+
+__global__ __launch_bounds__(kRankThreads) void k_lean_list_batch(const LeanArgs* T, const unsigned* blk_base, int n) {
+    const int f = batch_frame(blk_base, n, blockIdx.x);
+    list_block(T[f], blockIdx.x - blk_base[f]);
 }
 
 hipError_t launch_lean_masks(const LeanArgs& a, hipStream_t s) {
-    if (a.nblk) hipLaunchKernelGGL(k_lean_rank, dim3(a.nblk), dim3(kRankThreads), 0, s, a);
+    if (a.nblk) {
+        hipLaunchKernelGGL(k_lean_stencil, dim3(a.nblk), dim3(kRankThreads), 0, s, a);
+        hipLaunchKernelGGL(k_lean_list, dim3(a.nblk), dim3(kRankThreads), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_lean_masks_batch(const LeanArgs* T, const unsigned* blk_base, int n, unsigned total,
                                    hipStream_t s) {
-    if (total) hipLaunchKernelGGL(k_lean_rank_batch, dim3(total), dim3(kRankThreads), 0, s, T, blk_base, n);
+    if (total) {
+        hipLaunchKernelGGL(k_lean_stencil_batch, dim3(total), dim3(kRankThreads), 0, s, T, blk_base, n);
+        hipLaunchKernelGGL(k_lean_list_batch, dim3(total), dim3(kRankThreads), 0, s, T, blk_base, n);
+    }
     return hipGetLastError();
 }
 

@@ -68,8 +68,8 @@ __device__ __forceinline__ bool ndot_lt(const float* a, const float* b, float cn
 template <typename NT>
 __global__ __launch_bounds__(256) void k_edges_generic(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
     __shared__ uint8_t p4[4][8];
-    if (a.zero_counts && blockIdx.x == 0 && threadIdx.x < kMaxLevels) a.zero_counts[threadIdx.x] = 0u;
     const unsigned tile = xcd_remap(blockIdx.x, ntiles);
+    if (a.zero && tile * 256u + threadIdx.x < a.zero_n) a.zero[tile * 256u + threadIdx.x] = 0u;
     const int x0 = (int)(tile % tiles_x) * kEdgeTW;
     const int y0 = (int)(tile / tiles_x) * kEdgeTH;
     const int W = a.W, H = a.H;
@@ -310,11 +310,12 @@ __device__ __forceinline__ float dpp_shl1(float own, float src) {
 // that a block reads 1 KB runs of every row; levels up to 4 only (the 8 x 8
 // pooling blocks stay inside one wave).  Otherwise they are stacked (64 x 32
 // tile) and levels 5 and 6 are pooled across the waves through LDS.
-// One tile of the edge image (`first`: the block that zeroes the counters).
+// One tile of the edge image; tile k also zeroes counter words 256 k ..
+// 256 k + 255 (those below zero_n).
 template <typename NT, bool HARD, bool BITS, bool WIDE>
-__device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, unsigned tiles_x, bool first) {
+__device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, unsigned tiles_x) {
     __shared__ uint8_t p4[4][8];
-    if (a.zero_counts && first && threadIdx.x < kMaxLevels) a.zero_counts[threadIdx.x] = 0u;
+    if (a.zero && tile * 256u + threadIdx.x < a.zero_n) a.zero[tile * 256u + threadIdx.x] = 0u;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int x0 = WIDE ? (int)(tile % tiles_x) * (4 * kEdgeTW) + wave * kEdgeTW : (int)(tile % tiles_x) * kEdgeTW;
     const int y0 = WIDE ? (int)(tile / tiles_x) * 8 : (int)(tile / tiles_x) * kEdgeTH;
@@ -619,7 +620,7 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
 
 template <typename NT, bool HARD, bool BITS, bool WIDE>
 __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x, unsigned ntiles) {
-    edges_tile<NT, HARD, BITS, WIDE>(a, xcd_remap(blockIdx.x, ntiles), tiles_x, blockIdx.x == 0);
+    edges_tile<NT, HARD, BITS, WIDE>(a, xcd_remap(blockIdx.x, ntiles), tiles_x);
 }
 
 // Frames of a batch: one grid over all frames' tiles (tile_base[f] = first
@@ -627,12 +628,12 @@ __global__ __launch_bounds__(256) void k_edges_vec(EdgeArgs a, unsigned tiles_x,
 template <typename NT, bool HARD, bool BITS, bool WIDE>
 __global__ __launch_bounds__(256) void k_edges_batch(const EdgeArgs* T, const unsigned* tile_base,
                                                      const unsigned* tiles_x, int n, unsigned* queue) {
-    if (blockIdx.x == 0 && threadIdx.x < kQueueCounters) queue[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kBatchCounters) queue[threadIdx.x] = 0u;
     const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
     int f = 0;
     for (int k = 1; k < n; ++k) f += g >= tile_base[k] ? 1 : 0;
     const unsigned local = g - tile_base[f];
-    edges_tile<NT, HARD, BITS, WIDE>(T[f], local, tiles_x[f], local == 0);
+    edges_tile<NT, HARD, BITS, WIDE>(T[f], local, tiles_x[f]);
 }
 
 hipError_t launch_edges_batch(const EdgeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,

@@ -87,7 +87,10 @@ struct EdgeArgs {
     // bit x % 32 of word x / 32, rows of wpr words; null = not written
     uint32_t* Eb[3];
     int wpr[3];
-    uint32_t* zero_counts;  // optional: MR_MAX_LEVELS counters set to 0 by block 0
+    // optional: words zero[0 .. zero_n) set to 0, 256 per tile (the frame's
+    // level counts)
+    uint32_t* zero;
+    unsigned zero_n;
     // importance mask of a gaze point (fov != 0): squared radii, FP32
     int fov;
     float fgx, fgy, fri2, fro2;
@@ -246,16 +249,17 @@ struct LeanLevel {
     float* ac;           // a_i by rank
     int W, H, wpr, r;
     int tiles_x;         // ranking tiles per row of words
-    unsigned nwords, blk_base;
+    unsigned nwords, blk_base, ntiles;
     int count_idx;
     float g[2 * kMaxRadius + 1];
 };
 
 struct LeanArgs {
-    LeanLevel lv[3];  // enabled levels below the coarsest (levels 1..3)
+    LeanLevel lv[3];    // enabled levels below the coarsest (levels 1..3)
     int nlev;
-    unsigned nblk;    // ranking tiles (one block each) over all levels
-    uint32_t* count;  // per level, zero on entry
+    unsigned nblk;      // ranking tiles (one block each) over all levels
+    uint32_t* count;    // per level, written by the level's last tile
+    uint32_t* tot;      // per ranking tile: its number of stencil texels
 };
 
 struct LeanMapArgs {
@@ -378,6 +382,8 @@ hipError_t launch_lean_masks_batch(const LeanArgs* T, const unsigned* blk_base, 
                                    hipStream_t s);
 // how a batched evaluation hands out its chunks
 constexpr int kQueueCounters = 8;  // work-queue counters: one per XCD
+// words zeroed by the batch's edge launch: the queue counters
+constexpr int kBatchCounters = kQueueCounters;
 struct BatchSchedule {
     bool queue_mode;    // per-XCD work queues instead of fixed strides
     int blocks_per_cu;  // grid cap per CU, 0: as many blocks as are resident

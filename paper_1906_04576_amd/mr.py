@@ -109,6 +109,13 @@ class mr_batch_config(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mr_frame_layout(ctypes.Structure):
+    _fields_ = [("compact", ctypes.c_int), ("tile_words", ctypes.c_int), ("tile_rows", ctypes.c_int),
+                ("count", ctypes.c_size_t),
+                ("worklist", ctypes.c_size_t * MR_MAX_LEVELS), ("stencil_bits", ctypes.c_size_t * MR_MAX_LEVELS),
+                ("rank", ctypes.c_size_t * MR_MAX_LEVELS)]
+
+
 # entry points and their ctypes signatures (also used by the export test)
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -141,6 +148,8 @@ SIGNATURES = {
     "mr_batch_get_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
     "mr_batch_set_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
     "mr_batch_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mr_batch_config), _P]),
+    "mr_frame_workspace_layout": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
+                                                 ctypes.c_int, ctypes.POINTER(mr_frame_layout)]),
     "mr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mr_last_error": (ctypes.c_char_p, []),
     "mr_version": (ctypes.c_int, []),
@@ -587,9 +596,54 @@ class FrameRunner:
             self.desc.stage_events[k] = e.cuda_event
         self._events = tuple(events)
 
+    def _hold_for(self, stream):
+        """A frame enqueued on a stream other than torch's current one
+        keeps its workspace and output alive for that stream: torch's caching
+        allocator would otherwise hand their memory to the next allocation on
+        the current stream while the frame still runs."""
+        if stream is not None and stream != torch.cuda.current_stream():
+            self.workspace.record_stream(stream)
+            self.out.record_stream(stream)
+
     def __call__(self, stream=None):
+        self._hold_for(stream)
         _check(self._fn(ctypes.byref(self.desc), self._ws, self._nws, _stream(stream)))
         return self.out
+
+    def layout(self) -> mr_frame_layout:
+        return mr_frame_workspace_layout(self.desc.cam, self.desc.mp, self.effect)
+
+    def lists(self) -> dict:
+        """After the frame has completed: {level: (worklist, stencil bits,
+        ranks)} of the compact path's list levels as CPU int64 / uint32
+        arrays, read from the workspace."""
+        import numpy as np
+        lay = self.layout()
+        if not lay.compact:
+            raise ValueError("the frame does not take the compact path")
+        ws = self.workspace
+        W, H = self.desc.cam.width, self.desc.cam.height
+
+        def words(off, n):
+            return ws[off:off + 4 * n].cpu().numpy().view(np.uint32)
+
+        counts = words(lay.count, MR_MAX_LEVELS)
+        res = {}
+        for i in range(1, MR_MAX_LEVELS + 1):
+            if not lay.worklist[i - 1]:
+                continue
+            Wi, Hi = W >> (i - 1), H >> (i - 1)
+            n = int(counts[i - 1])
+            res[i] = (words(lay.worklist[i - 1], n).astype(np.int64),
+                      words(lay.stencil_bits[i - 1], Hi * (Wi // 32)).reshape(Hi, Wi // 32),
+                      words(lay.rank[i - 1], Hi * (Wi // 32)).reshape(Hi, Wi // 32))
+        return res
+
+
+def mr_frame_workspace_layout(cam: mr_camera, cmp: mr_mask_params, effect) -> mr_frame_layout:
+    lay = mr_frame_layout()
+    _check(lib().mr_frame_workspace_layout(ctypes.byref(cam), ctypes.byref(cmp), int(effect), ctypes.byref(lay)))
+    return lay
 
 
 def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,

@@ -43,7 +43,7 @@ def test_struct_sizes_match_header_layout():
 
 
 STRUCTS = ["mr_gbuffer", "mr_camera", "mr_fovea", "mr_mask_params", "mr_masks", "mr_ssao_params", "mr_shadow_params",
-           "mr_ssgi_params", "mr_frame_desc", "mr_batch_config", "mr_bilateral_params"]
+           "mr_ssgi_params", "mr_frame_desc", "mr_batch_config", "mr_bilateral_params", "mr_frame_layout"]
 
 
 @pytest.mark.skipif(not shutil.which("gcc"), reason="needs a C compiler")
@@ -168,3 +168,56 @@ def test_shadow_params_validation():
     sp.light_near = 0.0
     assert L.mr_shadow_hard(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(sp), ctypes.c_void_p(4096),
                             None) == mr.MR_E_PARAM
+
+
+def test_frame_workspace_layout_on_the_host():
+    """The compact path's mask layout (host call, no GPU): list, stencil-bit
+    and rank regions of every list level lie inside the workspace without
+    overlap, after the counter words; other parameters report compact = 0."""
+    mp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=(0.924, 1.848, 3.696, 0.0),
+                       weight=(100.0, 50.0, 20.0, 1.0))
+    for W, H in ((3840, 2160), (1920, 1080), (256, 256)):
+        cam = mr.camera(W, H, 100.0)
+        lay = mr.mr_frame_workspace_layout(cam, mp.c(), mr.MR_EFFECT_SSAO)
+        assert lay.compact == 1 and (lay.tile_words, lay.tile_rows) == (16, 32)
+        nws = mr.mr_workspace_bytes(W, H, 100.0, mp, mr.MR_EFFECT_SSAO)
+        assert lay.count == 0
+        spans = []
+        for i in (1, 2, 3):
+            Wi, Hi = W >> (i - 1), H >> (i - 1)
+            words = (Wi // 32) * Hi
+            spans += [(lay.worklist[i - 1], 4 * Wi * Hi), (lay.stencil_bits[i - 1], 4 * words),
+                      (lay.rank[i - 1], 4 * words)]
+        assert lay.worklist[3] == 0
+        spans.sort()
+        assert spans[0][0] >= 4 * 6
+        for (a, n), (b, _) in zip(spans, spans[1:]):
+            assert a + n <= b
+        assert spans[-1][0] + spans[-1][1] <= nws
+    lay = mr.mr_frame_workspace_layout(mr.camera(200, 120, 100.0), mp.c(), mr.MR_EFFECT_SSAO)
+    assert lay.compact == 0 and lay.worklist[0] == 0
+    with pytest.raises(mr.MRError):
+        mr.mr_frame_workspace_layout(mr.camera(0, 120, 100.0), mp.c(), mr.MR_EFFECT_SSAO)
+
+
+def test_frame_on_another_stream_holds_its_memory(monkeypatch):
+    """A frame enqueued on a stream other than the current one records that
+    stream on its workspace and output (torch's caching allocator then keeps
+    the memory until the stream has passed that point); on the current
+    stream, or with no stream, nothing is recorded."""
+    class FakeTensor:
+        def __init__(self):
+            self.streams = []
+
+        def record_stream(self, s):
+            self.streams.append(s)
+
+    current, other = object(), object()
+    monkeypatch.setattr(mr.torch.cuda, "current_stream", lambda: current)
+    fr = object.__new__(mr.FrameRunner)
+    fr.workspace, fr.out = FakeTensor(), FakeTensor()
+    fr._hold_for(None)
+    fr._hold_for(current)
+    assert fr.workspace.streams == [] and fr.out.streams == []
+    fr._hold_for(other)
+    assert fr.workspace.streams == [other] and fr.out.streams == [other]

@@ -5,7 +5,8 @@ of level 1 there on the stencil (Sec. 3.1 edges, Sec. 4.1 stencil), so the
 ranking tiles of 512 x 32 texels on that side hold more list entries than a
 tile builds in LDS and store them directly, while the tiles on the smooth
 side build theirs in LDS.  Both run in one frame, which must equal the
-oracle's bit for bit (masks, lists and lighting)."""
+oracle's bit for bit: the level map, the frame path's lists, stencil words
+and ranks (in ranking-tile order, see listcheck.py) and the image."""
 import math
 import sys
 
@@ -15,6 +16,7 @@ import torch
 
 import oracle
 import scenegen
+from listcheck import check_frame_lists
 from paper_1906_04576_amd import mr
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +62,11 @@ def test_dense_and_sparse_ranking_tiles_in_one_frame(seed):
     n = torch.from_numpy(normal).to(DEV)
     k = torch.from_numpy(K).to(DEV)
     lm = torch.empty((H, W), dtype=torch.uint8, device=DEV)
-    out = mr.mr_frame("ssao", d, n, focal, params(mr), mr.ssao_params(k, 1.0, 0.02), level_map=lm)
+    fr = mr.FrameRunner("ssao", d, n, focal, params(mr), True, params=mr.ssao_params(k, 1.0, 0.02), level_map=lm)
+    out = fr()
     torch.cuda.synchronize()
     assert np.array_equal(lm.cpu().numpy(), ref.pyramid.level_map)
+    check_frame_lists(fr.lists(), ref.pyramid)
     got = out.cpu().numpy()
     assert np.abs(got - ref.out).max() <= 1e-4
     assert np.array_equal(got, ref.out)

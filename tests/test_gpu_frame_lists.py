@@ -1,0 +1,73 @@
+"""Work lists of the timed frame path (Sec. 4.1: the stencil texels each
+level renders), read back from mr_frame's workspace and compared bit for bit
+with the oracle's stencils: the list in ranking-tile order (a fixed
+permutation of the row-major list, see listcheck.py), the stencil words and
+the per-word ranks.  Also: the same lists on every run, and the frame image
+against the oracle, at the 1080p workload and the 4K headline workload (the
+scene generator with 200 boxes and 50 spheres, 4 levels, SSAO with 32
+samples, radius 1.0)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from listcheck import check_frame_lists
+from paper_1906_04576_amd import mr
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+COS25 = float(np.float32(math.cos(math.radians(25.0))))
+
+CASES = {
+    # name: (W, H, boxes, spheres, seed, camera, samples, radius)
+    "384x200": (384, 200, 40, 10, 9, 2, 16, 0.8),
+    "640x360": (640, 360, 60, 15, 8, 5, 16, 1.0),
+    "1080p": (1920, 1080, 200, 50, 1, 0, 32, 1.0),
+    "4k_seed2_cam3": (3840, 2160, 200, 50, 2, 3, 32, 1.0),
+    "4k_seed3_cam6": (3840, 2160, 200, 50, 3, 6, 32, 1.0),
+}
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def params(lib):
+    t = scenegen.TABLE1["ssao"]
+    return lib.MaskParams(num_levels=4, level_enable=0xF, sigma2=t["sigma2"], weight=t["weight"], normal_cos=COS25)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_frame_path_lists_and_image_match_the_oracle(name):
+    W, H, nb, ns, seed, cam, S, r = CASES[name]
+    log(f"[gpu] frame lists {name} {W}x{H}")
+    scene = scenegen.make_scene(seed, nb, ns)
+    gb = scenegen.render_gbuffer(scene, scenegen.orbit_view(cam), W, H)
+    K = scenegen.ssao_kernel(S)
+    ref = oracle.frame("ssao", gb.depth, gb.normal, gb.focal, params(oracle), oracle.SSAOParams(K, r, 0.02))
+    d = torch.from_numpy(gb.depth).to(DEV)
+    n = torch.from_numpy(gb.normal).to(DEV)
+    k = torch.from_numpy(K).to(DEV)
+    fr = mr.FrameRunner("ssao", d, n, gb.focal, params(mr), True, params=mr.ssao_params(k, r, 0.02))
+    fr()
+    torch.cuda.synchronize()
+    first = fr.lists()
+    check_frame_lists(first, ref.pyramid)
+    got = fr.out.cpu().numpy()
+    assert np.abs(got - ref.out).max() <= 1e-4
+    assert np.array_equal(got, ref.out)
+    # run to run: the same lists after other frames have used the GPU
+    for _ in range(3):
+        fr()
+    torch.cuda.synchronize()
+    again = fr.lists()
+    for i in first:
+        for a, b in zip(first[i], again[i]):
+            assert np.array_equal(a, b), f"level {i} changed between runs"
+    assert np.array_equal(fr.out.cpu().numpy(), got)
