@@ -338,6 +338,22 @@ MR_API int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, cons
  * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */
 MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream);
 
+/* mr_frame for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same frame with the workspace taken from a static device array of
+ * MR_STATIC_SCRATCH_BYTES, one per device, that the library holds until the
+ * process ends.  It enqueues the same kernels as mr_frame and calls no
+ * allocating routine.  The stream's device must be the current device.
+ * Frames whose intermediates need more than MR_STATIC_SCRATCH_BYTES (on the
+ * compact path a 3840x2160 frame needs 27-39 MB; the other path needs about
+ * 4.5 B/px more) are rejected with MR_E_WORKSPACE.  Every call on a device
+ * shares that device's array: calls that may overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller; the array
+ * keeps the last frame's intermediates, and each frame initialises what it
+ * reads. */
+#define MR_STATIC_SCRATCH_BYTES (64u << 20)
+MR_API int mr_frame_static(const mr_frame_desc* d, void* stream);
+
 /* Where the compact frame path keeps its masks in the workspace, as byte
  * offsets from ws (host; for callers and tests that read them after a
  * frame has completed).  compact = 1 when mr_frame takes the compact path

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "mr_internal.hpp"
@@ -1310,6 +1311,64 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
 
 int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     return frame_run(d, ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+}
+
+// ---------------------------------------------------------------------------
+// mr_frame_static: mr_frame with its workspace in a file-scope device array,
+// for callers that cannot allocate.  The array's name is only a host-side
+// handle; its device address is looked up once per device (with that device
+// current) and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[MR_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxScratchDevices] = {};
+
+// device address of `scratch` on the device of `s` (which must be current)
+int static_scratch(hipStream_t s, void** out) {
+    int cur = -1, dev = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess) e = s ? hipStreamGetDevice(s, &dev) : hipSuccess;
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "device query failed: %s", hipGetErrorString(e));
+    if (!s) dev = cur;
+    if (dev != cur) return fail(MR_E_PARAM, "the stream belongs to device %d but device %d is current", dev, cur);
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(MR_E_DEVICE, "device %d beyond the %d devices with static scratch", dev, kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MR_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return MR_OK;
+}
+}  // namespace
+
+int mr_frame_static(const mr_frame_desc* d, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
+    // the size check first, so that an oversized frame is rejected with its
+    // own message before any device query
+    if (d->multires) {
+        Geo g;
+        int st = check_geo(&d->cam, &d->mp, g);
+        if (!st) st = check_mask_params(&d->mp, g);
+        if (st) return st;
+        const size_t need = lean_ok(g, &d->mp) ? lean_layout(g, d->effect).bytes : frame_layout(g, d->effect).bytes;
+        if (need > MR_STATIC_SCRATCH_BYTES)
+            return fail(MR_E_WORKSPACE, "frame needs %zu bytes of scratch, more than the %u of MR_STATIC_SCRATCH_BYTES",
+                        need, (unsigned)MR_STATIC_SCRATCH_BYTES);
+    }
+    void* ws = nullptr;
+    const int st = static_scratch(s, &ws);
+    if (st) return st;
+    return frame_run(d, ws, MR_STATIC_SCRATCH_BYTES, s, true);
 }
 
 int mr_frame_workspace_layout(const mr_camera* cam, const mr_mask_params* mp, int effect, mr_frame_layout* out) {

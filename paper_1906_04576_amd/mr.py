@@ -26,6 +26,7 @@ MR_WS_MASKS = -1
 MR_FRAME_EVENTS = 4
 MR_MAX_BATCH = 64
 MR_BATCH_PLAN_BYTES = 512
+MR_STATIC_SCRATCH_BYTES = 64 << 20
 EFFECTS = {"ssao": MR_EFFECT_SSAO, "shadow": MR_EFFECT_SHADOW, "ssgi": MR_EFFECT_SSGI}
 
 c_float6 = ctypes.c_float * MR_MAX_LEVELS
@@ -150,6 +151,7 @@ SIGNATURES = {
     "mr_batch_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mr_batch_config), _P]),
     "mr_frame_workspace_layout": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                                  ctypes.c_int, ctypes.POINTER(mr_frame_layout)]),
+    "mr_frame_static": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P]),
     "mr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mr_last_error": (ctypes.c_char_p, []),
     "mr_version": (ctypes.c_int, []),
@@ -644,6 +646,25 @@ def mr_frame_workspace_layout(cam: mr_camera, cmp: mr_mask_params, effect) -> mr
     lay = mr_frame_layout()
     _check(lib().mr_frame_workspace_layout(ctypes.byref(cam), ctypes.byref(cmp), int(effect), ctypes.byref(lay)))
     return lay
+
+
+class StaticFrameRunner(FrameRunner):
+    """mr_frame_static: the frame with the library's static device scratch
+    instead of a workspace (for callers that cannot allocate).  Frames on
+    one device share that scratch, so they must not overlap."""
+
+    def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
+                 out=None, level_map=None, level_dtype=torch.float32, bilateral: Bilateral = None):
+        super().__init__(effect, depth, normal, focal, mp, multires, color, params, out, level_map,
+                         workspace=torch.empty(256, dtype=torch.uint8, device=depth.device),
+                         level_dtype=level_dtype, bilateral=bilateral)
+        self._fn = lib().mr_frame_static
+
+    def __call__(self, stream=None):
+        if stream is not None and stream != torch.cuda.current_stream():
+            self.out.record_stream(stream)
+        _check(self._fn(ctypes.byref(self.desc), _stream(stream)))
+        return self.out
 
 
 def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,
