@@ -687,9 +687,12 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
         stage4<3, 3, R4::rw, C, VT>(a, t - nB, x0, y0, av[1], cv[1]);
     else if (t >= 128 && t < 128 + R3::n)
         stage4<2, 2, R3::rw, C, VT>(a, t - 128, x0, y0, av[1], cv[1]);
-    const int q = t & 15, row = t >> 4;
-    const int Y = y0 + row;
-    const int XQ = x0 + 4 * q;
+    // a wave covers a 16 x 16 pixel square of the tile (four pixels of a row
+    // per thread), so that the pixels near a stencil, where the blends run,
+    // fill fewer waves
+    const int w = t >> 6, l = t & 63;
+    const int Y = y0 + (l >> 2);
+    const int XQ = x0 + 16 * w + 4 * (l & 3);
     const bool active = Y < a.H && XQ < a.W;
     // ---- level 1: four pixels per thread, values by rank ----
     float a1[4] = {0, 0, 0, 0}, c1[C][4];
