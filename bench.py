@@ -25,18 +25,32 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x GHz: non-packed FP32 lane-ops/s
-# algorithmic FP32 operations of one SSAO sample: the sample point (3 x 3
-# multiplies + 3 x 3 adds), the reciprocal of its depth, the projection (2 x
-# (2 multiplies + 1 add)), 4 bounds tests, 2 floor conversions, the validity
-# test, the biased depth (multiply + subtract) and its test, the range test
-# (subtract, test) and the count
-SSAO_OPS_PER_SAMPLE = 41
-SSAO_OPS_PER_TEXEL = 40         # per evaluated texel outside the sample loop
+# FP32 arithmetic pipe: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-fused,
+# non-packed FP32 add / multiply / divide step per lane and clock (the
+# bit-exact contract rules out FMA contraction and packed FP32): 157.3 TFLOP/s
+# / 4.  A stream of independent v_add_f32 / v_mul_f32 / v_fma_f32 measured
+# 38.7 T lane-ops/s on the box.  Integer, compare and select instructions
+# issue at twice that rate there (measured 64.5 T), so they are not counted
+# against this pipe.
+FP32_PIPE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic FP32 arithmetic of the SSAO estimator (Sec. 2.4 reading):
+# per sample the sample point (9 multiplies + 9 adds), the reciprocal of its
+# depth, the projection (2 x (2 multiplies + 1 add)), the biased depth
+# (multiply + subtract) and the range difference (subtract) = 28; per texel
+# the view position (2 x (add, subtract, divide) + 2 multiplies), the
+# tangent frame (13), the scaled frame (9 multiplies) and the final divide
+# = 31.  Tests, floors, conversions and the count are not FP32 arithmetic.
+SSAO_FP32_PER_SAMPLE = 28
+SSAO_FP32_PER_TEXEL = 31
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (profiles/), scaled by the copy-kernel calibration;
 # None until measured for the current kernel
-TRAFFIC_BYTES = {"k_ssao_multi": 77367778}
+TRAFFIC_BYTES = {"k_ssao_multi": None}
+# VALU issue of the dominant kernel from the SQ_INSTS_VALU_* counters
+# (profiles/): wave instructions per launch of the FP32 arithmetic classes
+# (add, multiply, FMA, transcendental, conversion; 4 cycles per wave64
+# instruction) and of all other VALU instructions (2 cycles)
+VALU_ISSUE = {"k_ssao_multi": None}
 
 
 def log(*a):
@@ -62,11 +76,183 @@ def parse():
                     help="skip the paper variants (bilateral blur, foveated mask, fewer samples at full resolution)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched uneven-frame SSGI measurement (24 frames, 640x360..3840x2160)")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the sample-count sweep (16..256 at 4K) and the resolution sweep (720p..4K at S = 64)")
+    ap.add_argument("--no-pcss", action="store_true",
+                    help="skip the 4K soft-shadow frames (2048^2 map, 16 + 32 samples, FP16 normals)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--no-quality", action="store_true", help="profile helper: skip the multi vs naive comparison")
     ap.add_argument("--plain", action="store_true", help="profile helper: time only the naive pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profile helper: first run a 256 MiB device-to-device copy (known HBM traffic)")
     return ap.parse_args()
+
+
+def _wall(fn, steps, warm=2):
+    """Seconds per call of fn over `steps` calls, between device syncs."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _cycle(runners):
+    """Callable running the next runner of the list on each call."""
+    state = {"k": 0}
+
+    def go():
+        runners[state["k"] % len(runners)]()
+        state["k"] += 1
+    return go
+
+
+def sweep_samples(frames, W, H, focal, mp, dev, samples=(16, 32, 64, 128, 256), radius=1.0):
+    """4K frame time, multi-resolution and naive, for every SSAO sample count
+    (the analogue of the paper's speedup-vs-samples figure), over the
+    resident configurations; RMS of multi-res vs naive on 4 of them."""
+    import torch
+    import scenegen
+    from paper_1906_04576_amd import mr
+    ws = torch.empty(mr.mr_workspace_bytes(W, H, focal, mp, mr.MR_EFFECT_SSAO), dtype=torch.uint8, device=dev)
+    res = []
+    for S in samples:
+        sp = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(S)).to(dev), radius, 0.02)
+        multi = [mr.FrameRunner("ssao", f["d"], f["n"], focal, mp, True, params=sp, workspace=ws) for f in frames]
+        plain = [mr.FrameRunner("ssao", f["d"], f["n"], focal, mp, False, params=sp) for f in frames]
+        nf = len(frames)
+        tm = _wall(_cycle(multi), 2 * nf)
+        tp = _wall(_cycle(plain), max(nf // 2, 8) if S >= 128 else nf)
+        rms = []
+        for k in range(min(4, nf)):
+            a = multi[k]().clone()
+            b = plain[k]()
+            rms.append(float((a - b).double().pow(2).mean().sqrt()))
+        res.append({"samples": S, "multi_ms": round(tm * 1e3, 5), "plain_ms": round(tp * 1e3, 5),
+                    "speedup": round(tp / tm, 3), "multi_mpixels_s": round(W * H / tm / 1e6, 2),
+                    "rms_vs_plain": round(float(np.mean(rms)), 6)})
+        log(f"[bench] sweep S={S}: multi {tm * 1e3:.4f} ms, naive {tp * 1e3:.4f} ms, {tp / tm:.2f}x")
+    return res
+
+
+def sweep_resolution(dev, samples=64, radius=1.0, cams=8):
+    """Frame time at 720p .. 4K with 64 samples (the analogue of the
+    paper's speedup-vs-resolution figure), scene seed 1, 8 cameras."""
+    import torch
+    import scenegen
+    from paper_1906_04576_amd import mr
+    mp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=scenegen.TABLE1["ssao"]["sigma2"],
+                       weight=scenegen.TABLE1["ssao"]["weight"])
+    sp = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(samples)).to(dev), radius, 0.02)
+    scene = scenegen.make_scene(1, 200, 50)
+    res = []
+    for (W, H) in ((1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)):
+        gbs = [scenegen.render_gbuffer(scene, scenegen.orbit_view(c), W, H) for c in range(cams)]
+        focal = gbs[0].focal
+        ds = [(torch.from_numpy(g.depth).to(dev), torch.from_numpy(g.normal).to(dev)) for g in gbs]
+        ws = torch.empty(mr.mr_workspace_bytes(W, H, focal, mp, mr.MR_EFFECT_SSAO), dtype=torch.uint8, device=dev)
+        multi = [mr.FrameRunner("ssao", d, n, focal, mp, True, params=sp, workspace=ws) for d, n in ds]
+        plain = [mr.FrameRunner("ssao", d, n, focal, mp, False, params=sp) for d, n in ds]
+        tm = _wall(_cycle(multi), 4 * cams)
+        tp = _wall(_cycle(plain), 2 * cams)
+        res.append({"width": W, "height": H, "samples": samples, "multi_ms": round(tm * 1e3, 5),
+                    "plain_ms": round(tp * 1e3, 5), "speedup": round(tp / tm, 3),
+                    "multi_mpixels_s": round(W * H / tm / 1e6, 2)})
+        log(f"[bench] sweep {W}x{H} S={samples}: multi {tm * 1e3:.4f} ms, naive {tp * 1e3:.4f} ms, {tp / tm:.2f}x")
+    return res
+
+
+def pcss_4k(dev, cams=4):
+    """Soft shadows at 3840x2160: a 2048^2 shadow map from one square light
+    of side 0.5, 16 blocker + 32 PCF samples, FP16 normals, 4 levels with the
+    soft-shadow column of Table 1; frame time multi-res vs naive."""
+    import torch
+    import scenegen
+    from paper_1906_04576_amd import mr
+    w = scenegen.WORKLOADS["pcss_4k"]
+    W, H = w["width"], w["height"]
+    t = scenegen.TABLE1["shadow"]
+    mp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=t["sigma2"], weight=t["weight"])
+    scene = scenegen.make_scene(2, w["boxes"], w["spheres"])
+    bd = torch.from_numpy(scenegen.disk_samples(w["n_blocker"], 11)).to(dev)
+    pd = torch.from_numpy(scenegen.disk_samples(w["n_pcf"], 12)).to(dev)
+    multi, plain, keep = [], [], []
+    ws = None
+    for c in range(cams):
+        gb = scenegen.render_gbuffer(scene, scenegen.orbit_view(c), W, H)
+        si = scenegen.render_shadow_inputs(scene, gb.view, w["sm_size"], light_size=w["light_size"])
+        d = torch.from_numpy(gb.depth).to(dev)
+        n = torch.from_numpy(gb.normal.astype(np.float16)).to(dev)
+        sp = mr.shadow_params(torch.from_numpy(si.shadow_map).to(dev), si.view_to_light, si.light_focal,
+                              si.light_size, si.light_near, 0.05, bd, pd)
+        if ws is None:
+            ws = torch.empty(mr.mr_workspace_bytes(W, H, gb.focal, mp, mr.MR_EFFECT_SHADOW), dtype=torch.uint8,
+                             device=dev)
+        multi.append(mr.FrameRunner("shadow", d, n, gb.focal, mp, True, params=sp, workspace=ws))
+        plain.append(mr.FrameRunner("shadow", d, n, gb.focal, mp, False, params=sp))
+        keep.append(sp)
+    tm = _wall(_cycle(multi), 8 * cams)
+    tp = _wall(_cycle(plain), 4 * cams)
+    mad = float(np.mean([float((multi[k]().clone() - plain[k]()).double().abs().mean()) for k in range(cams)]))
+    log(f"[bench] 4K PCSS: multi {tm * 1e3:.4f} ms, naive {tp * 1e3:.4f} ms, {tp / tm:.2f}x")
+    return {"workload": f"pcss_4k: {W}x{H}, 2048^2 shadow map, 16 blocker + 32 PCF samples, FP16 normals, "
+                        f"4 levels, {cams} cameras of scene seed 2",
+            "multi_ms": round(tm * 1e3, 5), "plain_ms": round(tp * 1e3, 5), "speedup": round(tp / tm, 3),
+            "multi_mpixels_s": round(W * H / tm / 1e6, 2), "mad_vs_plain": round(mad, 6)}
+
+
+def serving(qps=4000.0, seconds=1.5):
+    """The request loop (serve.py) on a Poisson stream: p50 / p99 latency and
+    Mpixels/s, multi-resolution and naive, on the same requests."""
+    from paper_1906_04576_amd import serve
+    pool = serve.Pool(2)
+    reqs = serve.poisson_requests(pool, qps, seconds)
+    out = {"qps": qps, "seconds": seconds, "requests": len(reqs), "slots": 4, "budget_gb": 64}
+    for multires in (True, False):
+        srv = serve.Server(pool, 4, 64 << 30, multires)
+        srv.run(reqs[: min(len(reqs), 64)])
+        s_ = serve.summary(srv.run(reqs))
+        s_["saturated_mpixels_s"] = serve.summary(srv.run(reqs, realtime=False))["mpixels_s"]
+        out["multires" if multires else "plain"] = s_
+        log(f"[bench] serving {'multi-res' if multires else 'naive'}: {s_}")
+    return out
+
+
+def oracle_ssao_threads(depth, normal, focal, omp, op, pool, nthreads, multires=True):
+    """The oracle's SSAO frame with its per-texel estimator split over
+    threads (numpy releases the interpreter lock in its array loops): the
+    mask pyramid and the merge as in oracle.frame, every level's texels cut
+    into nthreads runs evaluated by oracle.ssao_texels.  Texels are
+    independent, so the image is bit-identical to oracle.frame's."""
+    import oracle
+
+    def level(zi, ni, i, sel):
+        Hi, Wi = zi.shape
+        ys, xs = np.divmod(np.arange(Hi * Wi), Wi) if sel is None else np.nonzero(sel)
+        out = np.full((Hi, Wi), np.nan, np.float32)
+        # runs of at least 64K texels: smaller arrays spend their time in the
+        # interpreter, which the threads share
+        nrun = max(1, min(nthreads, len(xs) // 65536))
+        runs = [r for r in np.array_split(np.arange(len(xs)), nrun) if len(r)]
+        vals = pool.map(lambda r: oracle.ssao_texels(zi, ni, focal, i, xs[r], ys[r], op), runs)
+        for r, v in zip(runs, vals):
+            out[ys[r], xs[r]] = v
+        return out
+
+    if not multires:
+        return level(depth, normal, 1, None)
+    E = oracle.edge_image(depth, normal, omp.depth_ratio, omp.normal_cos)
+    pyr = oracle.build_pyramid(E, omp)
+    L = pyr.levels[-1]
+    lo = {i: level(oracle.level_sample(depth, i), oracle.level_sample(normal, i), i,
+                   None if i == L else pyr.stencil[i]) for i in pyr.levels}
+    H, W = depth.shape
+    return oracle.upsample_merge(W, H, pyr.levels, {i: omp.weight[i - 1] for i in pyr.levels}, pyr.alpha,
+                                 pyr.stencil, lo)
 
 
 def main():
@@ -308,8 +494,8 @@ def main():
         b_merge = nb / 8 + 4 * nb / 32 + 8 * listed + 4 * n[3] + 4 * n[0]
         b_frame = b_masks + b_eval + b_merge
         t_frame = wall_m / args.steps
-        ops_multi = evaluated * (SSAO_OPS_PER_SAMPLE * S + SSAO_OPS_PER_TEXEL)
-        ops_plain = n[0] * (SSAO_OPS_PER_SAMPLE * S + SSAO_OPS_PER_TEXEL)
+        ops_multi = evaluated * (SSAO_FP32_PER_SAMPLE * S + SSAO_FP32_PER_TEXEL)
+        ops_plain = n[0] * (SSAO_FP32_PER_SAMPLE * S + SSAO_FP32_PER_TEXEL)
         t_eval = stages["multi_eval_ms"] * 1e-3
         stages.update({
             "coverage_f1_f2_f3": [round(c, 5) for c in cov], "F": round(F, 5),
@@ -319,16 +505,27 @@ def main():
             "frame_hbm_frac_incl_gathers": round((b_frame + 4.0 * S * evaluated) / t_frame / (HBM_PEAK_GBS * 1e9), 4),
             "masks_hbm_frac": round(b_masks / (stages["multi_masks_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "merge_hbm_frac": round(b_merge / (stages["multi_merge_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-            "eval_multi_valu_frac": round(ops_multi / t_eval / (VALU_PEAK_TOPS * 1e12), 4),
-            "eval_plain_valu_frac": round(ops_plain / (stages["plain_eval_ms"] * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4),
+            "eval_multi_fp32_frac": round(ops_multi / t_eval / (FP32_PIPE_PEAK_TOPS * 1e12), 4),
+            "eval_plain_fp32_frac": round(ops_plain / (stages["plain_eval_ms"] * 1e-3) / (FP32_PIPE_PEAK_TOPS * 1e12),
+                                          4),
         })
         # dominant kernel of the multi-resolution frame: the per-level SSAO
         # evaluation, one launch per frame bracketed by events [1] and [2]
         achieved = ops_multi / t_eval / 1e12
         roofline = {"kernel": "k_ssao<float, true, true> (all levels of one frame in one launch)", "bound": "alu",
-                    "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi"),
-                    "launch_ms": stages["multi_eval_ms"]}
+                    "achieved": round(achieved, 3), "peak": round(FP32_PIPE_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_PIPE_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi"),
+                    "launch_ms": stages["multi_eval_ms"],
+                    "basis": f"algorithmic FP32 arithmetic ({SSAO_FP32_PER_SAMPLE} per sample, "
+                             f"{SSAO_FP32_PER_TEXEL} per texel) of {int(evaluated)} evaluated texels per launch "
+                             "against the non-fused, non-packed FP32 pipe (157.3 TFLOP/s / 4)"}
+        vi = VALU_ISSUE.get("k_ssao_multi")
+        if vi:
+            # counter-backed issue use: FP32 arithmetic wave instructions at 4
+            # cycles, the other VALU instructions at 2, against every SIMD's
+            # cycles over the launch
+            cyc = 4 * vi["fp32_arith"] + 2 * vi["other"]
+            roofline["valu_issue_frac"] = round(cyc / (1024 * 2.4e9 * t_eval), 4)
         log("[bench] stages (ms): " + ", ".join(f"{k}={v}" for k, v in stages.items() if k.endswith("_ms")))
 
     # ---------------- batched uneven SSGI frames (graph-replayed batch) ----------------
@@ -339,8 +536,17 @@ def main():
         log(f"[bench] batched SSGI: {batched['mpixels_s']} Mpixels/s, {batched['speedup_vs_plain']}x naive, "
             f"{batched['speedup_vs_sequential']}x one after another")
 
+    # ---------------- sweeps, soft shadows at 4K, serving ----------------
+    sweeps = None
+    if not args.no_sweeps:
+        sweeps = {"samples_4k": sweep_samples(frames, W, H, focal, mp, dev),
+                  "resolution_s64": sweep_resolution(dev)}
+    pcss = None if args.no_pcss else pcss_4k(dev)
+    serving_res = None if args.no_serving else serving()
+
     # ---------------- CPU oracle on a bounded sample ----------------
     cpu = None
+    cpu_threads = None
     if not args.no_cpu_baseline:
         import oracle
         omp = oracle.MaskParams(num_levels=4, level_enable=0xF, sigma2=mp.sigma2, weight=mp.weight,
@@ -361,6 +567,26 @@ def main():
                "sample": f"{done} full multi-resolution SSAO frames at {W}x{H} (configurations 0..{done - 1}), "
                          f"numpy single thread, {dt:.1f}s"}
         log(f"[bench] cpu oracle: {cpu['value']} Mpixels/s")
+        # the same oracle with its per-texel estimator over the host's cores
+        # (the box's share of them, at most 16), multi-resolution and naive
+        from concurrent.futures import ThreadPoolExecutor
+        nthr = min(len(os.sched_getaffinity(0)), 16)
+        cpu_threads = {"cores": nthr, "host_cores_visible": len(os.sched_getaffinity(0)), "kind": "oracle",
+                       "unit": "Mpixels/s"}
+        with threadpool_limits(limits=1), ThreadPoolExecutor(nthr) as pool:
+            for multires in (True, False):
+                t_c = time.perf_counter()
+                done = 0
+                for k in range(nf):
+                    gb = frames[k]["gb"]
+                    oracle_ssao_threads(gb.depth, gb.normal, gb.focal, omp, op, pool, nthr, multires)
+                    done += 1
+                    if time.perf_counter() - t_c > 10:
+                        break
+                dt = time.perf_counter() - t_c
+                cpu_threads["multires" if multires else "plain"] = {
+                    "value": round(npx * done / dt / 1e6, 4), "frames": done, "seconds": round(dt, 2)}
+        log(f"[bench] cpu oracle on {nthr} threads: {cpu_threads}")
 
     res = {
         "metric": "Mpixels/s multi-res vs full-res SSAO at 4K (HBM %); p50/p99 frame latency",
@@ -392,7 +618,11 @@ def main():
         "roofline": roofline,
         "variants": variants,
         "batched_ssgi": batched,
+        "sweeps": sweeps,
+        "pcss_4k": pcss,
+        "serving": serving_res,
         "cpu_baseline": cpu,
+        "cpu_baseline_threads": cpu_threads,
     }
     print(json.dumps(res), flush=True)
 
