@@ -338,6 +338,28 @@ MR_API int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, cons
  * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */
 MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream);
 
+/* A frame whose mask pyramid stays resident in caller memory across frames
+ * (serving a static scene: the masks of Sec. 3.1 depend only on the
+ * G-buffer, so requests after the first skip the mask kernels).  Compact
+ * frame path only (coarsest level <= 4, width divisible by 128, blur radii
+ * <= 8), else MR_E_PARAM.
+ * mr_pyramid_bytes: sizes of the pyramid (edge and stencil bits, ranks, work
+ * lists, counts, point-sampled level depth) and of the per-frame scratch.
+ * mr_frame_cached: build = 1 computes the masks of d's inputs into `pyramid`,
+ * then evaluates and merges as mr_frame does; build = 0 evaluates and merges
+ * on the masks already in `pyramid`, which must come from an earlier call
+ * with build = 1 on the same G-buffer contents, camera, mask parameters and
+ * effect (and, for soft shadows, the same shadow inputs) -- the library
+ * cannot check this.  The image is bit-identical to mr_frame's.  ws holds
+ * the frame's scratch (at least the scratch size).  Frames that read one
+ * pyramid may run concurrently; a build must be ordered before them.  The
+ * stage events of d are recorded as in mr_frame (the mask stage is empty
+ * when build = 0). */
+MR_API int mr_pyramid_bytes(const mr_camera* cam, const mr_mask_params* mp, int effect, size_t* pyramid,
+                            size_t* scratch);
+MR_API int mr_frame_cached(const mr_frame_desc* d, void* pyramid, size_t pyramid_bytes, int build, void* ws,
+                           size_t ws_bytes, void* stream);
+
 /* mr_frame for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same frame with the workspace taken from a static device array of

@@ -326,12 +326,21 @@ bool lean_ok(const Geo& g, const mr_mask_params* mp) {
 }
 
 
+// The compact layout in two parts.  The mask pyramid (counts, tile totals,
+// edge and stencil bits, ranks, work lists and point-sampled level depth)
+// depends only on the frame's inputs; the scratch part (a_i and sub-image
+// values by rank, the coarsest level, hard-shadow bits, blurred values) is
+// rewritten by every frame.  Offsets of the pyramid fields are from the
+// pyramid's base, those of the scratch fields from the scratch's base;
+// mr_frame places the scratch right after the pyramid.
 struct LeanLayout {
-    size_t count = 0, tot = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, ac[3] = {}, cc[3] = {};
-    size_t zi[kMaxLevels] = {}, cL = 0, hard = 0;
+    size_t count = 0, tot = 0, Eb[3] = {}, Sb[3] = {}, woff[3] = {}, list[3] = {}, zi[kMaxLevels] = {};
+    size_t pyramid = 0;  // bytes of the pyramid part
+    size_t ac[3] = {}, cc[3] = {}, cL = 0, hard = 0;
     size_t bc[3] = {}, bL = 0;  // SSAO: bilaterally blurred values
+    size_t scratch = 0;  // bytes of the scratch part
     unsigned nblk = 0;
-    size_t bytes = 0;
+    size_t bytes = 0;    // pyramid + scratch
 };
 
 LeanLayout lean_layout(const Geo& g, int effect) {
@@ -354,12 +363,18 @@ LeanLayout lean_layout(const Geo& g, int effect) {
         f.Sb[i - 1] = take(4 * words);
         f.woff[i - 1] = take(4 * words);
         f.list[i - 1] = take(4 * n);
-        f.ac[i - 1] = take(4 * n);
-        f.cc[i - 1] = take(4 * n * C);
     }
     for (int j = 0; j < g.nlev; ++j) {
         const int i = g.levels[j];
         if (i >= 2) f.zi[i - 1] = take(4 * (size_t)g.n(i));
+    }
+    f.pyramid = off;
+    off = 0;
+    for (int j = 0; j + 1 < g.nlev; ++j) {
+        const int i = g.levels[j];
+        const size_t n = (size_t)g.n(i);
+        f.ac[i - 1] = take(4 * n);
+        f.cc[i - 1] = take(4 * n * C);
     }
     f.cL = take(4 * (size_t)g.n(g.L) * C);
     if (effect == MR_EFFECT_SHADOW) f.hard = take((size_t)g.W * g.H);
@@ -370,7 +385,8 @@ LeanLayout lean_layout(const Geo& g, int effect) {
         }
         f.bL = take(4 * (size_t)g.n(g.L));
     }
-    f.bytes = off;
+    f.scratch = off;
+    f.bytes = f.pyramid + f.scratch;
     return f;
 }
 
@@ -726,10 +742,12 @@ struct LeanPlan {
     LeanMergeArgs ma{};
 };
 
-void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, LeanPlan& P) {
+// pyr: the mask pyramid; scr: the frame's scratch (see LeanLayout)
+void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* pyr, uint8_t* scr, LeanPlan& P) {
     const int effect = d->effect;
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
     const LeanLayout f = lean_layout(g, effect);
+    uint8_t* const b = pyr;
     uint32_t* count = reinterpret_cast<uint32_t*>(b + f.count);
     const uint8_t* hard = nullptr;
     if (effect == MR_EFFECT_SHADOW) {
@@ -743,9 +761,9 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         memcpy(ha.M, d->shadow->view_to_light, sizeof(ha.M));
         ha.fL = d->shadow->light_focal_px;
         ha.bias = d->shadow->bias;
-        ha.hard = b + f.hard;
+        ha.hard = scr + f.hard;
         P.has_hard = true;
-        hard = b + f.hard;
+        hard = scr + f.hard;
     }
     // edges as bits, point-sampled level depth
     EdgeArgs& ea = P.ea;
@@ -787,7 +805,7 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         L.Sb = reinterpret_cast<uint32_t*>(b + f.Sb[i - 1]);
         L.woff = reinterpret_cast<uint32_t*>(b + f.woff[i - 1]);
         L.list = reinterpret_cast<uint32_t*>(b + f.list[i - 1]);
-        L.ac = reinterpret_cast<float*>(b + f.ac[i - 1]);
+        L.ac = reinterpret_cast<float*>(scr + f.ac[i - 1]);
         L.W = g.Wi[i - 1];
         L.H = g.Hi[i - 1];
         L.wpr = L.W / 32;
@@ -823,9 +841,9 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         if (i >= 2) m.level_depth[i - 1] = reinterpret_cast<float*>(b + f.zi[i - 1]);
         if (i < g.L) {
             m.worklist[i - 1] = reinterpret_cast<uint32_t*>(b + f.list[i - 1]);
-            lo[i - 1] = reinterpret_cast<float*>(b + f.cc[i - 1]);
+            lo[i - 1] = reinterpret_cast<float*>(scr + f.cc[i - 1]);
         } else {
-            lo[i - 1] = reinterpret_cast<float*>(b + f.cL);
+            lo[i - 1] = reinterpret_cast<float*>(scr + f.cL);
         }
     }
     build_eval(effect, &d->g, &d->cam, g, &m, params, lo, /*compact=*/true, &la, d->level_dtype == MR_F16, P.ev);
@@ -849,7 +867,7 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
             BilateralLevel& B = bl.lv[bl.nlev++];
             B.z = i == 1 ? d->g.depth : reinterpret_cast<const float*>(b + f.zi[i - 1]);
             B.c = lo[i - 1];
-            B.out = b + (i < g.L ? f.bc[i - 1] : f.bL);
+            B.out = scr + (i < g.L ? f.bc[i - 1] : f.bL);
             B.W = g.Wi[i - 1];
             B.H = g.Hi[i - 1];
             B.dense_n = (unsigned)g.n(i);
@@ -901,14 +919,20 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
     }
 }
 
-int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* b, hipStream_t s) {
+// build = false: the pyramid already holds this frame's masks; the mask
+// kernels are skipped
+int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_t* pyr, uint8_t* scr, bool build,
+                  hipStream_t s) {
     LeanPlan P;
-    build_lean(d, g, params, b, P);
+    build_lean(d, g, params, pyr, scr, P);
     int st = mark(d, 0, s);
     if (st) return st;
-    if (P.has_hard && launch_hard(P.ha, s) != hipSuccess) return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
-    if (launch_edges(P.ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
-    if (launch_lean_masks(P.la, s) != hipSuccess) return fail(MR_E_DEVICE, "lean mask kernels launch failed");
+    if (build) {
+        if (P.has_hard && launch_hard(P.ha, s) != hipSuccess)
+            return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
+        if (launch_edges(P.ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
+        if (launch_lean_masks(P.la, s) != hipSuccess) return fail(MR_E_DEVICE, "lean mask kernels launch failed");
+    }
     if (P.has_map && launch_lean_level_map(P.lm, s) != hipSuccess)
         return fail(MR_E_DEVICE, "level map kernel launch failed");
     if ((st = mark(d, 1, s))) return st;
@@ -1260,7 +1284,10 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
     const size_t need = path_only ? (lean ? lean_bytes : f.bytes) : (f.bytes > lean_bytes ? f.bytes : lean_bytes);
     if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
-    if (lean) return do_frame_lean(d, g, params, static_cast<uint8_t*>(ws), s);
+    if (lean) {
+        uint8_t* b = static_cast<uint8_t*>(ws);
+        return do_frame_lean(d, g, params, b, b + lean_layout(g, effect).pyramid, true, s);
+    }
     if (d->level_dtype == MR_F16)
         return fail(MR_E_DTYPE, "f16 sub-image storage needs the compact frame path (coarsest level <= 4, width "
                                 "divisible by 128, blur radii <= 8 with positive taps)");
@@ -1311,6 +1338,56 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
 
 int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     return frame_run(d, ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+}
+
+int mr_pyramid_bytes(const mr_camera* cam, const mr_mask_params* mp, int effect, size_t* pyramid, size_t* scratch) {
+    if (!cam || !mp || !pyramid || !scratch) return fail(MR_E_NULL, "an argument is NULL");
+    if (effect != MR_EFFECT_SSAO && effect != MR_EFFECT_SHADOW && effect != MR_EFFECT_SSGI)
+        return fail(MR_E_PARAM, "unknown effect %d", effect);
+    Geo g;
+    int st = check_geo(cam, mp, g);
+    if (!st) st = check_mask_params(mp, g);
+    if (st) return st;
+    if (!lean_ok(g, mp))
+        return fail(MR_E_PARAM, "the compact frame path does not apply (coarsest level <= 4, width divisible by 128, "
+                                "blur radii <= 8)");
+    const LeanLayout f = lean_layout(g, effect);
+    *pyramid = f.pyramid;
+    *scratch = f.scratch;
+    return MR_OK;
+}
+
+int mr_frame_cached(const mr_frame_desc* d, void* pyramid, size_t pyramid_bytes, int build, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int effect = d->effect;
+    int st = check_effect_params(effect, d->ssao, d->shadow, d->ssgi);
+    if (st) return st;
+    const void* params = effect == MR_EFFECT_SSAO ? (const void*)d->ssao
+                         : effect == MR_EFFECT_SHADOW ? (const void*)d->shadow : (const void*)d->ssgi;
+    if (!d->multires) return fail(MR_E_PARAM, "a cached mask pyramid needs multires = 1");
+    if (build != 0 && build != 1) return fail(MR_E_PARAM, "build %d is neither 0 nor 1", build);
+    if (!d->out) return fail(MR_E_NULL, "out is NULL");
+    if (misaligned(d->out)) return fail(MR_E_PARAM, "out is not 16-byte aligned");
+    if (d->level_dtype != MR_F32 && d->level_dtype != MR_F16)
+        return fail(MR_E_DTYPE, "level_dtype %d is neither MR_F32 nor MR_F16", d->level_dtype);
+    Geo g;
+    st = check_geo(&d->cam, &d->mp, g);
+    if (!st) st = check_mask_params(&d->mp, g);
+    if (!st) st = check_gbuffer(&d->g, true, effect == MR_EFFECT_SSGI);
+    if (st) return st;
+    if (d->level_map && misaligned(d->level_map)) return fail(MR_E_PARAM, "level_map is not 16-byte aligned");
+    if ((st = check_bilateral(d, g))) return st;
+    if (!lean_ok(g, &d->mp))
+        return fail(MR_E_PARAM, "the compact frame path does not apply (coarsest level <= 4, width divisible by 128, "
+                                "blur radii <= 8)");
+    const LeanLayout f = lean_layout(g, effect);
+    if (!pyramid || pyramid_bytes < f.pyramid)
+        return fail(MR_E_WORKSPACE, "pyramid %zu bytes < %zu needed", pyramid_bytes, f.pyramid);
+    if (!ws || ws_bytes < f.scratch) return fail(MR_E_WORKSPACE, "scratch %zu bytes < %zu needed", ws_bytes, f.scratch);
+    if (misaligned(pyramid) || misaligned(ws)) return fail(MR_E_PARAM, "pyramid or scratch is not 16-byte aligned");
+    return do_frame_lean(d, g, params, static_cast<uint8_t*>(pyramid), static_cast<uint8_t*>(ws), build != 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1441,7 +1518,7 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
         const mr_frame_desc& d = frames[k];
         const void* params = effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
         LeanPlan L;
-        build_lean(&d, geos[k], params, b + BL.frames[k], L);
+        build_lean(&d, geos[k], params, b + BL.frames[k], b + BL.frames[k] + lean_layout(geos[k], effect).pyramid, L);
         te[k] = L.ea;
         tl[k] = L.la;
         if (effect == MR_EFFECT_SSAO)

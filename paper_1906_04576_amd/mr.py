@@ -152,6 +152,10 @@ SIGNATURES = {
     "mr_frame_workspace_layout": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                                  ctypes.c_int, ctypes.POINTER(mr_frame_layout)]),
     "mr_frame_static": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P]),
+    "mr_pyramid_bytes": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "mr_frame_cached": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P, ctypes.c_size_t, ctypes.c_int, _P,
+                                       ctypes.c_size_t, _P]),
     "mr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mr_last_error": (ctypes.c_char_p, []),
     "mr_version": (ctypes.c_int, []),
@@ -543,7 +547,8 @@ class FrameRunner:
     once so that repeated calls cost one ctypes call each."""
 
     def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
-                 out=None, level_map=None, workspace=None, level_dtype=torch.float32, bilateral: Bilateral = None):
+                 out=None, level_map=None, workspace=None, level_dtype=torch.float32, bilateral: Bilateral = None,
+                 ws_bytes=None):
         self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         H, W = depth.shape
         C = 3 if self.effect == MR_EFFECT_SSGI else 1
@@ -569,7 +574,7 @@ class FrameRunner:
             d.bilateral = bilateral.c()
         self.desc = d
         self._keep = (depth, normal, color, level_map)
-        nws = mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0
+        nws = ws_bytes if ws_bytes is not None else (mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0)
         if workspace is not None and workspace.numel() >= nws:
             self.workspace = workspace
         else:
@@ -646,6 +651,44 @@ def mr_frame_workspace_layout(cam: mr_camera, cmp: mr_mask_params, effect) -> mr
     lay = mr_frame_layout()
     _check(lib().mr_frame_workspace_layout(ctypes.byref(cam), ctypes.byref(cmp), int(effect), ctypes.byref(lay)))
     return lay
+
+
+def mr_pyramid_bytes(W, H, focal, mp: MaskParams, effect) -> tuple:
+    """(pyramid bytes, scratch bytes) of a frame with a resident pyramid."""
+    cam, cmp = camera(W, H, focal), mp.c()
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mr_pyramid_bytes(ctypes.byref(cam), ctypes.byref(cmp), int(effect), ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+class CachedFrameRunner(FrameRunner):
+    """mr_frame_cached: the frame with its mask pyramid in `pyramid` (a
+    device tensor of at least the pyramid size, kept by the caller across
+    frames of the same inputs).  call(build=True) computes the masks into
+    it, call(build=False) reuses them."""
+
+    def __init__(self, effect, depth, normal, focal, mp: MaskParams, pyramid, color=None, params=None, out=None,
+                 level_map=None, workspace=None, level_dtype=torch.float32, bilateral: Bilateral = None):
+        eff = EFFECTS[effect] if isinstance(effect, str) else int(effect)
+        H, W = depth.shape
+        npyr, nscr = mr_pyramid_bytes(W, H, focal, mp, eff)
+        if pyramid.numel() < npyr:
+            raise ValueError(f"pyramid needs {npyr} bytes")
+        super().__init__(effect, depth, normal, focal, mp, True, color, params, out, level_map, workspace=workspace,
+                         level_dtype=level_dtype, bilateral=bilateral, ws_bytes=nscr)
+        self.pyramid = pyramid
+        self._pyr = _ptr(pyramid)
+        self._npyr = pyramid.numel()
+        self._cfn = lib().mr_frame_cached
+
+    def __call__(self, stream=None, build=True):
+        if stream is not None and stream != torch.cuda.current_stream():
+            self.workspace.record_stream(stream)
+            self.out.record_stream(stream)
+            self.pyramid.record_stream(stream)
+        _check(self._cfn(ctypes.byref(self.desc), self._pyr, self._npyr, 1 if build else 0, self._ws, self._nws,
+                         _stream(stream)))
+        return self.out
 
 
 class StaticFrameRunner(FrameRunner):

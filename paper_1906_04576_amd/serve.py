@@ -2,12 +2,15 @@
 
 Requests (a resident seeded scene at some resolution, one of the three
 effects) arrive as a Poisson stream.  A request is admitted as soon as one of
-the slots is free and its working memory (workspace and output) fits the HBM
-budget next to the requests in flight; each slot is a HIP stream with its own
-workspace, so admitted requests overlap on the device while others keep
-arriving.  Latency is completion minus arrival, throughput the pixels
-finished per second of wall time.  Every frame goes through mr_frame; this
-module only schedules.
+the slots is free and its working memory (scratch and output) fits the HBM
+budget next to the requests in flight and the resident data; each slot is a
+HIP stream with its own scratch, so admitted requests overlap on the device
+while others keep arriving.  The scenes' G-buffers stay resident, and so do
+their mask pyramids: the first request for a (scene, effect) pair builds the
+pyramid (mr_frame_cached with build = 1), later ones evaluate and merge on
+it (build = 0, after the build's completion on the device).  Latency is
+completion minus arrival, throughput the pixels finished per second of wall
+time.  This module only schedules; every frame runs in the library.
 
     python -m paper_1906_04576_amd.serve --qps 4000 --seconds 2
 prints one JSON line with p50/p99 latency and Mpixels/s, multi-resolution
@@ -34,7 +37,8 @@ EFFECTS = ("ssao", "shadow", "ssgi")
 
 @dataclass
 class Scene:
-    """Resident inputs of one seeded scene at one resolution."""
+    """Resident inputs of one seeded scene at one resolution (and their host
+    copies, for checking results)."""
     W: int
     H: int
     focal: float
@@ -43,6 +47,15 @@ class Scene:
     color: torch.Tensor
     shadow: mr.mr_shadow_params
     bytes: int
+    host: dict = None
+
+
+@dataclass
+class Pyramid:
+    """Resident mask pyramid of one (scene, effect) pair."""
+    mem: torch.Tensor
+    built: bool = False
+    ready: torch.cuda.Event = None  # completion of the request that built it
 
 
 @dataclass
@@ -95,18 +108,54 @@ class Pool:
                                       bd, pd)
                 nbytes = sum(t.numel() * t.element_size() for t in (d, n, c, sm))
                 self.res_index.setdefault((W, H), []).append(len(self.scenes))
-                self.scenes.append(Scene(W, H, float(gb.focal), d, n, c, sp, nbytes))
+                self.scenes.append(Scene(W, H, float(gb.focal), d, n, c, sp, nbytes,
+                                         host={"gb": gb, "shadow": si, "color": col}))
         self.mp = {e: _mask_params(e) for e in EFFECTS}
         self.ssao = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(32)).to(device), 1.0, 0.02)
         self.ssgi = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(64)).to(device), 2.0, 0.02)
+        self.pyramids: dict[tuple, Pyramid] = {}
+        self._compact: dict[tuple, bool] = {}
+
+    def resident_bytes(self) -> int:
+        return sum(sc.bytes for sc in self.scenes) + sum(p.mem.numel() for p in self.pyramids.values())
+
+    def pyramid_bytes(self, scene: int, effect: str) -> int:
+        sc = self.scenes[scene]
+        return mr.mr_pyramid_bytes(sc.W, sc.H, sc.focal, self.mp[effect], mr.EFFECTS[effect])[0]
+
+    def pyramid(self, scene: int, effect: str) -> Pyramid:
+        key = (scene, effect)
+        if key not in self.pyramids:
+            self.pyramids[key] = Pyramid(torch.empty(self.pyramid_bytes(scene, effect), dtype=torch.uint8,
+                                                     device=self.device))
+        return self.pyramids[key]
+
+    def scratch_bytes(self) -> int:
+        """Per-frame memory when pyramids stay resident: the scratch of a
+        compact frame, the whole workspace of any other; the largest over the
+        resident resolutions and the effects."""
+        return max(mr.mr_pyramid_bytes(sc.W, sc.H, sc.focal, self.mp[e], mr.EFFECTS[e])[1]
+                   if self.compact(k, e) else mr.mr_workspace_bytes(sc.W, sc.H, sc.focal, self.mp[e], mr.EFFECTS[e])
+                   for k, sc in enumerate(self.scenes) for e in EFFECTS)
 
     def params(self, effect: str, scene: Scene):
         return {"ssao": self.ssao, "shadow": scene.shadow, "ssgi": self.ssgi}[effect]
 
     def workspace_bytes(self) -> int:
-        W, H = max(RESOLUTIONS, key=lambda r: r[0] * r[1])
-        f = self.scenes[0].focal
-        return max(mr.mr_workspace_bytes(W, H, f, self.mp[e], mr.EFFECTS[e]) for e in EFFECTS)
+        """Workspace of a frame that builds its own masks: the largest over
+        the resident resolutions and the effects."""
+        return max(mr.mr_workspace_bytes(sc.W, sc.H, sc.focal, self.mp[e], mr.EFFECTS[e])
+                   for sc in self.scenes for e in EFFECTS)
+
+    def compact(self, scene: int, effect: str) -> bool:
+        """Whether the scene's frames take the compact path, the one whose
+        mask pyramid can stay resident."""
+        key = (scene, effect)
+        if key not in self._compact:
+            sc = self.scenes[scene]
+            self._compact[key] = mr.mr_frame_workspace_layout(mr.camera(sc.W, sc.H, sc.focal), self.mp[effect].c(),
+                                                              mr.EFFECTS[effect]).compact == 1
+        return self._compact[key]
 
 
 def poisson_requests(pool: Pool, qps: float, seconds: float, seed: int = 7) -> list[Request]:
@@ -134,10 +183,11 @@ class Server:
     budget for the working memory of the requests in flight."""
 
     def __init__(self, pool: Pool, slots: int = 4, budget_bytes: int = 64 << 30, multires: bool = True,
-                 level_dtype=torch.float32, keep_outputs: bool = False):
+                 level_dtype=torch.float32, keep_outputs: bool = False, resident_masks: bool = True):
         self.pool, self.multires, self.level_dtype, self.keep = pool, multires, level_dtype, keep_outputs
+        self.cached = multires and resident_masks
         self.budget = budget_bytes
-        ws = pool.workspace_bytes() if multires else 256
+        ws = (pool.scratch_bytes() if self.cached else pool.workspace_bytes()) if multires else 256
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.ws = [torch.empty(ws, dtype=torch.uint8, device=pool.device) for _ in range(slots)]
         self.ws_bytes = ws
@@ -149,13 +199,27 @@ class Server:
         with torch.cuda.stream(st):
             out = torch.empty((C, sc.H, sc.W) if C > 1 else (sc.H, sc.W), dtype=torch.float32,
                               device=self.pool.device)
-        fr = mr.FrameRunner(req.effect, sc.depth, sc.normal, sc.focal, self.pool.mp[req.effect], self.multires,
-                            color=sc.color if req.effect == "ssgi" else None,
-                            params=self.pool.params(req.effect, sc), out=out, workspace=self.ws[slot],
-                            level_dtype=self.level_dtype)
-        fr(st)
+        color = sc.color if req.effect == "ssgi" else None
+        params = self.pool.params(req.effect, sc)
+        cached = self.cached and self.pool.compact(req.scene, req.effect)
+        if cached:
+            pyr = self.pool.pyramid(req.scene, req.effect)
+            build = not pyr.built
+            if not build and pyr.ready is not None:
+                st.wait_event(pyr.ready)  # the build may still run on another slot
+            fr = mr.CachedFrameRunner(req.effect, sc.depth, sc.normal, sc.focal, self.pool.mp[req.effect], pyr.mem,
+                                      color=color, params=params, out=out, workspace=self.ws[slot],
+                                      level_dtype=self.level_dtype)
+            fr(st, build=build)
+        else:
+            fr = mr.FrameRunner(req.effect, sc.depth, sc.normal, sc.focal, self.pool.mp[req.effect], self.multires,
+                                color=color, params=params, out=out, workspace=self.ws[slot],
+                                level_dtype=self.level_dtype)
+            fr(st)
         ev = torch.cuda.Event()
         ev.record(st)
+        if cached and build:
+            pyr.built, pyr.ready = True, ev
         return out, ev, out.numel() * 4 + self.ws_bytes
 
     def run(self, reqs: list[Request], realtime: bool = True) -> list[Done]:
@@ -184,7 +248,10 @@ class Server:
                 req = pending[0]
                 sc = self.pool.scenes[req.scene]
                 need = (3 if req.effect == "ssgi" else 1) * sc.W * sc.H * 4 + self.ws_bytes
-                if used + need > self.budget and inflight:
+                if self.cached and (req.scene, req.effect) not in self.pool.pyramids and \
+                        self.pool.compact(req.scene, req.effect):
+                    need += self.pool.pyramid_bytes(req.scene, req.effect)  # becomes resident
+                if used + need + self.pool.resident_bytes() > self.budget and inflight:
                     break  # admitted when memory frees up
                 pending.pop(0)
                 slot = free.pop(0)
@@ -216,15 +283,16 @@ def main(argv=None):
     print(f"[serve] {len(pool.scenes)} resident scenes in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     reqs = poisson_requests(pool, args.qps, args.seconds)
     res = {"qps": args.qps, "seconds": args.seconds, "slots": args.slots, "budget_gb": args.budget_gb}
-    for multires in (True, False):
-        srv = Server(pool, args.slots, int(args.budget_gb * (1 << 30)), multires)
-        srv.run(reqs[: min(len(reqs), 64)])  # warm-up
+    for name, multires, resident in (("multires", True, True), ("multires_rebuild", True, False),
+                                     ("plain", False, False)):
+        srv = Server(pool, args.slots, int(args.budget_gb * (1 << 30)), multires, resident_masks=resident)
+        srv.run(reqs[: min(len(reqs), 64)])  # warm-up (builds the resident pyramids)
         s = summary(srv.run(reqs))
         # the same requests admitted back to back: the loop's capacity
         sat = summary(srv.run(reqs, realtime=False))
         s["saturated_mpixels_s"] = sat["mpixels_s"]
-        res["multires" if multires else "plain"] = s
-        print(f"[serve] {'multi-res' if multires else 'plain'}: {s}", file=sys.stderr, flush=True)
+        res[name] = s
+        print(f"[serve] {name}: {s}", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 

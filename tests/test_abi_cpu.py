@@ -200,6 +200,32 @@ def test_frame_workspace_layout_on_the_host():
         mr.mr_frame_workspace_layout(mr.camera(0, 120, 100.0), mp.c(), mr.MR_EFFECT_SSAO)
 
 
+def test_pyramid_and_scratch_sizes_on_the_host():
+    """mr_pyramid_bytes (host call, no GPU): the resident pyramid holds every
+    list, stencil-bit and rank region of the compact layout, pyramid plus
+    scratch fit the frame's workspace, soft shadows need more scratch (the
+    hard-shadow bytes), and parameters off the compact path are refused."""
+    mp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=(0.924, 1.848, 3.696, 0.0),
+                       weight=(100.0, 50.0, 20.0, 1.0))
+    for W, H in ((3840, 2160), (384, 256)):
+        cam = mr.camera(W, H, 100.0)
+        npyr, nscr = mr.mr_pyramid_bytes(W, H, 100.0, mp, mr.MR_EFFECT_SSAO)
+        assert npyr > 0 and nscr > 0
+        assert npyr + nscr <= mr.mr_workspace_bytes(W, H, 100.0, mp, mr.MR_EFFECT_SSAO)
+        lay = mr.mr_frame_workspace_layout(cam, mp.c(), mr.MR_EFFECT_SSAO)
+        for i in (1, 2, 3):
+            Wi, Hi = W >> (i - 1), H >> (i - 1)
+            assert lay.worklist[i - 1] + 4 * Wi * Hi <= npyr
+            assert lay.stencil_bits[i - 1] + 4 * (Wi // 32) * Hi <= npyr
+            assert lay.rank[i - 1] + 4 * (Wi // 32) * Hi <= npyr
+        sp, ss = mr.mr_pyramid_bytes(W, H, 100.0, mp, mr.MR_EFFECT_SHADOW)
+        assert sp == npyr and ss >= W * H
+    with pytest.raises(mr.MRError):
+        mr.mr_pyramid_bytes(200, 120, 100.0, mp, mr.MR_EFFECT_SSAO)  # width not divisible by 128
+    with pytest.raises(mr.MRError):
+        mr.mr_pyramid_bytes(384, 256, 100.0, mp, 7)
+
+
 def test_frame_on_another_stream_holds_its_memory(monkeypatch):
     """A frame enqueued on a stream other than the current one records that
     stream on its workspace and output (torch's caching allocator then keeps

@@ -1,13 +1,18 @@
-"""The continuous-batching request loop: every request's frame is the same
-bit for bit alone and in a mix of overlapping requests (other effects and
+"""The continuous-batching request loop: a served request of each effect is
+the oracle's frame (both the request that builds the scene's resident mask
+pyramid and one that reuses it), every request's frame is the same bit for
+bit alone and in a mix of overlapping requests (other effects and
 resolutions on other streams), the HBM budget limits what is in flight, and
 the latency/throughput summary is well formed."""
+import math
 import sys
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
+import scenegen
 from paper_1906_04576_amd import serve
 
 pytestmark = pytest.mark.gpu
@@ -24,6 +29,42 @@ def pool():
     if not _pool:
         _pool["p"] = serve.Pool(scenes_per_res=1, resolutions=((384, 256), (640, 360)), shadow_map=512)
     return _pool["p"]
+
+
+def oracle_frame(p, scene, effect):
+    sc = p.scenes[scene]
+    gb = sc.host["gb"]
+    mp = p.mp[effect]
+    omp = oracle.MaskParams(num_levels=mp.num_levels, level_enable=mp.level_enable, depth_ratio=mp.depth_ratio,
+                            normal_cos=float(np.float32(mp.normal_cos)), sigma2=mp.sigma2, weight=mp.weight)
+    if effect == "shadow":
+        si = sc.host["shadow"]
+        op = oracle.ShadowParams(si.shadow_map, si.view_to_light, si.light_focal, si.light_size, si.light_near,
+                                 np.float32(0.05), scenegen.disk_samples(16, 11), scenegen.disk_samples(32, 12))
+    elif effect == "ssao":
+        op = oracle.SSAOParams(scenegen.ssao_kernel(32), 1.0, 0.02)
+    else:
+        op = oracle.SSGIParams(scenegen.ssao_kernel(64), 2.0, 0.02)
+    return oracle.frame(effect, gb.depth, gb.normal, gb.focal, omp, op,
+                        color=sc.host["color"] if effect == "ssgi" else None).out
+
+
+@pytest.mark.parametrize("effect", serve.EFFECTS)
+def test_served_requests_match_the_oracle(effect):
+    p = pool()
+    scene = p.res_index[(384, 256)][0]
+    assert p.compact(scene, effect)
+    p.pyramids.pop((scene, effect), None)
+    reqs = [serve.Request(0, 0.0, effect, scene), serve.Request(1, 0.0, effect, scene)]
+    log(f"[gpu] served {effect} scene {scene}: build, then reuse on another slot")
+    done = serve.Server(p, slots=2, keep_outputs=True).run(reqs, realtime=False)
+    assert p.pyramids[(scene, effect)].built
+    ref = oracle_frame(p, scene, effect)
+    for d in done:
+        got = d.out.cpu().numpy()
+        assert got.shape == ref.shape
+        assert np.abs(got - ref).max() <= 1e-4
+        assert np.array_equal(got, ref), d.rid
 
 
 def test_results_identical_alone_and_in_the_mix():
