@@ -43,14 +43,15 @@ FP32_PIPE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 SSAO_FP32_PER_SAMPLE = 28
 SSAO_FP32_PER_TEXEL = 31
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
-# WRITE_SIZE counters (profiles/), scaled by the copy-kernel calibration;
-# None until measured for the current kernel
-TRAFFIC_BYTES = {"k_ssao_multi": None}
+# WRITE_SIZE counters (profiles/ssao_4k_hbm_counters.md), scaled by the
+# copy-kernel calibration; None once the kernel changes, until re-measured
+TRAFFIC_BYTES = {"k_ssao_multi": 61880025}
 # VALU issue of the dominant kernel from the SQ_INSTS_VALU_* counters
-# (profiles/): wave instructions per launch of the FP32 arithmetic classes
-# (add, multiply, FMA, transcendental, conversion; 4 cycles per wave64
-# instruction) and of all other VALU instructions (2 cycles)
-VALU_ISSUE = {"k_ssao_multi": None}
+# (profiles/ssao_4k_eval_valu_issue.md): wave instructions per launch of the
+# FP32 arithmetic classes (add, multiply, FMA, transcendental, conversion; 4
+# cycles per wave64 instruction) and of all other VALU instructions (2
+# cycles); None once the kernel changes, until re-measured
+VALU_ISSUE = {"k_ssao_multi": {"fp32_arith": 12909635, "other": 8422348}}
 
 
 def log(*a):
