@@ -39,9 +39,12 @@
  *  - Every call validates all arguments before it enqueues anything; on
  *    error it returns a negative MR_E_* code, enqueues nothing, leaves the
  *    outputs untouched and sets a thread-local message (mr_last_error).
- *  - Calls are re-entrant: the library has no mutable global state besides
- *    the thread-local error message.  Calls that share output or workspace
- *    memory must be ordered by the caller (same stream or events).
+ *  - Calls are re-entrant.  Besides the thread-local error message the
+ *    library keeps only per-device facts, each set on its first use on that
+ *    device and read-only afterwards: the compute-unit count, kernels'
+ *    resident-block counts and the address of the static scratch
+ *    (mr_frame_static).  Calls that share output or workspace memory must be
+ *    ordered by the caller (same stream or events).
  *  - Floating point: IEEE binary32, round to nearest even, no fused
  *    multiply-add, correctly rounded division and square root, denormals
  *    kept; results are deterministic run to run.

@@ -2,6 +2,7 @@
 // mapping of a flat item index onto (level, texel) over the work lists and
 // the dense coarsest level, and the view-space position of a texel.
 #pragma once
+#include <atomic>
 
 #include "mr_internal.hpp"
 #include "recip.hpp"
@@ -239,20 +240,43 @@ __host__ inline bool fused_alpha(const EvalCommon& c) {
     return false;
 }
 
-// Blocks of 256 threads of `Kernel` that are resident on the device at once
-// (CUs x blocks per CU at the kernel's occupancy), queried once per kernel.
+// per-device caches of device properties: filled on first use on each
+// device (with that device current), read-only afterwards; 0 = not yet
+// queried.  Concurrent first uses store the same value.
+constexpr int kMaxPropDevices = 64;
+
+__host__ inline int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxPropDevices) return -1;
+    return dev;
+}
+
+__host__ inline unsigned query_cus(int dev) {
+    int cus = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256u;
+    return (unsigned)cus;
+}
+
+// Blocks of 256 threads of `Kernel` that are resident on the current device
+// at once (CUs x blocks per CU at the kernel's occupancy), queried once per
+// kernel and device.
 template <auto Kernel>
 __host__ unsigned resident_blocks() {
-    static const unsigned n = [] {
-        int dev = 0, cus = 0, per = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(Kernel), 256, 0) !=
-                hipSuccess ||
-            cus <= 0 || per <= 0)
-            return 8192u;
-        return (unsigned)cus * (unsigned)per;
-    }();
+    static std::atomic<unsigned> cache[kMaxPropDevices];
+    const int dev = current_device();
+    if (dev >= 0) {
+        const unsigned v = cache[dev].load(std::memory_order_relaxed);
+        if (v) return v;
+    }
+    int per = 0;
+    unsigned n = 8192u;
+    if (dev >= 0 &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(Kernel), 256, 0) ==
+            hipSuccess &&
+        per > 0)
+        n = query_cus(dev) * (unsigned)per;
+    if (dev >= 0) cache[dev].store(n, std::memory_order_relaxed);
     return n;
 }
 
@@ -268,15 +292,17 @@ __host__ inline unsigned eval_blocks(unsigned total_hint) {
     return b;
 }
 
+// compute units of the current device, queried once per device
 __host__ inline unsigned cu_count() {
-    static const unsigned n = [] {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            return 256u;
-        return (unsigned)cus;
-    }();
-    return n;
+    static std::atomic<unsigned> cache[kMaxPropDevices];
+    const int dev = current_device();
+    if (dev < 0) return query_cus(dev);
+    unsigned v = cache[dev].load(std::memory_order_relaxed);
+    if (!v) {
+        v = query_cus(dev);
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 // eval_blocks capped at blocks_per_cu blocks on every CU (0: no cap)
