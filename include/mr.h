@@ -413,7 +413,8 @@ MR_API int mr_frame_workspace_layout(const mr_camera* cam, const mr_mask_params*
  * MR_EFFECT_SSGI) with identical mask and effect parameters and input types
  * but any sizes, processed with one launch per stage for all frames (edges,
  * ranks and work lists, per-level evaluation over one item space of all
- * frames by a resident grid, merge).  Every frame must take the compact path
+ * frames by a resident grid, merge), or in one persistent launch whose
+ * blocks take the stages' tiles from one queue (mr_batch_config).  Every frame must take the compact path
  * (coarsest level <= 4, width divisible by 128, blur radii <= 8), have
  * multires = 1, level_map = NULL and no bilateral blur; stage_events are not
  * recorded.
@@ -446,12 +447,35 @@ MR_API int mr_batch_run(const void* plan, void* stream);
  *                       as can be resident
  *   merge_generic       0: the four-level merge with fixed tap geometry
  *                          where it applies (levels 1..4 all enabled),
- *                       1: the general merge */
+ *                       1: the general merge
+ *   persistent          0: one launch per stage; 1: the whole batch in one
+ *                          launch of resident blocks that take tickets from
+ *                          one counter in stage order (every edge tile, then
+ *                          every ranking tile twice -- stencil, then list --,
+ *                          evaluation workers, merge tiles; frames in order
+ *                          within a stage), a ticket first waiting until the
+ *                          previous stage of its frame has finished.  Needs
+ *                          frames of at most 4 levels and at most 256
+ *                          samples (else MR_E_PARAM); edge_tile,
+ *                          eval_queue and eval_blocks_per_cu do not apply.
+ *   eval_items          persistent launch: texels per evaluation thread and
+ *                       chunk, 1, 2 or 4 (0: 1); the staged evaluation takes
+ *                       one (a loop over more cost it a wave per SIMD)
+ *   worker_pixels       persistent launch: one evaluation worker ticket per
+ *                       this many pixels of a frame (4096 .. 2^24; 0: 8192);
+ *                       a frame's workers share its chunks through per-XCD
+ *                       counters
+ *   tiles_per_ticket    persistent launch: edge and merge tiles per ticket
+ *                       (1 .. 64; 0: 16) */
 typedef struct mr_batch_config {
     int edge_tile;
     int eval_queue;
     int eval_blocks_per_cu;
     int merge_generic;
+    int persistent;
+    int eval_items;
+    int worker_pixels;
+    int tiles_per_ticket;
 } mr_batch_config;
 
 /* Read or replace a filled plan's configuration (MR_E_PARAM for a plan not
@@ -462,12 +486,23 @@ MR_API int mr_batch_set_config(void* plan, const mr_batch_config* cfg);
 
 /* Autotuner: times the batch (one warm-up run, then `reps` runs, 1..1000) on
  * `stream` under candidate configurations, one choice at a time (the
- * evaluation's schedule and grid cap first, then the edge tile shape, then
- * the merge kernel), keeps the fastest in the plan and, when best is not
- * NULL, in *best.  It runs the batch on its current inputs and waits for the
+ * evaluation's schedule and grid cap first, then the edge tile shape and
+ * the merge kernel, then the persistent launch with two worker sizes and
+ * one or two texels per evaluation thread and, if it is the faster, its
+ * tiles per ticket), keeps the
+ * fastest in the plan and, when best is not NULL, in *best.  It runs the batch on its current inputs and waits for the
  * stream: not for use under graph capture.  Outputs after it are those of a
  * plain run. */
 MR_API int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream);
+
+/* The persistent launch bounds every wait for another stage (it cannot
+ * deadlock: each ticket waits only for tickets taken earlier by running
+ * blocks); a wait that runs out of polls sets an error word in the
+ * workspace and the launch goes on, so it always ends.  mr_batch_check waits
+ * for `stream`, reads and clears that word, and returns MR_E_DEVICE if it
+ * was set (the outputs of the runs since the last check are then not
+ * valid), else MR_OK.  Not for use under graph capture. */
+MR_API int mr_batch_check(const void* plan, void* stream);
 
 
 /* Host helpers. */

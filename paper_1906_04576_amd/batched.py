@@ -82,13 +82,25 @@ def measure(steps=20, frames=None, device="cuda"):
         cfg = b.tune(reps=3, stream=st)
         t_tuned = _wall(lambda: b(st), steps)
     st.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=st):
-        b(st)
-    g.replay()
-    t_graph = _wall(g.replay, steps)
+
+    def graph_time(config):
+        b.config = config
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=st):
+            b(st)
+        gr.replay()
+        t = _wall(gr.replay, steps)
+        b.check(st)  # no wait of a persistent run gave up
+        return gr, t
+
+    # the staged launches and the persistent launch, each with the tuner's
+    # other choices, both replayed from graphs; the tuned one is kept
+    t_mode = {}
+    for mode in (0, 1):
+        _, t_mode[mode] = graph_time(dict(cfg, persistent=mode))
+    g, t_graph = graph_time(cfg)
     log(f"[batched] batch {t_default * 1e3:.3f} ms (default config), {t_tuned * 1e3:.3f} ms (tuned {cfg}), "
-        f"{t_graph * 1e3:.3f} ms (graph)")
+        f"{t_graph * 1e3:.3f} ms (graph); staged {t_mode[0] * 1e3:.3f} ms, persistent {t_mode[1] * 1e3:.3f} ms")
 
     # the same frames one after another (one workspace), and the naive pass
     nws = max(mr.mr_workspace_bytes(f["depth"].shape[1], f["depth"].shape[0], f["focal"], mp, mr.MR_EFFECT_SSGI)
@@ -123,6 +135,7 @@ def measure(steps=20, frames=None, device="cuda"):
         "batch_ms": round(t_graph * 1e3, 4), "mpixels_s": round(npx / t_graph / 1e6, 2),
         "batch_default_config_ms": round(t_default * 1e3, 4), "batch_tuned_eager_ms": round(t_tuned * 1e3, 4),
         "tuned_config": cfg,
+        "staged_graph_ms": round(t_mode[0] * 1e3, 4), "persistent_graph_ms": round(t_mode[1] * 1e3, 4),
         "sequential_ms": round(t_seq * 1e3, 4), "sequential_mpixels_s": round(npx / t_seq / 1e6, 2),
         "plain_ms": round(t_plain * 1e3, 4), "plain_mpixels_s": round(npx / t_plain / 1e6, 2),
         "speedup_vs_plain": round(t_plain / t_graph, 3), "speedup_vs_sequential": round(t_seq / t_graph, 3),

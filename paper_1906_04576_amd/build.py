@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmr.so")
 
-SOURCES = ["api.cpp", "k_masks.hip", "k_compact.hip", "k_ssao.hip", "k_shadow.hip", "k_ssgi.hip",
+SOURCES = ["api.cpp", "k_masks.hip", "k_compact.hip", "k_ssao.hip", "k_shadow.hip", "k_ssgi.hip", "k_fused.hip",
            "k_merge.hip",
            "k_lean.hip", "k_bilateral.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

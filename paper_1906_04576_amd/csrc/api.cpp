@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <limits>
 #include <vector>
 
 #include "mr_internal.hpp"
@@ -958,16 +959,28 @@ struct BatchPlan {
     const LeanArgs* tl;
     const void* tv;  // SsaoArgs or SsgiArgs
     const LeanMergeArgs* tm;
-    const unsigned *edge_base[2], *edge_tx[2], *rank_base, *merge_base, *merge_tx;
+    const unsigned *edge_base[2], *edge_tx[2], *rank_base, *merge_base, *merge_tx, *px;
     unsigned* queue;
+    unsigned* fused_ctr;
     unsigned edge_total[2], rank_total, eval_hint, merge_total;
 };
 static_assert(sizeof(BatchPlan) <= MR_BATCH_PLAN_BYTES, "batch plan exceeds MR_BATCH_PLAN_BYTES");
 
 // per-frame tables in the batch workspace: edge tile bases and tiles per row
 // for both edge tile shapes, rank block bases, merge tile bases and tiles per
-// row; then the evaluation's work-queue counters
-constexpr int kBatchTables = 7;
+// row, pixel counts; then the evaluation's work-queue counters and the
+// persistent launch's counters
+constexpr int kBatchTables = 8;
+// persistent launch defaults (the fastest measured on 24 uneven SSGI frames)
+constexpr int kDefaultWorkerPixels = 8192;
+constexpr int kDefaultTilesPerTicket = 16;
+// polls of a persistent-launch wait before it gives up (tens of ms or more;
+// a wait for another stage of the same frame normally lasts well under 1 ms)
+constexpr unsigned kFusedSpinLimit = 1u << 18;
+
+// the persistent launch: edge tiles of 256 x 8 pixels (at most 4 levels)
+// and at most kFusedSamples samples
+bool fused_ok(const BatchPlan& P) { return P.wide_ok && P.S <= kFusedSamples; }
 
 struct BatchLayout {
     size_t te, tl, tv, tm, bases, frames[MR_MAX_BATCH], bytes;
@@ -1023,7 +1036,7 @@ BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos) {
     L.tl = take(sizeof(LeanArgs) * n);
     L.tv = take((fr[0].effect == MR_EFFECT_SSAO ? sizeof(SsaoArgs) : sizeof(SsgiArgs)) * n);
     L.tm = take(sizeof(LeanMergeArgs) * n);
-    L.bases = take(sizeof(unsigned) * (kBatchTables * (MR_MAX_BATCH + 1) + kBatchCounters));
+    L.bases = take(sizeof(unsigned) * (kBatchTables * (MR_MAX_BATCH + 1) + kBatchCounters + kFusedCounters));
     for (int k = 0; k < n; ++k) L.frames[k] = take(lean_layout(geos[k], fr[k].effect).bytes);
     L.bytes = off;
     return L;
@@ -1037,18 +1050,57 @@ int load_plan(const void* plan, BatchPlan& P) {
     return MR_OK;
 }
 
-int check_config(const mr_batch_config& c) {
+int check_config(const BatchPlan& P, const mr_batch_config& c) {
     if (c.edge_tile != 0 && c.edge_tile != 1) return fail(MR_E_PARAM, "edge_tile %d not 0 or 1", c.edge_tile);
     if (c.eval_queue != 0 && c.eval_queue != 1) return fail(MR_E_PARAM, "eval_queue %d not 0 or 1", c.eval_queue);
     if (c.eval_blocks_per_cu < 0 || c.eval_blocks_per_cu > 64)
         return fail(MR_E_PARAM, "eval_blocks_per_cu %d outside [0, 64]", c.eval_blocks_per_cu);
     if (c.merge_generic != 0 && c.merge_generic != 1)
         return fail(MR_E_PARAM, "merge_generic %d not 0 or 1", c.merge_generic);
+    if (c.persistent != 0 && c.persistent != 1) return fail(MR_E_PARAM, "persistent %d not 0 or 1", c.persistent);
+    if (c.persistent && !fused_ok(P))
+        return fail(MR_E_PARAM, "the persistent launch needs frames of at most 4 levels and at most %d samples",
+                    kFusedSamples);
+    if (c.eval_items != 0 && c.eval_items != 1 && c.eval_items != 2 && c.eval_items != 4)
+        return fail(MR_E_PARAM, "eval_items %d not 0, 1, 2 or 4", c.eval_items);
+    if (c.worker_pixels != 0 && (c.worker_pixels < 4096 || c.worker_pixels > (1 << 24)))
+        return fail(MR_E_PARAM, "worker_pixels %d not 0 or in [4096, 2^24]", c.worker_pixels);
+    if (c.tiles_per_ticket < 0 || c.tiles_per_ticket > 64)
+        return fail(MR_E_PARAM, "tiles_per_ticket %d outside [0, 64]", c.tiles_per_ticket);
+    return MR_OK;
+}
+
+int run_fused(const BatchPlan& P, hipStream_t s) {
+    const mr_batch_config& c = P.cfg;
+    FusedArgs a{};
+    a.te = P.te;
+    a.tl = P.tl;
+    a.tv = P.tv;
+    a.tm = P.tm;
+    a.base[0] = P.edge_base[0];  // 256 x 8 tiles (fused_ok)
+    a.base[1] = P.rank_base;
+    a.base[2] = P.rank_base;
+    a.base[3] = nullptr;  // evaluation workers: from px in the kernel
+    a.base[4] = P.merge_base;
+    a.px = P.px;
+    a.edge_tx = P.edge_tx[0];
+    a.merge_tx = P.merge_tx;
+    a.worker_px = (unsigned)(c.worker_pixels ? c.worker_pixels : kDefaultWorkerPixels);
+    a.group = c.tiles_per_ticket ? c.tiles_per_ticket : kDefaultTilesPerTicket;
+    a.ctr = P.fused_ctr;
+    a.n = P.n;
+    a.wide = 1;
+    a.m4 = P.m4_ok && !c.merge_generic;
+    a.items = c.eval_items ? c.eval_items : 1;
+    a.spin_limit = kFusedSpinLimit;
+    if (launch_batch_fused(a, P.effect, P.S, P.ndt, P.cdt, nullptr, s) != hipSuccess)
+        return fail(MR_E_DEVICE, "persistent batch kernel launch failed");
     return MR_OK;
 }
 
 int run_plan(const BatchPlan& P, hipStream_t s) {
     const mr_batch_config& c = P.cfg;
+    if (c.persistent) return run_fused(P, s);
     const int et = c.edge_tile;
     const bool wide = et == 0 && P.wide_ok;
     if (launch_edges_batch(P.te, P.edge_base[et], P.edge_tx[et], P.n, P.edge_total[et], P.ndt, false, wide,
@@ -1503,7 +1555,8 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     unsigned* edge_tx[2] = {table(2), table(3)};
     unsigned* rank_base = table(4);
     unsigned* merge_base = table(5);
-    unsigned* merge_tx = table(6);  // the queue counters follow, zero
+    unsigned* merge_tx = table(6);
+    unsigned* px = table(7);  // the counters follow, zero
     BatchPlan P{};
     P.magic = kBatchMagic;
     P.n = n;
@@ -1543,6 +1596,7 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
         merge_base[k] = mt;
         merge_tx[k] = mx;
         mt += mx * (unsigned)((geos[k].H + kMergeTH - 1) / kMergeTH);
+        px[k] = (unsigned)geos[k].W * (unsigned)geos[k].H;
         hint += L.ev.hint + 1024u;  // + padding of the levels' and frame's item ranges
         if (k == 0) {
             P.m4_ok = merge4_applies(L.ma);
@@ -1559,7 +1613,7 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     P.merge_total = mt;
     P.eval_hint = hint;
     P.wide_ok = wide;
-    P.cfg = mr_batch_config{0, 0, 0, 0};
+    P.cfg = mr_batch_config{};
     P.te = reinterpret_cast<const EdgeArgs*>(b + BL.te);
     P.tl = reinterpret_cast<const LeanArgs*>(b + BL.tl);
     P.tv = b + BL.tv;
@@ -1573,7 +1627,9 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     P.rank_base = dtable(4);
     P.merge_base = dtable(5);
     P.merge_tx = dtable(6);
+    P.px = dtable(7);
     P.queue = dtable(kBatchTables);
+    P.fused_ctr = P.queue + kBatchCounters;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(b, host.data(), host.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1601,7 +1657,7 @@ int mr_batch_set_config(void* plan, const mr_batch_config* cfg) {
     if (!cfg) return fail(MR_E_NULL, "config is NULL");
     BatchPlan P;
     int st = load_plan(plan, P);
-    if (!st) st = check_config(*cfg);
+    if (!st) st = check_config(P, *cfg);
     if (st) return st;
     P.cfg = *cfg;
     memcpy(plan, &P, sizeof(P));
@@ -1619,7 +1675,9 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
         if (e0) (void)hipEventDestroy(e0);
         return fail(MR_E_DEVICE, "event creation failed");
     }
-    // time of reps runs with configuration c after one warm-up run
+    // time of reps runs with configuration c after one warm-up run; a
+    // persistent configuration whose runs gave up a wait is not a candidate
+    // (its time is reported as infinite and the error word is cleared)
     auto time_of = [&](const mr_batch_config& c, float& ms) -> int {
         P.cfg = c;
         int r = run_plan(P, s);
@@ -1630,6 +1688,17 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             return fail(MR_E_DEVICE, "batch timing failed");
+        if (c.persistent) {
+            unsigned err = 0;
+            if (hipMemcpy(&err, P.fused_ctr + 2, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(MR_E_DEVICE, "batch check failed");
+            if (err) {
+                const unsigned zero = 0;
+                if (hipMemcpy(P.fused_ctr + 2, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+                    return fail(MR_E_DEVICE, "batch check failed");
+                ms = std::numeric_limits<float>::infinity();
+            }
+        }
         return MR_OK;
     };
     // one choice at a time, the evaluation's schedule first (it dominates)
@@ -1637,7 +1706,7 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
     float bt = 0.f;
     st = time_of(bc, bt);
     auto consider = [&](mr_batch_config c) {
-        if (st || check_config(c) != MR_OK) return;
+        if (st || check_config(P, c) != MR_OK) return;
         float t = 0.f;
         st = time_of(c, t);
         if (!st && t < bt) {
@@ -1663,6 +1732,24 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
         c.merge_generic = 1 - bc.merge_generic;
         consider(c);
     }
+    // the persistent launch, with the staged launches' merge choice
+    if (fused_ok(P)) {
+        const mr_batch_config staged = bc;
+        for (int wp : {kDefaultWorkerPixels, 4 * kDefaultWorkerPixels})
+            for (int it : {1, 2}) {
+                mr_batch_config c = staged;
+                c.persistent = 1;
+                c.worker_pixels = wp;
+                c.eval_items = it;
+                consider(c);
+            }
+        if (bc.persistent)
+            for (int g : {4, 64}) {
+                mr_batch_config c = bc;
+                c.tiles_per_ticket = g;
+                consider(c);
+            }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
@@ -1670,6 +1757,22 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
     memcpy(plan, &P, sizeof(P));
     if (best) *best = bc;
     return MR_OK;
+}
+
+int mr_batch_check(const void* plan, void* stream) {
+    BatchPlan P;
+    int st = load_plan(plan, P);
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned err = 0;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(&err, P.fused_ctr + 2, sizeof(err), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "batch check failed: %s", hipGetErrorString(e));
+    if (!err) return MR_OK;
+    const unsigned zero = 0;
+    e = hipMemcpy(P.fused_ctr + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(MR_E_DEVICE, "batch check failed: %s", hipGetErrorString(e));
+    return fail(MR_E_DEVICE, "a persistent batch run gave up waiting for a stage (its outputs are not valid)");
 }
 
 const char* mr_status_string(int status) {

@@ -114,17 +114,18 @@ __device__ __forceinline__ void for_each_chunk(unsigned nchunks, unsigned* queue
 }
 
 // Frames of one batched launch at most.
-constexpr int kMaxBatch = 64;
+constexpr int kMaxBatch = kMaxBatchFrames;
 
-// cbase[f] = first chunk (of 256 items) of frame f in a batch's item space,
-// cbase[n] = total: each frame's item range (from its device counts) rounded
-// up to whole chunks.  Computed by the first wave; ends with a barrier.
+// cbase[f] = first chunk (of `per` items, a multiple of 256) of frame f in a
+// batch's item space, cbase[n] = total: each frame's item range (from its
+// device counts) rounded up to whole chunks.  Computed by the first wave;
+// ends with a barrier.
 template <typename Args>
-__device__ __forceinline__ void batch_chunk_bases(const Args* T, int n, unsigned* cbase) {
+__device__ __forceinline__ void batch_chunk_bases(const Args* T, int n, unsigned per, unsigned* cbase) {
     if (threadIdx.x < 64) {
         const int f = threadIdx.x;
         unsigned cnt = 0;
-        if (f < n) cnt = (item_total(make_item_map(T[f].c)) + 255u) / 256u;
+        if (f < n) cnt = (item_total(make_item_map(T[f].c)) + per - 1u) / per;
         unsigned inc = cnt;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {

@@ -396,4 +396,43 @@ hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int S, int normal_dtype, 
 hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
                                    unsigned total, int C, bool c16, bool m4, hipStream_t s);
 
+// The whole batch in one persistent launch.  Blocks take tickets from one
+// counter; tickets run in stage order (edge tiles, stencil tiles, list tiles,
+// evaluation workers, merge tiles; frames in order within a stage), and a
+// ticket first waits until every ticket of the previous stage of its frame
+// has finished.  Every ticket it waits for was taken earlier by a running
+// block, so the waits always end; each is bounded all the same (spin_limit
+// polls), and one that runs out sets the error word and goes on.  An
+// evaluation worker takes its frame's chunks of 256 x items texels from
+// per-XCD counters (its own XCD's region first, then the others').  The last
+// block to leave zeroes the counters for the next run.
+constexpr int kFusedStages = 5;
+constexpr int kFusedSamples = 256;  // sample sets staged in LDS at most
+constexpr int kFusedReady = 4;      // stages whose completion is counted
+// counter words: ticket, blocks left, error word, then ready[kFusedReady][kMaxBatchFrames] and
+// eval[kMaxBatchFrames][8]
+constexpr int kMaxBatchFrames = 64;
+constexpr int kFusedCounters = 3 + kFusedReady * kMaxBatchFrames + 8 * kMaxBatchFrames;
+struct FusedArgs {
+    const EdgeArgs* te;
+    const LeanArgs* tl;
+    const void* tv;  // SsaoArgs or SsgiArgs
+    const LeanMergeArgs* tm;
+    // per stage: frame f's first tile (edge, ranking, -, ranking, merge)
+    // within the stage, n + 1 entries (base[3] unused); the blocks derive
+    // their ticket tables from these, the pixel counts px and the group and
+    // worker sizes
+    const unsigned* base[kFusedStages];
+    const unsigned* px;
+    const unsigned* edge_tx;   // edge tiles per row, per frame
+    const unsigned* merge_tx;  // merge tiles per row, per frame
+    unsigned worker_px;        // pixels of a frame per evaluation worker ticket
+    int group;                 // edge and merge tiles per ticket
+    unsigned* ctr;             // kFusedCounters words, zero between runs
+    int n, wide, m4, items;
+    unsigned spin_limit;
+};
+hipError_t launch_batch_fused(const FusedArgs& a, int effect, int S, int normal_dtype, int color_dtype,
+                              unsigned* grid_out, hipStream_t s);
+
 }  // namespace mr

@@ -104,7 +104,8 @@ class mr_frame_desc(ctypes.Structure):
 
 class mr_batch_config(ctypes.Structure):
     _fields_ = [("edge_tile", ctypes.c_int), ("eval_queue", ctypes.c_int), ("eval_blocks_per_cu", ctypes.c_int),
-                ("merge_generic", ctypes.c_int)]
+                ("merge_generic", ctypes.c_int), ("persistent", ctypes.c_int), ("eval_items", ctypes.c_int),
+                ("worker_pixels", ctypes.c_int), ("tiles_per_ticket", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -149,6 +150,7 @@ SIGNATURES = {
     "mr_batch_get_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
     "mr_batch_set_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
     "mr_batch_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mr_batch_config), _P]),
+    "mr_batch_check": (ctypes.c_int, [_P, _P]),
     "mr_frame_workspace_layout": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                                  ctypes.c_int, ctypes.POINTER(mr_frame_layout)]),
     "mr_frame_static": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P]),
@@ -718,7 +720,8 @@ def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True
 
 class Batch:
     """Frames of one effect (same mask and effect parameters, any sizes)
-    run with one launch per stage (mr_batch_setup / mr_batch_run).
+    run with one launch per stage, or in one persistent launch
+    (config["persistent"] = 1), through mr_batch_setup / mr_batch_run.
     frames: list of FrameRunner-style argument dicts:
         dict(depth=, normal=, focal=, color=None, out=None)
     The frame tensors must stay alive and at the same addresses."""
@@ -776,6 +779,11 @@ class Batch:
         for k, v in cfg.items():
             setattr(c, k, int(v))
         _check(lib().mr_batch_set_config(ctypes.cast(self.plan, ctypes.c_void_p), ctypes.byref(c)))
+
+    def check(self, stream=None):
+        """mr_batch_check: waits for the stream and raises MRError if a
+        persistent run gave up waiting for a stage since the last check."""
+        _check(lib().mr_batch_check(ctypes.cast(self.plan, ctypes.c_void_p), _stream(stream)))
 
     def tune(self, reps=5, stream=None) -> dict:
         """Autotune the plan's launch configuration on the current inputs

@@ -180,9 +180,10 @@ def test_graph_capture_replays_to_eager():
         assert torch.equal(got[0], alone(effect, fr[0], mp, p)), rep
 
 
-CONFIGS = [dict(edge_tile=t, eval_queue=q, eval_blocks_per_cu=b, merge_generic=m)
-           for t, q, b, m in ((0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 1, 2, 0), (0, 0, 1, 0), (0, 0, 0, 1),
-                              (1, 1, 3, 1))]
+CONFIGS = [dict(edge_tile=t, eval_queue=q, eval_blocks_per_cu=b, merge_generic=m, persistent=0, eval_items=i,
+                worker_pixels=0, tiles_per_ticket=0)
+           for t, q, b, m, i in ((0, 0, 0, 0, 0), (1, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 1, 2, 0, 0), (0, 0, 1, 0, 0),
+                                 (0, 0, 0, 1, 0), (1, 1, 3, 1, 0))]
 
 
 @pytest.mark.parametrize("effect", ["ssao", "ssgi"])
@@ -211,7 +212,8 @@ def test_config_rejects_out_of_range_values():
     mp = mask_params("ssao")
     _, _, p = effect_params("ssao")
     b = mr.Batch("ssao", frames_for("ssao", SIZES[:2]), mp, p)
-    for bad in (dict(edge_tile=2), dict(eval_queue=-1), dict(eval_blocks_per_cu=65), dict(merge_generic=3)):
+    for bad in (dict(edge_tile=2), dict(eval_queue=-1), dict(eval_blocks_per_cu=65), dict(merge_generic=3),
+                dict(persistent=2), dict(eval_items=3), dict(worker_pixels=100), dict(tiles_per_ticket=65)):
         with pytest.raises(mr.MRError) as e:
             b.config = bad
         assert e.value.status == mr.MR_E_PARAM
@@ -230,6 +232,8 @@ def test_tuner_keeps_a_valid_configuration_and_the_outputs():
     log(f"[gpu] tuned {cfg}")
     assert b.config == cfg
     assert cfg["edge_tile"] in (0, 1) and cfg["eval_queue"] in (0, 1) and 0 <= cfg["eval_blocks_per_cu"] <= 64
+    assert cfg["persistent"] in (0, 1) and cfg["eval_items"] in (0, 1, 2, 4)
+    b.check()
     torch.cuda.synchronize()
     for o, r in zip(b.outs, ref):
         assert torch.equal(o, r)
