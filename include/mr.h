@@ -253,7 +253,15 @@ typedef struct {
  *            that stage.
  * bilateral  optional blur of the SSAO sub-images (levels = 0: off); needs
  *            MR_EFFECT_SSAO, multires = 1 and the compact frame path, else
- *            MR_E_PARAM.  Counted in the evaluation stage. */
+ *            MR_E_PARAM.  Counted in the evaluation stage.
+ * eval_halo  0, 8, 16 or 24: how the SSAO evaluation gathers the depth of
+ *            the dense coarsest level.  0: from the level's depth plane.  >0:
+ *            the level is evaluated in 16 x 16 texel tiles whose depth, with
+ *            a border of eval_halo texels, is staged in LDS, and the samples
+ *            that land in that square read it there.  The image is
+ *            bit-identical either way.  Nonzero needs MR_EFFECT_SSAO,
+ *            multires = 1, the compact frame path and at most 256 samples,
+ *            else MR_E_PARAM. */
 typedef struct {
     int effect;
     int multires;
@@ -268,6 +276,7 @@ typedef struct {
     int level_dtype;
     void* stage_events[MR_FRAME_EVENTS];
     mr_bilateral_params bilateral;
+    int eval_halo;
 } mr_frame_desc;
 
 /* Workspace bytes needed by mr_frame for `effect` (MR_EFFECT_*) or by

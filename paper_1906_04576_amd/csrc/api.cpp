@@ -713,6 +713,20 @@ int mark(const mr_frame_desc* d, int k, hipStream_t s) {
     return MR_OK;
 }
 
+// eval_halo: 0, or an LDS halo for the SSAO evaluation of the dense coarsest
+// level (multi-resolution SSAO frames of at most kTiledSamples samples)
+constexpr int kTiledSamplesHost = 256;
+int check_halo(const mr_frame_desc* d) {
+    const int h = d->eval_halo;
+    if (h == 0) return MR_OK;
+    if (h != 8 && h != 16 && h != 24) return fail(MR_E_PARAM, "eval_halo %d is not 0, 8, 16 or 24", h);
+    if (d->effect != MR_EFFECT_SSAO || !d->multires)
+        return fail(MR_E_PARAM, "eval_halo applies to multi-resolution MR_EFFECT_SSAO frames only");
+    if (d->ssao->samples > kTiledSamplesHost)
+        return fail(MR_E_PARAM, "eval_halo needs at most %d samples", kTiledSamplesHost);
+    return MR_OK;
+}
+
 int check_bilateral(const mr_frame_desc* d, const Geo& g) {
     const mr_bilateral_params& p = d->bilateral;
     if (!p.levels) return MR_OK;
@@ -848,6 +862,10 @@ void build_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint8_
         }
     }
     build_eval(effect, &d->g, &d->cam, g, &m, params, lo, /*compact=*/true, &la, d->level_dtype == MR_F16, P.ev);
+    if (effect == MR_EFFECT_SSAO && d->eval_halo) {
+        P.ev.sa.halo = d->eval_halo;
+        P.ev.sa.c.dense_tiles = 1;
+    }
     // bilateral blur of chosen SSAO levels into their second buffers
     void* merged[kMaxLevels] = {};
     for (int j = 0; j < g.nlev; ++j) merged[g.levels[j] - 1] = lo[g.levels[j] - 1];
@@ -998,6 +1016,7 @@ int check_batch(const mr_frame_desc* fr, int n, Geo* geos) {
         if (!d.multires) return fail(MR_E_PARAM, "frame %d: batches are multi-resolution only", k);
         if (d.level_map) return fail(MR_E_PARAM, "frame %d: level_map is not produced in batches", k);
         if (d.bilateral.levels) return fail(MR_E_PARAM, "frame %d: batches do not apply the bilateral blur", k);
+        if (d.eval_halo) return fail(MR_E_PARAM, "frame %d: eval_halo applies to single frames", k);
         const void* p = d.effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
         const void* p0 = f0.effect == MR_EFFECT_SSAO ? (const void*)f0.ssao : (const void*)f0.ssgi;
         int st = check_effect_params(d.effect, d.ssao, d.shadow, d.ssgi);
@@ -1311,6 +1330,7 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
     const int C = effect == MR_EFFECT_SSGI ? 3 : 1;
     if (d->level_dtype != MR_F32 && d->level_dtype != MR_F16)
         return fail(MR_E_DTYPE, "level_dtype %d is neither MR_F32 nor MR_F16", d->level_dtype);
+    if ((st = check_halo(d))) return st;
     if (!d->multires) {
         if (d->bilateral.levels) return fail(MR_E_PARAM, "the bilateral blur needs multires = 1");
         Geo g;
@@ -1333,6 +1353,9 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
     const FrameLayout f = frame_layout(g, effect);
     const size_t lean_bytes = lean_layout(g, effect).bytes;
     const bool lean = lean_ok(g, &d->mp);
+    if (d->eval_halo && !lean)
+        return fail(MR_E_PARAM, "eval_halo needs the compact frame path (coarsest level <= 4, width divisible by 128, "
+                                "blur radii <= 8)");
     const size_t need = path_only ? (lean ? lean_bytes : f.bytes) : (f.bytes > lean_bytes ? f.bytes : lean_bytes);
     if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
@@ -1430,7 +1453,7 @@ int mr_frame_cached(const mr_frame_desc* d, void* pyramid, size_t pyramid_bytes,
     if (!st) st = check_gbuffer(&d->g, true, effect == MR_EFFECT_SSGI);
     if (st) return st;
     if (d->level_map && misaligned(d->level_map)) return fail(MR_E_PARAM, "level_map is not 16-byte aligned");
-    if ((st = check_bilateral(d, g))) return st;
+    if ((st = check_bilateral(d, g)) || (st = check_halo(d))) return st;
     if (!lean_ok(g, &d->mp))
         return fail(MR_E_PARAM, "the compact frame path does not apply (coarsest level <= 4, width divisible by 128, "
                                 "blur radii <= 8)");

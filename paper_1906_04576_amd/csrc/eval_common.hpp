@@ -20,6 +20,10 @@ struct ItemMap {
     int nlev;
 };
 
+// tiles of the dense coarsest level when EvalCommon.dense_tiles is set
+constexpr int kDenseTile = 16;
+__host__ __device__ __forceinline__ unsigned dense_tiles_x(int W) { return (unsigned)(W + kDenseTile - 1) / kDenseTile; }
+
 __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
     ItemMap m;
     m.nlev = c.nlev;
@@ -28,8 +32,13 @@ __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
     for (int j = 0; j < kMaxLevels; ++j) {
         unsigned n = 0;
         if (j < c.nlev) {
+            const EvalLevel& L = c.lv[j];
             // a list never holds more entries than its level has texels
-            n = c.lv[j].list ? min(c.counts[c.lv[j].count_idx], c.lv[j].dense_n) : c.lv[j].dense_n;
+            n = L.list ? min(c.counts[L.count_idx], L.dense_n) : L.dense_n;
+            if (c.dense_tiles && j == c.nlev - 1 && !L.list) {
+                n = dense_tiles_x(L.W) * ((unsigned)(L.H + kDenseTile - 1) / kDenseTile) * 256u;
+                m.cum[j] = (m.cum[j] + 255u) & ~255u;  // a chunk per tile
+            }
         }
         m.cnt[j] = n;
         m.cum[j + 1] = m.cum[j] + ((n + 63u) & ~63u);

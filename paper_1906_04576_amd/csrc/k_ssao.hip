@@ -15,6 +15,19 @@ __global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
     ssao_items<NT, KLDS, AL>(a, ks, eg, kmax);
 }
 
+// The compact frame path with the coarsest level in 16 x 16 tiles whose depth
+// (with a halo of H texels) is staged in LDS; at most kTiledSamples samples,
+// staged in LDS as well.
+constexpr int kTiledSamples = 256;
+template <typename NT, int H>
+__global__ __launch_bounds__(256) void k_ssao_tiled(SsaoArgs a) {
+    __shared__ float ks[3 * kTiledSamples];
+    __shared__ float eg[kMaxLevels * kEgStride];
+    __shared__ float zt[(kDenseTile + 2 * H) * (kDenseTile + 2 * H)];
+    const float kmax = ssao_stage<true, true>(a, ks, eg);
+    ssao_items_tiled<NT, H>(a, ks, eg, kmax, zt);
+}
+
 // Frames of a batch (same samples, mask and effect parameters): one item
 // space over all frames, each frame's range padded to whole chunks of 256,
 // swept by a resident grid like the single-frame launch.
@@ -179,6 +192,29 @@ hipError_t launch_ssao_fullres(const FullresArgs& a, int normal_dtype, hipStream
 
 hipError_t launch_ssao(const SsaoArgs& a, int normal_dtype, unsigned total_hint, hipStream_t s) {
     const bool al = fused_alpha(a.c), lds = a.S <= kLdsSamples;
+    if (a.halo) {
+        if (!al || !a.c.dense_tiles || a.S > kTiledSamples) return hipErrorInvalidValue;
+#define MR_ST(NT, H) \
+    hipLaunchKernelGGL((k_ssao_tiled<NT, H>), dim3(eval_blocks<k_ssao_tiled<NT, H>>(total_hint)), dim3(256), 0, s, a)
+#define MR_STH(NT)                                \
+    do {                                          \
+        if (a.halo == 8)                          \
+            MR_ST(NT, 8);                         \
+        else if (a.halo == 16)                    \
+            MR_ST(NT, 16);                        \
+        else if (a.halo == 24)                    \
+            MR_ST(NT, 24);                        \
+        else                                      \
+            return hipErrorInvalidValue;          \
+    } while (0)
+        if (normal_dtype == MR_F16)
+            MR_STH(_Float16);
+        else
+            MR_STH(float);
+#undef MR_STH
+#undef MR_ST
+        return hipGetLastError();
+    }
 #define MR_SSAO(NT, AL, KL) \
     hipLaunchKernelGGL((k_ssao<NT, AL, KL>), dim3(eval_blocks<k_ssao<NT, AL, KL>>(total_hint)), dim3(256), 0, s, a)
     if (normal_dtype == MR_F16) {

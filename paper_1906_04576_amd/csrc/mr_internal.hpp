@@ -171,6 +171,9 @@ struct EvalCommon {
     const void* normal;
     const void* color;
     long long plane;  // H * W, full-res plane stride of normal/colour
+    // the dense coarsest level's items in 16 x 16 texel tiles (one chunk of
+    // 256 items per tile, its range starting on a chunk boundary)
+    int dense_tiles;
 };
 
 struct SsaoArgs {
@@ -178,6 +181,9 @@ struct SsaoArgs {
     const float* kernel;
     int S;
     float r, b;
+    // LDS halo in texels around a tile of the dense coarsest level (0: its
+    // samples read the depth plane); needs c.dense_tiles
+    int halo;
 };
 
 struct ShadowArgs {

@@ -35,7 +35,8 @@ constexpr int kGroupPlain = 8, kGroupMulti = 2;
 // second form keeps register use at full occupancy (measured).
 template <bool FAST, bool CLAMP, typename KP>
 __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, const SsaoTexel& T, unsigned zpy,
-                                             unsigned zpx, unsigned last, bool& on, float& d, unsigned& off) {
+                                             unsigned zpx, unsigned last, bool& on, float& d, unsigned& off,
+                                             unsigned& sx, unsigned& sy) {
     const float Wf = (float)L.W, Hf = (float)L.H;
     const float kx = K[3 * s], ky = K[3 * s + 1], kz = K[3 * s + 2];
     const float qz = ((T.pz + kx * T.rtz) + ky * T.rbz) + kz * T.rnz;
@@ -53,23 +54,34 @@ __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, co
         // byte pitches < 2^22 fit the 24-bit products; on screen the offset
         // is at most last, so the clamp leaves it unchanged, and off screen
         // it keeps the gather inside the plane (its value is not used).
-        const unsigned sx = (unsigned)cvt_i32_sat(u), sy = (unsigned)cvt_i32_sat(v);
+        sx = (unsigned)cvt_i32_sat(u);
+        sy = (unsigned)cvt_i32_sat(v);
         off = __builtin_elementwise_min((unsigned)__umul24(sy, 4u * zpy) + (unsigned)__umul24(sx, 4u * zpx), last);
     } else {
         on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
         // u, v >= 0 when on, so truncation is floor; rows < 2^14 and pitches
         // < 2^20 keep the offset products within 24 bits
-        const unsigned sx = (unsigned)(int)(on ? u : 0.0f), sy = (unsigned)(int)(on ? v : 0.0f);
+        sx = (unsigned)(int)(on ? u : 0.0f);
+        sy = (unsigned)(int)(on ? v : 0.0f);
         off = __umul24(sy, zpy) + __umul24(sx, zpx);
     }
 }
+
+// A staged copy of the level depth around a tile: tw x tw texels from
+// (x0, y0), in LDS.  TILE: a sample whose texel lies in it reads it there,
+// the others read the depth plane.
+struct DepthTile {
+    const float* t;
+    unsigned x0, y0, tw;
+};
 
 // Gathers of a group of G samples are issued together, one projection at a
 // time (sched_barrier: interleaving the projections buys little ILP and costs
 // registers, i.e. occupancy); the group size sets how many gathers of a wave
 // are in flight.
-template <bool FAST, int G, typename SA, typename KP>
-__device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K, const SsaoTexel& T) {
+template <bool FAST, int G, bool TILE = false, typename SA, typename KP>
+__device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K, const SsaoTexel& T,
+                                          const DepthTile& dt = DepthTile{}) {
     constexpr bool CLAMP = G <= 2;
     const float r = a.r, b = a.b;
     const int S = a.S;
@@ -81,30 +93,37 @@ __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K,
     auto occluded = [&](bool on, float d, float zs) {
         return (on & (zs > 0.0f) & (zs < d - (b * d)) & (fabsf(T.z - zs) < r)) ? 1 : 0;
     };
+    auto gather = [&](unsigned sx, unsigned sy, unsigned off) -> float {
+        if constexpr (TILE) {
+            const unsigned dx = sx - dt.x0, dy = sy - dt.y0;
+            if ((dx < dt.tw) & (dy < dt.tw)) return dt.t[dy * dt.tw + dx];
+        }
+        return buf_f1(rz, CLAMP ? off : off * 4u);
+    };
     int occ = 0;
     int s = 0;
     for (; s + G <= S; s += G) {
         bool on[G];
         float d[G], zs[G];
-        unsigned off[G];
+        unsigned off[G], sx[G], sy[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            ssao_project<FAST, CLAMP>(L, K, s + k, T, zpy, zpx, last, on[k], d[k], off[k]);
+            ssao_project<FAST, CLAMP>(L, K, s + k, T, zpy, zpx, last, on[k], d[k], off[k], sx[k], sy[k]);
             // one projection at a time: interleaving them buys little ILP
             // and costs registers (occupancy)
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int k = 0; k < G; ++k) zs[k] = buf_f1(rz, CLAMP ? off[k] : off[k] * 4u);
+        for (int k = 0; k < G; ++k) zs[k] = gather(sx[k], sy[k], off[k]);
 #pragma unroll
         for (int k = 0; k < G; ++k) occ += occluded(on[k], d[k], zs[k]);
     }
     for (; s < S; ++s) {
         bool on;
         float d;
-        unsigned off;
-        ssao_project<FAST, CLAMP>(L, K, s, T, zpy, zpx, last, on, d, off);
-        occ += occluded(on, d, buf_f1(rz, CLAMP ? off : off * 4u));
+        unsigned off, sx, sy;
+        ssao_project<FAST, CLAMP>(L, K, s, T, zpy, zpx, last, on, d, off, sx, sy);
+        occ += occluded(on, d, gather(sx, sy, off));
     }
     return occ;
 }
@@ -112,9 +131,10 @@ __device__ __forceinline__ int ssao_count(const SA& a, const EvalLevel& L, KP K,
 // occlusion of one texel; K points to LDS (staged samples) or global memory;
 // kmax = the largest |component| over the samples (+inf when unknown); a
 // holds the sampling parameters r, b and S (SsaoArgs or SsaoSampling)
-template <typename NT, int G, typename SA, typename KP>
+template <typename NT, int G, bool TILE = false, typename SA, typename KP>
 __device__ __forceinline__ float ssao_texel(const SA& a, const EvalLevel& L, const NT* nrm, unsigned plane,
-                                            KP K, float kmax, int x, int y, float z) {
+                                            KP K, float kmax, int x, int y, float z,
+                                            const DepthTile& dt = DepthTile{}) {
     const float r = a.r;
     const unsigned g = (unsigned)L.goff + (unsigned)y * (unsigned)L.gpy + (unsigned)x * (unsigned)L.gpx;
     const float nx = ld(nrm, g), ny = ld(nrm, plane + g), nz = ld(nrm, 2 * plane + g);
@@ -131,7 +151,8 @@ __device__ __forceinline__ float ssao_texel(const SA& a, const EvalLevel& L, con
     // these margins all d are in [2^-126, 2^126), where recip_fast is exact.
     const float B0 = kmax * ((fabsf(T.rtz) + fabsf(T.rbz)) + fabsf(T.rnz));
     const bool safe = (z * 0.999f > B0 * 1.001f + 1e-37f) && ((z + B0) * 1.001f < 0x1p125f);
-    const int occ = __ballot(!safe) == 0 ? ssao_count<true, G>(a, L, K, T) : ssao_count<false, G>(a, L, K, T);
+    const int occ =
+        __ballot(!safe) == 0 ? ssao_count<true, G, TILE>(a, L, K, T, dt) : ssao_count<false, G, TILE>(a, L, K, T, dt);
     return (float)occ / (float)a.S;
 }
 
@@ -168,6 +189,54 @@ __device__ __forceinline__ void ssao_items(const SsaoArgs& a, const float* ks, c
     for (unsigned c = cr.first; c < cr.end; c += cr.step) {
         const unsigned item = c * 256u + threadIdx.x;
         if (item < total) ssao_item<NT, KLDS, AL>(a, m, item, ks, eg, kmax);
+    }
+}
+
+// The multi-resolution evaluation with the dense coarsest level in 16 x 16
+// texel tiles, each with a halo of H texels of its depth staged in LDS (zt,
+// (16 + 2H)^2 floats) before its texels' samples gather: the samples that
+// land in the staged square read it there.  Values outside the level are
+// staged clamped; only off-screen samples, which never count, can reach
+// them.  The list levels' chunks run as in ssao_items.
+template <typename NT, int H>
+__device__ __forceinline__ void ssao_items_tiled(const SsaoArgs& a, const float* ks, const float* eg, float kmax,
+                                                 float* zt) {
+    constexpr int TW = kDenseTile + 2 * H;
+    const ItemMap m = make_item_map(a.c);
+    const unsigned total = item_total(m);
+    const int jd = m.nlev - 1;  // the dense coarsest level
+    unsigned dense0 = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) dense0 = k == jd ? m.cum[k] : dense0;
+    const NT* nrm = static_cast<const NT*>(a.c.normal);
+    const unsigned plane = (unsigned)a.c.plane;
+    const ChunkRange cr = chunk_range((total + 255) / 256);
+    for (unsigned c = cr.first; c < cr.end; c += cr.step) {
+        if (c * 256u < dense0) {
+            const unsigned item = c * 256u + threadIdx.x;
+            if (item < total) ssao_item<NT, true, true>(a, m, item, ks, eg, kmax);
+            continue;
+        }
+        const EvalLevel& L = a.c.lv[jd];
+        const unsigned tile = c - dense0 / 256u, tx = dense_tiles_x(L.W);
+        const int x0 = (int)(tile % tx) * kDenseTile, y0 = (int)(tile / tx) * kDenseTile;
+        for (int i = threadIdx.x; i < TW * TW; i += 256) {
+            const int ry = i / TW, rx = i - ry * TW;
+            const int gx = min(max(x0 - H + rx, 0), L.W - 1), gy = min(max(y0 - H + ry, 0), L.H - 1);
+            zt[i] = L.z[(unsigned)gy * (unsigned)L.zpy + (unsigned)gx * (unsigned)L.zpx];
+        }
+        __syncthreads();
+        const int x = x0 + (int)(threadIdx.x % kDenseTile), y = y0 + (int)(threadIdx.x / kDenseTile);
+        if (x < L.W && y < L.H) {
+            const float z = zt[(y - y0 + H) * TW + (x - x0 + H)];
+            float res = 0.0f;
+            if (valid_depth(z)) {
+                const DepthTile dt{zt, (unsigned)(x0 - H), (unsigned)(y0 - H), (unsigned)TW};
+                res = ssao_texel<NT, kGroupMulti, true>(a, L, nrm, plane, ks, kmax, x, y, z, dt);
+            }
+            store_out(L, (unsigned)y * (unsigned)L.W + (unsigned)x, res);
+        }
+        __syncthreads();  // the next tile's staging overwrites zt
     }
 }
 

@@ -99,7 +99,8 @@ class mr_frame_desc(ctypes.Structure):
                 ("ssao", ctypes.POINTER(mr_ssao_params)), ("shadow", ctypes.POINTER(mr_shadow_params)),
                 ("ssgi", ctypes.POINTER(mr_ssgi_params)), ("out", ctypes.c_void_p),
                 ("level_map", ctypes.c_void_p), ("level_dtype", ctypes.c_int),
-                ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS), ("bilateral", mr_bilateral_params)]
+                ("stage_events", ctypes.c_void_p * MR_FRAME_EVENTS), ("bilateral", mr_bilateral_params),
+                ("eval_halo", ctypes.c_int)]
 
 
 class mr_batch_config(ctypes.Structure):
@@ -550,7 +551,7 @@ class FrameRunner:
 
     def __init__(self, effect, depth, normal, focal, mp: MaskParams, multires=True, color=None, params=None,
                  out=None, level_map=None, workspace=None, level_dtype=torch.float32, bilateral: Bilateral = None,
-                 ws_bytes=None):
+                 ws_bytes=None, eval_halo=0):
         self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         H, W = depth.shape
         C = 3 if self.effect == MR_EFFECT_SSGI else 1
@@ -574,6 +575,7 @@ class FrameRunner:
         d.level_dtype = MR_F16 if level_dtype == torch.float16 else MR_F32
         if bilateral is not None:
             d.bilateral = bilateral.c()
+        d.eval_halo = int(eval_halo)
         self.desc = d
         self._keep = (depth, normal, color, level_map)
         nws = ws_bytes if ws_bytes is not None else (mr_workspace_bytes(W, H, focal, mp, self.effect) if multires else 0)
@@ -713,9 +715,9 @@ class StaticFrameRunner(FrameRunner):
 
 
 def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True, color=None, out=None,
-             level_map=None, stream=None, level_dtype=torch.float32, bilateral: Bilateral = None):
+             level_map=None, stream=None, level_dtype=torch.float32, bilateral: Bilateral = None, eval_halo=0):
     return FrameRunner(effect, depth, normal, focal, mp, multires, color, params, out, level_map,
-                       level_dtype=level_dtype, bilateral=bilateral)(stream)
+                       level_dtype=level_dtype, bilateral=bilateral, eval_halo=eval_halo)(stream)
 
 
 class Batch:

@@ -141,6 +141,20 @@ def test_entry_points_reject_null_and_bad_shapes_without_enqueueing():
     assert L.mr_frame(ctypes.byref(d), ctypes.c_void_p(4096), 100, None) == mr.MR_E_WORKSPACE
     d.effect = 9
     assert L.mr_frame(ctypes.byref(d), ctypes.c_void_p(4096), 100, None) == mr.MR_E_PARAM
+    # eval_halo: not one of 0, 8, 16, 24; too many samples; off the compact path
+    d.effect = mr.MR_EFFECT_SSAO
+    for h in (4, 32, -8):
+        d.eval_halo = h
+        assert L.mr_frame(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 30, None) == mr.MR_E_PARAM
+        assert "eval_halo" in mr.mr_last_error()
+    d.eval_halo = 16
+    sp300 = mr.mr_ssao_params(ctypes.c_void_p(4096), 300, 0.5, 0.02)
+    d.ssao = ctypes.pointer(sp300)
+    assert L.mr_frame(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 30, None) == mr.MR_E_PARAM
+    d.ssao = ctypes.pointer(sp)
+    assert L.mr_frame(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 30, None) == mr.MR_E_PARAM  # width 64
+    assert "compact" in mr.mr_last_error()
+    d.eval_halo = 0
     # merge: bad channel count
     mm = mr.mr_masks()
     arr = mr.c_ptr6()
