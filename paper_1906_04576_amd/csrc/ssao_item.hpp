@@ -30,9 +30,11 @@ constexpr int kGroupPlain = 8, kGroupMulti = 2;
 // else in elements (element pitches zpy, zpx; last = byte offset of the
 // plane's last texel).  Two exact forms:
 // CLAMP tests 0 <= u < W and 0 <= v < H as unsigned compares of the bit
-// patterns and clamps the offset to last, four instructions fewer per sample
-// than selecting texel 0 off screen; with groups of 8 samples in flight the
-// second form keeps register use at full occupancy (measured).
+// patterns and gathers at whatever offset an off-screen sample gives (the
+// depth plane is a buffer resource: past its end a load returns 0 without
+// an access), five instructions fewer per sample than selecting texel 0 off
+// screen; with groups of 8 samples in flight the second form keeps register
+// use at full occupancy (measured).
 template <bool FAST, bool CLAMP, typename KP>
 __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, const SsaoTexel& T, unsigned zpy,
                                              unsigned zpx, unsigned last, bool& on, float& d, unsigned& off,
@@ -48,17 +50,21 @@ __device__ __forceinline__ void ssao_project(const EvalLevel& L, KP K, int s, co
     const float v = L.cy - (qy * inv) * L.f;
     if (CLAMP) {
         // exact for every u other than -0: u = cx + t and v = cy - t' are
-        // never -0 because cx, cy > 0 (a sum is -0 only when both terms are)
-        on = (d > 0.0f) & (__float_as_uint(u) < __float_as_uint(Wf)) & (__float_as_uint(v) < __float_as_uint(Hf));
+        // never -0 because cx, cy > 0 (a sum is -0 only when both terms are).
+        // FAST: every d of the texel is at least 2^-126, so d > 0 holds.
+        on = (FAST || d > 0.0f) & (__float_as_uint(u) < __float_as_uint(Wf)) &
+             (__float_as_uint(v) < __float_as_uint(Hf));
         // u, v >= 0 when on, so truncation is floor.  Coordinates < 2^14 and
-        // byte pitches < 2^22 fit the 24-bit products; on screen the offset
-        // is at most last, so the clamp leaves it unchanged, and off screen
-        // it keeps the gather inside the plane (its value is not used).
+        // byte pitches < 2^22 fit the 24-bit products, so on screen the
+        // offset is the texel's.  Off screen it is any value: the buffer
+        // resource returns 0 past the plane and no access faults, and the
+        // value is not used.
         sx = (unsigned)cvt_i32_sat(u);
         sy = (unsigned)cvt_i32_sat(v);
-        off = __builtin_elementwise_min((unsigned)__umul24(sy, 4u * zpy) + (unsigned)__umul24(sx, 4u * zpx), last);
+        off = (unsigned)__umul24(sy, 4u * zpy) + (unsigned)__umul24(sx, 4u * zpx);
+        (void)last;
     } else {
-        on = (d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
+        on = (FAST || d > 0.0f) & (u >= 0.0f) & (u < Wf) & (v >= 0.0f) & (v < Hf);
         // u, v >= 0 when on, so truncation is floor; rows < 2^14 and pitches
         // < 2^20 keep the offset products within 24 bits
         sx = (unsigned)(int)(on ? u : 0.0f);
