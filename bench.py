@@ -209,15 +209,16 @@ def pcss_4k(dev, cams=4):
 def serving(qps=4000.0, seconds=1.5):
     """The request loop (serve.py) on a Poisson stream: p50 / p99 latency and
     Mpixels/s on the same requests, multi-resolution with the scenes' mask
-    pyramids resident, multi-resolution rebuilding the masks per request, and
-    naive."""
+    pyramids resident, multi-resolution rebuilding the masks per request,
+    multi-resolution with same-effect requests batched (up to 4 per launch
+    set), and naive."""
     from paper_1906_04576_amd import serve
     pool = serve.Pool(2)
     reqs = serve.poisson_requests(pool, qps, seconds)
     out = {"qps": qps, "seconds": seconds, "requests": len(reqs), "slots": 4, "budget_gb": 64}
-    for name, multires, resident in (("multires", True, True), ("multires_rebuild", True, False),
-                                     ("plain", False, False)):
-        srv = serve.Server(pool, 4, 64 << 30, multires, resident_masks=resident)
+    for name, multires, resident, bmax in (("multires", True, True, 0), ("multires_rebuild", True, False, 0),
+                                           ("multires_batched", True, True, 4), ("plain", False, False, 0)):
+        srv = serve.Server(pool, 4, 64 << 30, multires, resident_masks=resident, batch_max=bmax)
         srv.run(reqs[: min(len(reqs), 64)])
         s_ = serve.summary(srv.run(reqs))
         s_["saturated_mpixels_s"] = serve.summary(srv.run(reqs, realtime=False))["mpixels_s"]

@@ -443,6 +443,19 @@ MR_API int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t w
                           size_t plan_bytes, void* stream);
 MR_API int mr_batch_run(const void* plan, void* stream);
 
+/* mr_batch_setup that does not wait, for a loop that forms a new batch from
+ * whatever requests are pending (continuous batching).  The argument tables
+ * are written to `staging`, caller-owned host memory of at least
+ * mr_batch_staging_bytes(frames, n) bytes (page-locked, so that the copy is
+ * asynchronous), and copied into ws by hipMemcpyAsync on `stream`; staging
+ * must stay unchanged until the stream has passed that copy (e.g. until an
+ * event recorded after the batch's run has completed), and ws must not be in
+ * use by an earlier batch still in flight.  Returns 0 from
+ * mr_batch_staging_bytes for an invalid batch (mr_last_error says why). */
+MR_API size_t mr_batch_staging_bytes(const mr_frame_desc* frames, int n);
+MR_API int mr_batch_setup_async(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan,
+                                size_t plan_bytes, void* staging, size_t staging_bytes, void* stream);
+
 /* How a batch's launches are shaped.  mr_batch_setup puts the defaults (all
  * zero) in the plan.  Every choice gives bit-identical outputs; only the time
  * differs.

@@ -1553,8 +1553,20 @@ size_t mr_batch_workspace_bytes(const mr_frame_desc* frames, int n) {
     return batch_layout(frames, n, geos).bytes;
 }
 
-int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan, size_t plan_bytes,
-                   void* stream) {
+size_t mr_batch_staging_bytes(const mr_frame_desc* frames, int n) {
+    Geo geos[MR_MAX_BATCH];
+    if (check_batch(frames, n, geos)) return 0;
+    return batch_layout(frames, n, geos).frames[0];
+}
+
+}  // extern "C"
+
+namespace {
+// mr_batch_setup and mr_batch_setup_async: the tables are built in `stage`
+// (host memory of BL.frames[0] bytes) and copied to the start of ws on the
+// stream; wait: the call returns after the copy (stage may be freed then)
+int batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan, size_t plan_bytes,
+                uint8_t* stage, size_t stage_bytes, bool wait, hipStream_t s) {
     Geo geos[MR_MAX_BATCH];
     int st = check_batch(frames, n, geos);
     if (st) return st;
@@ -1563,16 +1575,20 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     const BatchLayout BL = batch_layout(frames, n, geos);
     if (!ws || ws_bytes < BL.bytes) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, BL.bytes);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
+    if (!stage) return fail(MR_E_NULL, "staging is NULL");
+    if (stage_bytes < BL.frames[0])
+        return fail(MR_E_WORKSPACE, "staging %zu bytes < %zu needed", stage_bytes, BL.frames[0]);
     uint8_t* b = static_cast<uint8_t*>(ws);
     const int effect = frames[0].effect;
-    // host copy of the tables region, then one copy to the device
-    std::vector<uint8_t> host(BL.frames[0], 0);
-    EdgeArgs* te = reinterpret_cast<EdgeArgs*>(host.data() + BL.te);
-    LeanArgs* tl = reinterpret_cast<LeanArgs*>(host.data() + BL.tl);
-    SsaoArgs* tsa = reinterpret_cast<SsaoArgs*>(host.data() + BL.tv);
-    SsgiArgs* tgi = reinterpret_cast<SsgiArgs*>(host.data() + BL.tv);
-    LeanMergeArgs* tm = reinterpret_cast<LeanMergeArgs*>(host.data() + BL.tm);
-    unsigned* bases = reinterpret_cast<unsigned*>(host.data() + BL.bases);
+    // the tables region on the host, then one copy to the device
+    uint8_t* const host = stage;
+    memset(host, 0, BL.frames[0]);
+    EdgeArgs* te = reinterpret_cast<EdgeArgs*>(host + BL.te);
+    LeanArgs* tl = reinterpret_cast<LeanArgs*>(host + BL.tl);
+    SsaoArgs* tsa = reinterpret_cast<SsaoArgs*>(host + BL.tv);
+    SsgiArgs* tgi = reinterpret_cast<SsgiArgs*>(host + BL.tv);
+    LeanMergeArgs* tm = reinterpret_cast<LeanMergeArgs*>(host + BL.tm);
+    unsigned* bases = reinterpret_cast<unsigned*>(host + BL.bases);
     auto table = [&](int t) { return bases + t * (MR_MAX_BATCH + 1); };
     unsigned* edge_base[2] = {table(0), table(1)};
     unsigned* edge_tx[2] = {table(2), table(3)};
@@ -1653,12 +1669,30 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     P.px = dtable(7);
     P.queue = dtable(kBatchTables);
     P.fused_ctr = P.queue + kBatchCounters;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(b, host.data(), host.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipError_t e = hipMemcpyAsync(b, host, BL.frames[0], hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && wait) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(MR_E_DEVICE, "batch table copy failed: %s", hipGetErrorString(e));
     memcpy(plan, &P, sizeof(P));
     return MR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan, size_t plan_bytes,
+                   void* stream) {
+    Geo geos[MR_MAX_BATCH];
+    const int st = check_batch(frames, n, geos);
+    if (st) return st;
+    std::vector<uint8_t> host(batch_layout(frames, n, geos).frames[0]);
+    return batch_setup(frames, n, ws, ws_bytes, plan, plan_bytes, host.data(), host.size(), true,
+                       static_cast<hipStream_t>(stream));
+}
+
+int mr_batch_setup_async(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan,
+                         size_t plan_bytes, void* staging, size_t staging_bytes, void* stream) {
+    return batch_setup(frames, n, ws, ws_bytes, plan, plan_bytes, static_cast<uint8_t*>(staging), staging_bytes, false,
+                       static_cast<hipStream_t>(stream));
 }
 
 int mr_batch_run(const void* plan, void* stream) {

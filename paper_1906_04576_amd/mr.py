@@ -152,6 +152,9 @@ SIGNATURES = {
     "mr_batch_set_config": (ctypes.c_int, [_P, ctypes.POINTER(mr_batch_config)]),
     "mr_batch_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mr_batch_config), _P]),
     "mr_batch_check": (ctypes.c_int, [_P, _P]),
+    "mr_batch_staging_bytes": (ctypes.c_size_t, [ctypes.POINTER(mr_frame_desc), ctypes.c_int]),
+    "mr_batch_setup_async": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), ctypes.c_int, _P, ctypes.c_size_t, _P,
+                                            ctypes.c_size_t, _P, ctypes.c_size_t, _P]),
     "mr_frame_workspace_layout": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                                  ctypes.c_int, ctypes.POINTER(mr_frame_layout)]),
     "mr_frame_static": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P]),
@@ -720,6 +723,36 @@ def mr_frame(effect, depth, normal, focal, mp: MaskParams, params, multires=True
                        level_dtype=level_dtype, bilateral=bilateral, eval_halo=eval_halo)(stream)
 
 
+def _batch_descs(effect: int, frames, mp: MaskParams, params, level_dtype):
+    """Frame descriptors of a batch, the output tensors (allocated where a
+    frame brings none) and the tensors the descriptors point into."""
+    n = len(frames)
+    descs = (mr_frame_desc * n)()
+    outs, keep = [], [params]
+    C = 3 if effect == MR_EFFECT_SSGI else 1
+    for k, f in enumerate(frames):
+        depth, normal, color = f["depth"], f["normal"], f.get("color")
+        H, W = depth.shape
+        out = f.get("out")
+        if out is None:
+            out = torch.empty((C, H, W) if C > 1 else (H, W), dtype=torch.float32, device=depth.device)
+        d = descs[k]
+        d.effect = effect
+        d.multires = 1
+        d.g = gbuffer(depth, normal, color)
+        d.cam = camera(W, H, f["focal"])
+        d.mp = mp.c()
+        if effect == MR_EFFECT_SSAO:
+            d.ssao = ctypes.pointer(params)
+        else:
+            d.ssgi = ctypes.pointer(params)
+        d.out = _ptr(out)
+        d.level_dtype = MR_F16 if level_dtype == torch.float16 else MR_F32
+        outs.append(out)
+        keep += [depth, normal, color]
+    return descs, outs, keep
+
+
 class Batch:
     """Frames of one effect (same mask and effect parameters, any sizes)
     run with one launch per stage, or in one persistent launch
@@ -731,29 +764,7 @@ class Batch:
     def __init__(self, effect, frames, mp: MaskParams, params, level_dtype=torch.float32, stream=None):
         self.effect = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         n = len(frames)
-        descs = (mr_frame_desc * n)()
-        self.outs, self._keep = [], [params]
-        C = 3 if self.effect == MR_EFFECT_SSGI else 1
-        for k, f in enumerate(frames):
-            depth, normal, color = f["depth"], f["normal"], f.get("color")
-            H, W = depth.shape
-            out = f.get("out")
-            if out is None:
-                out = torch.empty((C, H, W) if C > 1 else (H, W), dtype=torch.float32, device=depth.device)
-            d = descs[k]
-            d.effect = self.effect
-            d.multires = 1
-            d.g = gbuffer(depth, normal, color)
-            d.cam = camera(W, H, f["focal"])
-            d.mp = mp.c()
-            if self.effect == MR_EFFECT_SSAO:
-                d.ssao = ctypes.pointer(params)
-            else:
-                d.ssgi = ctypes.pointer(params)
-            d.out = _ptr(out)
-            d.level_dtype = MR_F16 if level_dtype == torch.float16 else MR_F32
-            self.outs.append(out)
-            self._keep += [depth, normal, color]
+        descs, self.outs, self._keep = _batch_descs(self.effect, frames, mp, params, level_dtype)
         self.descs = descs
         nws = lib().mr_batch_workspace_bytes(descs, n)
         if nws == 0:
@@ -794,6 +805,45 @@ class Batch:
         _check(lib().mr_batch_tune(ctypes.cast(self.plan, ctypes.c_void_p), int(reps), ctypes.byref(c),
                                    _stream(stream)))
         return c.as_dict()
+
+
+class BatchSlot:
+    """Memory for batches formed on the fly (mr_batch_setup_async): a device
+    workspace and a page-locked staging buffer of fixed sizes.  run() sets up
+    a batch of the given frames and enqueues it on the stream without
+    waiting; the slot may take its next batch once the stream has passed
+    this one (the caller orders that, e.g. with an event)."""
+
+    def __init__(self, ws_bytes: int, staging_bytes: int, device="cuda"):
+        self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+        self.staging = torch.empty(staging_bytes, dtype=torch.uint8, pin_memory=True)
+        self.plan = (ctypes.c_uint8 * MR_BATCH_PLAN_BYTES)()
+        self._keep = None
+
+    @staticmethod
+    def sizes(effect, frames, mp: MaskParams, params, level_dtype=torch.float32) -> tuple:
+        """(workspace bytes, staging bytes) of a batch of these frames."""
+        eff = EFFECTS[effect] if isinstance(effect, str) else int(effect)
+        descs, _, _ = _batch_descs(eff, frames, mp, params, level_dtype)
+        nws = lib().mr_batch_workspace_bytes(descs, len(frames))
+        nst = lib().mr_batch_staging_bytes(descs, len(frames))
+        if nws == 0 or nst == 0:
+            _check(MR_E_PARAM)
+        return int(nws), int(nst)
+
+    def run(self, effect, frames, mp: MaskParams, params, stream=None, level_dtype=torch.float32):
+        eff = EFFECTS[effect] if isinstance(effect, str) else int(effect)
+        descs, outs, keep = _batch_descs(eff, frames, mp, params, level_dtype)
+        if stream is not None and stream != torch.cuda.current_stream():
+            self.workspace.record_stream(stream)
+            for o in outs:
+                o.record_stream(stream)
+        _check(lib().mr_batch_setup_async(descs, len(frames), _ptr(self.workspace), self.workspace.numel(),
+                                          ctypes.cast(self.plan, ctypes.c_void_p), MR_BATCH_PLAN_BYTES,
+                                          _ptr(self.staging), self.staging.numel(), _stream(stream)))
+        _check(lib().mr_batch_run(ctypes.cast(self.plan, ctypes.c_void_p), _stream(stream)))
+        self._keep = (descs, keep)  # the frame descriptors' targets stay alive until the next batch
+        return outs
 
 
 class Prepared:

@@ -20,6 +20,8 @@ requests admitted back to back (the loop's capacity).
 from __future__ import annotations
 
 import argparse
+import collections
+import itertools
 import json
 import sys
 import time
@@ -179,11 +181,17 @@ def poisson_requests(pool: Pool, qps: float, seconds: float, seed: int = 7) -> l
 
 
 class Server:
-    """slots concurrent frames (one stream and workspace each) under an HBM
-    budget for the working memory of the requests in flight."""
+    """slots concurrent launches (one stream and workspace each) under an HBM
+    budget for the working memory of the requests in flight.  batch_max >= 2:
+    when a slot frees up, the oldest pending request takes with it up to
+    batch_max - 1 other arrived requests of the same effect (SSAO or SSGI,
+    compact path), and they run as one batch (mr_batch_setup_async, one
+    launch per stage for all of them; the masks are built afresh); a request
+    that finds no partner runs alone as before."""
 
     def __init__(self, pool: Pool, slots: int = 4, budget_bytes: int = 64 << 30, multires: bool = True,
-                 level_dtype=torch.float32, keep_outputs: bool = False, resident_masks: bool = True):
+                 level_dtype=torch.float32, keep_outputs: bool = False, resident_masks: bool = True,
+                 batch_max: int = 0):
         self.pool, self.multires, self.level_dtype, self.keep = pool, multires, level_dtype, keep_outputs
         self.cached = multires and resident_masks
         self.budget = budget_bytes
@@ -191,14 +199,42 @@ class Server:
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.ws = [torch.empty(ws, dtype=torch.uint8, device=pool.device) for _ in range(slots)]
         self.ws_bytes = ws
+        self.batch_max = batch_max if multires else 0
+        self.batched = 0  # requests served in batches of two or more
+        self.slots_b = []
+        self.batch_ws_bytes = 0
+        if self.batch_max >= 2:
+            nws, nst = 0, 0
+            for e in ("ssao", "ssgi"):
+                ks = [k for k in range(len(pool.scenes)) if pool.compact(k, e)]
+                if not ks:
+                    continue
+                big = max(ks, key=lambda k: pool.scenes[k].W * pool.scenes[k].H)
+                w, t = mr.BatchSlot.sizes(e, [self._frame(big, e)] * self.batch_max, pool.mp[e],
+                                          pool.params(e, pool.scenes[big]), level_dtype)
+                nws, nst = max(nws, w), max(nst, t)
+            self.slots_b = [mr.BatchSlot(nws, nst, pool.device) for _ in range(slots)]
+            self.batch_ws_bytes = nws
+
+    def _frame(self, scene: int, effect: str, out=None) -> dict:
+        sc = self.pool.scenes[scene]
+        return dict(depth=sc.depth, normal=sc.normal, focal=sc.focal, color=sc.color if effect == "ssgi" else None,
+                    out=out)
+
+    def _batchable(self, req: Request) -> bool:
+        return self.batch_max >= 2 and req.effect in ("ssao", "ssgi") and self.pool.compact(req.scene, req.effect)
+
+    def _out(self, req: Request, st):
+        sc = self.pool.scenes[req.scene]
+        C = 3 if req.effect == "ssgi" else 1
+        with torch.cuda.stream(st):
+            return torch.empty((C, sc.H, sc.W) if C > 1 else (sc.H, sc.W), dtype=torch.float32,
+                               device=self.pool.device)
 
     def _launch(self, req: Request, slot: int):
         sc = self.pool.scenes[req.scene]
-        C = 3 if req.effect == "ssgi" else 1
         st = self.streams[slot]
-        with torch.cuda.stream(st):
-            out = torch.empty((C, sc.H, sc.W) if C > 1 else (sc.H, sc.W), dtype=torch.float32,
-                              device=self.pool.device)
+        out = self._out(req, st)
         color = sc.color if req.effect == "ssgi" else None
         params = self.pool.params(req.effect, sc)
         cached = self.cached and self.pool.compact(req.scene, req.effect)
@@ -220,14 +256,40 @@ class Server:
         ev.record(st)
         if cached and build:
             pyr.built, pyr.ready = True, ev
-        return out, ev, out.numel() * 4 + self.ws_bytes
+        return [out], ev, out.numel() * 4 + self.ws_bytes
+
+    def _launch_batch(self, reqs: list[Request], slot: int):
+        st = self.streams[slot]
+        e = reqs[0].effect
+        outs = [self._out(r, st) for r in reqs]
+        frames = [self._frame(r.scene, e, o) for r, o in zip(reqs, outs)]
+        self.slots_b[slot].run(e, frames, self.pool.mp[e], self.pool.params(e, self.pool.scenes[reqs[0].scene]),
+                               stream=st, level_dtype=self.level_dtype)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        self.batched += len(reqs)
+        return outs, ev, sum(o.numel() * 4 for o in outs) + self.batch_ws_bytes
+
+    def _group(self, pending: list[Request], now: float, realtime: bool) -> list[Request]:
+        """The oldest pending request and, if it can be batched, up to
+        batch_max - 1 more arrived requests of its effect."""
+        first = pending[0]
+        group = [first]
+        if not self._batchable(first):
+            return group
+        for r in itertools.islice(pending, 1, None):
+            if len(group) == self.batch_max or (realtime and r.arrival > now):
+                break
+            if r.effect == first.effect and self._batchable(r):
+                group.append(r)
+        return group
 
     def run(self, reqs: list[Request], realtime: bool = True) -> list[Done]:
         """Serve the request stream; realtime=False admits every request as
         soon as a slot is free (arrival times ignored)."""
-        pending = list(reqs)
+        pending = collections.deque(reqs)
         free = list(range(len(self.streams)))
-        inflight = {}  # slot -> (req, out, event, bytes, start)
+        inflight = {}  # slot -> (reqs, outs, event, bytes, start)
         used = 0
         done: list[Done] = []
         torch.cuda.synchronize()
@@ -235,29 +297,42 @@ class Server:
         while pending or inflight:
             now = time.perf_counter() - t0
             for slot in list(inflight):
-                req, out, ev, nb, start = inflight[slot]
+                group, outs, ev, nb, start = inflight[slot]
                 if ev.query():
                     end = time.perf_counter() - t0
-                    sc = self.pool.scenes[req.scene]
-                    done.append(Done(req.rid, req.arrival if realtime else start, start, end, sc.W * sc.H,
-                                     out if self.keep else None))
+                    for req, out in zip(group, outs):
+                        sc = self.pool.scenes[req.scene]
+                        done.append(Done(req.rid, req.arrival if realtime else start, start, end, sc.W * sc.H,
+                                         out if self.keep else None))
                     used -= nb
                     del inflight[slot]
                     free.append(slot)
             while pending and free and (not realtime or pending[0].arrival <= now):
-                req = pending[0]
-                sc = self.pool.scenes[req.scene]
-                need = (3 if req.effect == "ssgi" else 1) * sc.W * sc.H * 4 + self.ws_bytes
-                if self.cached and (req.scene, req.effect) not in self.pool.pyramids and \
-                        self.pool.compact(req.scene, req.effect):
-                    need += self.pool.pyramid_bytes(req.scene, req.effect)  # becomes resident
+                group = self._group(pending, now, realtime)
+                need = 0
+                for req in group:
+                    sc = self.pool.scenes[req.scene]
+                    need += (3 if req.effect == "ssgi" else 1) * sc.W * sc.H * 4
+                if len(group) > 1:
+                    need += self.batch_ws_bytes
+                else:
+                    req = group[0]
+                    need += self.ws_bytes
+                    if self.cached and (req.scene, req.effect) not in self.pool.pyramids and \
+                            self.pool.compact(req.scene, req.effect):
+                        need += self.pool.pyramid_bytes(req.scene, req.effect)  # becomes resident
                 if used + need + self.pool.resident_bytes() > self.budget and inflight:
                     break  # admitted when memory frees up
-                pending.pop(0)
+                pending.popleft()
+                for r in group[1:]:
+                    pending.remove(r)  # near the front: within the arrived requests
                 slot = free.pop(0)
-                out, ev, nb = self._launch(req, slot)
+                if len(group) > 1:
+                    outs, ev, nb = self._launch_batch(group, slot)
+                else:
+                    outs, ev, nb = self._launch(group[0], slot)
                 used += nb
-                inflight[slot] = (req, out, ev, nb, time.perf_counter() - t0)
+                inflight[slot] = (group, outs, ev, nb, time.perf_counter() - t0)
         torch.cuda.synchronize()
         return sorted(done, key=lambda d: d.rid)
 
@@ -283,9 +358,10 @@ def main(argv=None):
     print(f"[serve] {len(pool.scenes)} resident scenes in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     reqs = poisson_requests(pool, args.qps, args.seconds)
     res = {"qps": args.qps, "seconds": args.seconds, "slots": args.slots, "budget_gb": args.budget_gb}
-    for name, multires, resident in (("multires", True, True), ("multires_rebuild", True, False),
-                                     ("plain", False, False)):
-        srv = Server(pool, args.slots, int(args.budget_gb * (1 << 30)), multires, resident_masks=resident)
+    for name, multires, resident, bmax in (("multires", True, True, 0), ("multires_rebuild", True, False, 0),
+                                           ("multires_batched", True, True, 4), ("plain", False, False, 0)):
+        srv = Server(pool, args.slots, int(args.budget_gb * (1 << 30)), multires, resident_masks=resident,
+                     batch_max=bmax)
         srv.run(reqs[: min(len(reqs), 64)])  # warm-up (builds the resident pyramids)
         s = summary(srv.run(reqs))
         # the same requests admitted back to back: the loop's capacity

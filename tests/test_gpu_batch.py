@@ -241,3 +241,22 @@ def test_tuner_keeps_a_valid_configuration_and_the_outputs():
     torch.cuda.synchronize()
     for o, r in zip(b.outs, ref):
         assert torch.equal(o, r)
+
+
+def test_async_setup_in_a_reused_slot():
+    """mr_batch_setup_async through a BatchSlot: two different batches in a
+    row in one slot, each equal to the frames alone."""
+    mp = mask_params("ssgi")
+    _, _, p = effect_params("ssgi")
+    fr_a = frames_for("ssgi", SIZES[:3])
+    fr_b = frames_for("ssgi", SIZES[3:])
+    nws = max(mr.BatchSlot.sizes("ssgi", f, mp, p)[0] for f in (fr_a, fr_b))
+    nst = max(mr.BatchSlot.sizes("ssgi", f, mp, p)[1] for f in (fr_a, fr_b))
+    slot = mr.BatchSlot(nws, nst)
+    st = torch.cuda.Stream()
+    log("[gpu] async batch setup, two batches in one slot")
+    for fr in (fr_a, fr_b):
+        outs = slot.run("ssgi", fr, mp, p, stream=st)
+        st.synchronize()
+        for f, o in zip(fr, outs):
+            assert torch.equal(o, alone("ssgi", f, mp, p))

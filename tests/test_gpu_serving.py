@@ -80,6 +80,24 @@ def test_results_identical_alone_and_in_the_mix():
         assert torch.isfinite(d.out).all()
 
 
+def test_batched_requests_equal_requests_alone():
+    """Same-effect requests served as batches (up to 4 per batch, set up
+    without waiting) give the frames of the same requests served alone; a
+    batched SSGI request also equals the oracle."""
+    p = pool()
+    reqs = [serve.Request(k, 0.0, ("ssao", "ssgi", "shadow")[k % 3], k % len(p.scenes)) for k in range(18)]
+    log(f"[gpu] batched serving of {len(reqs)} requests")
+    srv = serve.Server(p, slots=2, keep_outputs=True, batch_max=4)
+    mix = srv.run(reqs, realtime=False)
+    assert srv.batched >= 8
+    for r, d in zip(reqs, mix):
+        alone = serve.Server(p, slots=1, keep_outputs=True).run([r], realtime=False)[0]
+        assert torch.equal(alone.out, d.out), (r.rid, r.effect)
+    k = next(i for i, r in enumerate(reqs) if r.effect == "ssgi" and p.scenes[r.scene].W == 384)
+    ref = oracle_frame(p, reqs[k].scene, "ssgi")
+    assert np.array_equal(mix[k].out.cpu().numpy(), ref)
+
+
 def test_budget_limits_requests_in_flight():
     p = pool()
     reqs = serve.poisson_requests(p, qps=20000.0, seconds=0.001, seed=4)
