@@ -45,13 +45,13 @@ SSAO_FP32_PER_TEXEL = 31
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (profiles/ssao_4k_hbm_counters.md), scaled by the
 # copy-kernel calibration; None once the kernel changes, until re-measured
-TRAFFIC_BYTES = {"k_ssao_multi": None}
+TRAFFIC_BYTES = {"k_ssao_multi": 61866903}
 # VALU issue of the dominant kernel from the SQ_INSTS_VALU_* counters
 # (profiles/ssao_4k_eval_valu_issue.md): wave instructions per launch of the
 # FP32 arithmetic classes (add, multiply, FMA, transcendental, conversion; 4
 # cycles per wave64 instruction) and of all other VALU instructions (2
 # cycles); None once the kernel changes, until re-measured
-VALU_ISSUE = {"k_ssao_multi": None}
+VALU_ISSUE = {"k_ssao_multi": {"fp32_arith": 12909635, "other": 7702172}}
 
 
 def log(*a):
