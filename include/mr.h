@@ -456,6 +456,20 @@ MR_API size_t mr_batch_staging_bytes(const mr_frame_desc* frames, int n);
 MR_API int mr_batch_setup_async(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan,
                                 size_t plan_bytes, void* staging, size_t staging_bytes, void* stream);
 
+/* A batch on resident mask pyramids (serving resident scenes): pyramids[k]
+ * is frame k's pyramid, built by mr_frame_cached (build = 1) on the same
+ * G-buffer contents, camera, mask parameters and effect -- the library
+ * cannot check this -- and ordered before the run.  The batch evaluates and
+ * merges only (its edge and ranking launches are skipped), so ws holds just
+ * the frames' scratch: at least mr_batch_cached_workspace_bytes(frames, n).
+ * Set up without waiting, as mr_batch_setup_async.  Its plan runs staged
+ * with fixed evaluation strides: mr_batch_set_config refuses persistent = 1
+ * and eval_queue = 1 for it. */
+MR_API size_t mr_batch_cached_workspace_bytes(const mr_frame_desc* frames, int n);
+MR_API int mr_batch_setup_cached(const mr_frame_desc* frames, void* const* pyramids, int n, void* ws,
+                                 size_t ws_bytes, void* plan, size_t plan_bytes, void* staging,
+                                 size_t staging_bytes, void* stream);
+
 /* How a batch's launches are shaped.  mr_batch_setup puts the defaults (all
  * zero) in the plan.  Every choice gives bit-identical outputs; only the time
  * differs.

@@ -972,6 +972,7 @@ struct BatchPlan {
     uint32_t magic;
     int n, effect, ndt, cdt, S, C;
     bool c16, m4_ok, wide_ok;
+    bool cached;  // evaluation and merge on resident mask pyramids only
     mr_batch_config cfg;
     const EdgeArgs* te;
     const LeanArgs* tl;
@@ -1043,7 +1044,9 @@ int check_batch(const mr_frame_desc* fr, int n, Geo* geos) {
     return MR_OK;
 }
 
-BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos) {
+// cached: the frames' mask pyramids live elsewhere (resident), the
+// workspace holds only their per-frame scratch
+BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos, bool cached = false) {
     BatchLayout L{};
     size_t off = 0;
     auto take = [&](size_t nb) {
@@ -1056,7 +1059,10 @@ BatchLayout batch_layout(const mr_frame_desc* fr, int n, const Geo* geos) {
     L.tv = take((fr[0].effect == MR_EFFECT_SSAO ? sizeof(SsaoArgs) : sizeof(SsgiArgs)) * n);
     L.tm = take(sizeof(LeanMergeArgs) * n);
     L.bases = take(sizeof(unsigned) * (kBatchTables * (MR_MAX_BATCH + 1) + kBatchCounters + kFusedCounters));
-    for (int k = 0; k < n; ++k) L.frames[k] = take(lean_layout(geos[k], fr[k].effect).bytes);
+    for (int k = 0; k < n; ++k) {
+        const LeanLayout f = lean_layout(geos[k], fr[k].effect);
+        L.frames[k] = take(cached ? f.scratch : f.bytes);
+    }
     L.bytes = off;
     return L;
 }
@@ -1077,6 +1083,9 @@ int check_config(const BatchPlan& P, const mr_batch_config& c) {
     if (c.merge_generic != 0 && c.merge_generic != 1)
         return fail(MR_E_PARAM, "merge_generic %d not 0 or 1", c.merge_generic);
     if (c.persistent != 0 && c.persistent != 1) return fail(MR_E_PARAM, "persistent %d not 0 or 1", c.persistent);
+    if (P.cached && (c.persistent || c.eval_queue))
+        return fail(MR_E_PARAM, "a batch on resident mask pyramids runs staged with fixed evaluation strides "
+                                "(persistent = 0, eval_queue = 0)");
     if (c.persistent && !fused_ok(P))
         return fail(MR_E_PARAM, "the persistent launch needs frames of at most 4 levels and at most %d samples",
                     kFusedSamples);
@@ -1122,11 +1131,13 @@ int run_plan(const BatchPlan& P, hipStream_t s) {
     if (c.persistent) return run_fused(P, s);
     const int et = c.edge_tile;
     const bool wide = et == 0 && P.wide_ok;
-    if (launch_edges_batch(P.te, P.edge_base[et], P.edge_tx[et], P.n, P.edge_total[et], P.ndt, false, wide,
-                           P.queue, s) != hipSuccess)
-        return fail(MR_E_DEVICE, "batched edge kernel launch failed");
-    if (launch_lean_masks_batch(P.tl, P.rank_base, P.n, P.rank_total, s) != hipSuccess)
-        return fail(MR_E_DEVICE, "batched rank kernel launch failed");
+    if (!P.cached) {
+        if (launch_edges_batch(P.te, P.edge_base[et], P.edge_tx[et], P.n, P.edge_total[et], P.ndt, false, wide,
+                               P.queue, s) != hipSuccess)
+            return fail(MR_E_DEVICE, "batched edge kernel launch failed");
+        if (launch_lean_masks_batch(P.tl, P.rank_base, P.n, P.rank_total, s) != hipSuccess)
+            return fail(MR_E_DEVICE, "batched rank kernel launch failed");
+    }
     const BatchSchedule bs{c.eval_queue != 0, c.eval_blocks_per_cu, P.queue};
     hipError_t e;
     if (P.effect == MR_EFFECT_SSAO)
@@ -1565,14 +1576,19 @@ namespace {
 // mr_batch_setup and mr_batch_setup_async: the tables are built in `stage`
 // (host memory of BL.frames[0] bytes) and copied to the start of ws on the
 // stream; wait: the call returns after the copy (stage may be freed then)
-int batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan, size_t plan_bytes,
-                uint8_t* stage, size_t stage_bytes, bool wait, hipStream_t s) {
+int batch_setup(const mr_frame_desc* frames, void* const* pyramids, int n, void* ws, size_t ws_bytes, void* plan,
+                size_t plan_bytes, uint8_t* stage, size_t stage_bytes, bool wait, hipStream_t s) {
     Geo geos[MR_MAX_BATCH];
     int st = check_batch(frames, n, geos);
     if (st) return st;
     if (!plan) return fail(MR_E_NULL, "plan is NULL");
     if (plan_bytes < MR_BATCH_PLAN_BYTES) return fail(MR_E_PARAM, "plan needs %d bytes", MR_BATCH_PLAN_BYTES);
-    const BatchLayout BL = batch_layout(frames, n, geos);
+    const bool cached = pyramids != nullptr;
+    for (int k = 0; cached && k < n; ++k) {
+        if (!pyramids[k]) return fail(MR_E_NULL, "frame %d: pyramid is NULL", k);
+        if (misaligned(pyramids[k])) return fail(MR_E_PARAM, "frame %d: pyramid is not 16-byte aligned", k);
+    }
+    const BatchLayout BL = batch_layout(frames, n, geos, cached);
     if (!ws || ws_bytes < BL.bytes) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, BL.bytes);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
     if (!stage) return fail(MR_E_NULL, "staging is NULL");
@@ -1598,6 +1614,7 @@ int batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, v
     unsigned* px = table(7);  // the counters follow, zero
     BatchPlan P{};
     P.magic = kBatchMagic;
+    P.cached = cached;
     P.n = n;
     P.effect = effect;
     P.ndt = frames[0].g.normal_dtype;
@@ -1610,7 +1627,11 @@ int batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, v
         const mr_frame_desc& d = frames[k];
         const void* params = effect == MR_EFFECT_SSAO ? (const void*)d.ssao : (const void*)d.ssgi;
         LeanPlan L;
-        build_lean(&d, geos[k], params, b + BL.frames[k], b + BL.frames[k] + lean_layout(geos[k], effect).pyramid, L);
+        uint8_t* const fb = b + BL.frames[k];
+        if (cached)
+            build_lean(&d, geos[k], params, static_cast<uint8_t*>(pyramids[k]), fb, L);
+        else
+            build_lean(&d, geos[k], params, fb, fb + lean_layout(geos[k], effect).pyramid, L);
         te[k] = L.ea;
         tl[k] = L.la;
         if (effect == MR_EFFECT_SSAO)
@@ -1685,14 +1706,27 @@ int mr_batch_setup(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes
     const int st = check_batch(frames, n, geos);
     if (st) return st;
     std::vector<uint8_t> host(batch_layout(frames, n, geos).frames[0]);
-    return batch_setup(frames, n, ws, ws_bytes, plan, plan_bytes, host.data(), host.size(), true,
+    return batch_setup(frames, nullptr, n, ws, ws_bytes, plan, plan_bytes, host.data(), host.size(), true,
                        static_cast<hipStream_t>(stream));
 }
 
 int mr_batch_setup_async(const mr_frame_desc* frames, int n, void* ws, size_t ws_bytes, void* plan,
                          size_t plan_bytes, void* staging, size_t staging_bytes, void* stream) {
-    return batch_setup(frames, n, ws, ws_bytes, plan, plan_bytes, static_cast<uint8_t*>(staging), staging_bytes, false,
-                       static_cast<hipStream_t>(stream));
+    return batch_setup(frames, nullptr, n, ws, ws_bytes, plan, plan_bytes, static_cast<uint8_t*>(staging),
+                       staging_bytes, false, static_cast<hipStream_t>(stream));
+}
+
+size_t mr_batch_cached_workspace_bytes(const mr_frame_desc* frames, int n) {
+    Geo geos[MR_MAX_BATCH];
+    if (check_batch(frames, n, geos)) return 0;
+    return batch_layout(frames, n, geos, true).bytes;
+}
+
+int mr_batch_setup_cached(const mr_frame_desc* frames, void* const* pyramids, int n, void* ws, size_t ws_bytes,
+                          void* plan, size_t plan_bytes, void* staging, size_t staging_bytes, void* stream) {
+    if (!pyramids) return fail(MR_E_NULL, "pyramids are NULL");
+    return batch_setup(frames, pyramids, n, ws, ws_bytes, plan, plan_bytes, static_cast<uint8_t*>(staging),
+                       staging_bytes, false, static_cast<hipStream_t>(stream));
 }
 
 int mr_batch_run(const void* plan, void* stream) {

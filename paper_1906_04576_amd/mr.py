@@ -153,6 +153,10 @@ SIGNATURES = {
     "mr_batch_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mr_batch_config), _P]),
     "mr_batch_check": (ctypes.c_int, [_P, _P]),
     "mr_batch_staging_bytes": (ctypes.c_size_t, [ctypes.POINTER(mr_frame_desc), ctypes.c_int]),
+    "mr_batch_cached_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mr_frame_desc), ctypes.c_int]),
+    "mr_batch_setup_cached": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.c_int, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P,
+                                             ctypes.c_size_t, _P]),
     "mr_batch_setup_async": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), ctypes.c_int, _P, ctypes.c_size_t, _P,
                                             ctypes.c_size_t, _P, ctypes.c_size_t, _P]),
     "mr_frame_workspace_layout": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
@@ -821,26 +825,39 @@ class BatchSlot:
         self._keep = None
 
     @staticmethod
-    def sizes(effect, frames, mp: MaskParams, params, level_dtype=torch.float32) -> tuple:
-        """(workspace bytes, staging bytes) of a batch of these frames."""
+    def sizes(effect, frames, mp: MaskParams, params, level_dtype=torch.float32, cached=False) -> tuple:
+        """(workspace bytes, staging bytes) of a batch of these frames
+        (cached: on resident pyramids, scratch only)."""
         eff = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         descs, _, _ = _batch_descs(eff, frames, mp, params, level_dtype)
-        nws = lib().mr_batch_workspace_bytes(descs, len(frames))
+        fn = lib().mr_batch_cached_workspace_bytes if cached else lib().mr_batch_workspace_bytes
+        nws = fn(descs, len(frames))
         nst = lib().mr_batch_staging_bytes(descs, len(frames))
         if nws == 0 or nst == 0:
             _check(MR_E_PARAM)
         return int(nws), int(nst)
 
-    def run(self, effect, frames, mp: MaskParams, params, stream=None, level_dtype=torch.float32):
+    def run(self, effect, frames, mp: MaskParams, params, stream=None, level_dtype=torch.float32, pyramids=None):
+        """pyramids: per frame a device tensor holding that frame's built
+        mask pyramid (mr_batch_setup_cached: evaluation and merge only)."""
         eff = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         descs, outs, keep = _batch_descs(eff, frames, mp, params, level_dtype)
         if stream is not None and stream != torch.cuda.current_stream():
             self.workspace.record_stream(stream)
             for o in outs:
                 o.record_stream(stream)
-        _check(lib().mr_batch_setup_async(descs, len(frames), _ptr(self.workspace), self.workspace.numel(),
-                                          ctypes.cast(self.plan, ctypes.c_void_p), MR_BATCH_PLAN_BYTES,
-                                          _ptr(self.staging), self.staging.numel(), _stream(stream)))
+            for t in pyramids or ():
+                t.record_stream(stream)
+        if pyramids is not None:
+            pp = (ctypes.c_void_p * len(frames))(*[t.data_ptr() for t in pyramids])
+            keep = keep + [pyramids, pp]
+            _check(lib().mr_batch_setup_cached(descs, pp, len(frames), _ptr(self.workspace), self.workspace.numel(),
+                                               ctypes.cast(self.plan, ctypes.c_void_p), MR_BATCH_PLAN_BYTES,
+                                               _ptr(self.staging), self.staging.numel(), _stream(stream)))
+        else:
+            _check(lib().mr_batch_setup_async(descs, len(frames), _ptr(self.workspace), self.workspace.numel(),
+                                              ctypes.cast(self.plan, ctypes.c_void_p), MR_BATCH_PLAN_BYTES,
+                                              _ptr(self.staging), self.staging.numel(), _stream(stream)))
         _check(lib().mr_batch_run(ctypes.cast(self.plan, ctypes.c_void_p), _stream(stream)))
         self._keep = (descs, keep)  # the frame descriptors' targets stay alive until the next batch
         return outs

@@ -185,9 +185,11 @@ class Server:
     budget for the working memory of the requests in flight.  batch_max >= 2:
     when a slot frees up, the oldest pending request takes with it up to
     batch_max - 1 other arrived requests of the same effect (SSAO or SSGI,
-    compact path), and they run as one batch (mr_batch_setup_async, one
-    launch per stage for all of them; the masks are built afresh); a request
-    that finds no partner runs alone as before."""
+    compact path), and they run as one batch with one launch per stage for
+    all of them.  With resident pyramids only requests whose pyramid is
+    built are batched, and the batch evaluates and merges on those pyramids
+    (mr_batch_setup_cached); without, the batch builds its masks
+    (mr_batch_setup_async).  A request that finds no partner runs alone."""
 
     def __init__(self, pool: Pool, slots: int = 4, budget_bytes: int = 64 << 30, multires: bool = True,
                  level_dtype=torch.float32, keep_outputs: bool = False, resident_masks: bool = True,
@@ -211,7 +213,7 @@ class Server:
                     continue
                 big = max(ks, key=lambda k: pool.scenes[k].W * pool.scenes[k].H)
                 w, t = mr.BatchSlot.sizes(e, [self._frame(big, e)] * self.batch_max, pool.mp[e],
-                                          pool.params(e, pool.scenes[big]), level_dtype)
+                                          pool.params(e, pool.scenes[big]), level_dtype, cached=self.cached)
                 nws, nst = max(nws, w), max(nst, t)
             self.slots_b = [mr.BatchSlot(nws, nst, pool.device) for _ in range(slots)]
             self.batch_ws_bytes = nws
@@ -222,7 +224,12 @@ class Server:
                     out=out)
 
     def _batchable(self, req: Request) -> bool:
-        return self.batch_max >= 2 and req.effect in ("ssao", "ssgi") and self.pool.compact(req.scene, req.effect)
+        if self.batch_max < 2 or req.effect not in ("ssao", "ssgi") or not self.pool.compact(req.scene, req.effect):
+            return False
+        if self.cached:  # its pyramid must be built (the first request builds it alone)
+            pyr = self.pool.pyramids.get((req.scene, req.effect))
+            return pyr is not None and pyr.built
+        return True
 
     def _out(self, req: Request, st):
         sc = self.pool.scenes[req.scene]
@@ -263,8 +270,16 @@ class Server:
         e = reqs[0].effect
         outs = [self._out(r, st) for r in reqs]
         frames = [self._frame(r.scene, e, o) for r, o in zip(reqs, outs)]
+        pyrs = None
+        if self.cached:
+            pyrs = []
+            for r in reqs:
+                pyr = self.pool.pyramids[(r.scene, e)]
+                if pyr.ready is not None:
+                    st.wait_event(pyr.ready)  # built on another slot
+                pyrs.append(pyr.mem)
         self.slots_b[slot].run(e, frames, self.pool.mp[e], self.pool.params(e, self.pool.scenes[reqs[0].scene]),
-                               stream=st, level_dtype=self.level_dtype)
+                               stream=st, level_dtype=self.level_dtype, pyramids=pyrs)
         ev = torch.cuda.Event()
         ev.record(st)
         self.batched += len(reqs)

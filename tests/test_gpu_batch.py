@@ -260,3 +260,28 @@ def test_async_setup_in_a_reused_slot():
         st.synchronize()
         for f, o in zip(fr, outs):
             assert torch.equal(o, alone("ssgi", f, mp, p))
+
+
+def test_batch_on_resident_pyramids():
+    """mr_batch_setup_cached: frames whose pyramids mr_frame_cached built,
+    evaluated and merged as one batch, equal the frames alone."""
+    for effect in ("ssao", "ssgi"):
+        mp = mask_params(effect)
+        _, _, p = effect_params(effect)
+        fr = frames_for(effect, SIZES)
+        pyrs = []
+        for f in fr:
+            H, W = f["depth"].shape
+            npyr, nscr = mr.mr_pyramid_bytes(W, H, f["focal"], mp, mr.EFFECTS[effect])
+            pyr = torch.empty(npyr, dtype=torch.uint8, device=DEV)
+            mr.CachedFrameRunner(effect, f["depth"], f["normal"], f["focal"], mp, pyr, color=f.get("color"),
+                                 params=p)(build=True)
+            pyrs.append(pyr)
+        nws, nst = mr.BatchSlot.sizes(effect, fr, mp, p, cached=True)
+        assert nws < mr.BatchSlot.sizes(effect, fr, mp, p)[0]
+        slot = mr.BatchSlot(nws, nst)
+        log(f"[gpu] {effect} batch on resident pyramids")
+        outs = slot.run(effect, fr, mp, p, pyramids=pyrs)
+        torch.cuda.synchronize()
+        for f, o in zip(fr, outs):
+            assert torch.equal(o, alone(effect, f, mp, p))
