@@ -227,39 +227,6 @@ def serving(qps=4000.0, seconds=1.5):
     return out
 
 
-def oracle_ssao_threads(depth, normal, focal, omp, op, pool, nthreads, multires=True):
-    """The oracle's SSAO frame with its per-texel estimator split over
-    threads (numpy releases the interpreter lock in its array loops): the
-    mask pyramid and the merge as in oracle.frame, every level's texels cut
-    into nthreads runs evaluated by oracle.ssao_texels.  Texels are
-    independent, so the image is bit-identical to oracle.frame's."""
-    import oracle
-
-    def level(zi, ni, i, sel):
-        Hi, Wi = zi.shape
-        ys, xs = np.divmod(np.arange(Hi * Wi), Wi) if sel is None else np.nonzero(sel)
-        out = np.full((Hi, Wi), np.nan, np.float32)
-        # runs of at least 64K texels: smaller arrays spend their time in the
-        # interpreter, which the threads share
-        nrun = max(1, min(nthreads, len(xs) // 65536))
-        runs = [r for r in np.array_split(np.arange(len(xs)), nrun) if len(r)]
-        vals = pool.map(lambda r: oracle.ssao_texels(zi, ni, focal, i, xs[r], ys[r], op), runs)
-        for r, v in zip(runs, vals):
-            out[ys[r], xs[r]] = v
-        return out
-
-    if not multires:
-        return level(depth, normal, 1, None)
-    E = oracle.edge_image(depth, normal, omp.depth_ratio, omp.normal_cos)
-    pyr = oracle.build_pyramid(E, omp)
-    L = pyr.levels[-1]
-    lo = {i: level(oracle.level_sample(depth, i), oracle.level_sample(normal, i), i,
-                   None if i == L else pyr.stencil[i]) for i in pyr.levels}
-    H, W = depth.shape
-    return oracle.upsample_merge(W, H, pyr.levels, {i: omp.weight[i - 1] for i in pyr.levels}, pyr.alpha,
-                                 pyr.stencil, lo)
-
-
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -310,7 +277,10 @@ def main():
         """Throughput: `steps` frames back to back, bracketed by device
         synchronisations and nothing else on the stream.  Latency: the same
         frames again, each between two timing events (device-scope release);
-        each event adds a few microseconds of its own to the stream."""
+        each event adds a few microseconds of its own to the stream.  Host
+        latency: the same frames once more, each from before its ctypes call
+        to the return of a device synchronisation after it (the submission
+        alone is the time until the call returns)."""
         for k in range(warm):
             runners[k % nf]()
         torch.cuda.synchronize()
@@ -327,7 +297,14 @@ def main():
             mr.record(ev[k][1], stream)
         torch.cuda.synchronize()
         lat = np.array([a.elapsed_ms(b) for a, b in ev])
-        return wall, lat
+        host = np.zeros((steps, 2))
+        for k in range(steps):
+            t0 = time.perf_counter()
+            runners[k % nf]()
+            t1 = time.perf_counter()
+            torch.cuda.synchronize()
+            host[k] = (t1 - t0, time.perf_counter() - t0)
+        return wall, lat, host * 1e3
 
     def concurrent(multires, streams, steps):
         """Throughput with frames spread round robin over `streams` HIP
@@ -349,13 +326,13 @@ def main():
         return (time.perf_counter() - t_start) / steps
 
     if args.plain:
-        wall, lat = timed(plain, args.steps, args.warmup)
+        wall, lat, _ = timed(plain, args.steps, args.warmup)
         log(f"[bench] plain {args.steps} frames {wall * 1e3 / args.steps:.3f} ms/frame")
         return
 
-    wall_m, lat_m = timed(multi, args.steps, args.warmup)
+    wall_m, lat_m, host_m = timed(multi, args.steps, args.warmup)
     log(f"[bench] multi-res: {wall_m * 1e3 / args.steps:.3f} ms/frame")
-    wall_p, lat_p = timed(plain, args.steps, args.warmup)
+    wall_p, lat_p, host_p = timed(plain, args.steps, args.warmup)
     log(f"[bench] plain:     {wall_p * 1e3 / args.steps:.3f} ms/frame")
 
     npx = W * H
@@ -549,49 +526,61 @@ def main():
     pcss = None if args.no_pcss else pcss_4k(dev)
     serving_res = None if args.no_serving else serving()
 
-    # ---------------- CPU oracle on a bounded sample ----------------
+    # ---------------- CPU oracle: modes A and B at 1080p and 4K; quality at 1080p ----------------
+    # The oracle runs in a child process that never touches the GPU
+    # (oracle.timing): one warm-up and three runs of the multi-resolution
+    # and naive frame of configuration 0's scene and camera, in one process
+    # on one thread (mode A) and in row bands over one process per core the
+    # host gives this job (mode B, bit-identical).  Its 1080p images are
+    # compared with this path's at the same inputs.
     cpu = None
-    cpu_threads = None
+    cpu_protocol = None
+    quality_1080p = None
     if not args.no_cpu_baseline:
-        import oracle
-        omp = oracle.MaskParams(num_levels=4, level_enable=0xF, sigma2=mp.sigma2, weight=mp.weight,
-                                normal_cos=float(np.float32(mp.normal_cos)))
-        op = oracle.SSAOParams(K, args.radius, 0.02)
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):  # numpy's elementwise work is single-threaded; pin any BLAS too
+        import subprocess
+        import tempfile
+        qW, qH = 1920, 1080
+        gbq = scenegen.render_gbuffer(scenegen.make_scene(1, 200, 50), scenegen.orbit_view(0), qW, qH)
+        dq, nq = torch.from_numpy(gbq.depth).to(dev), torch.from_numpy(gbq.normal).to(dev)
+        gq = {key: mr.FrameRunner("ssao", dq, nq, gbq.focal, mp, key == "multires", params=sp)().cpu().numpy()
+              for key in ("multires", "plain")}
+        with tempfile.TemporaryDirectory() as tmp:
+            cmd = [sys.executable, "-m", "oracle.timing", "--resolutions", f"{qW}x{qH},{W}x{H}",
+                   "--samples", str(S), "--radius", str(args.radius), "--seed", "1", "--camera", "0",
+                   "--save", tmp, "--save-res", f"{qW}x{qH}"]
+            log("[bench] cpu oracle: " + " ".join(cmd[1:]))
             t_c = time.perf_counter()
-            done = 0
-            for k in range(nf):  # about 20 s of CPU work
-                gb = frames[k]["gb"]
-                oracle.frame("ssao", gb.depth, gb.normal, gb.focal, omp, op)
-                done += 1
-                if time.perf_counter() - t_c > 20:
-                    break
-            dt = time.perf_counter() - t_c
-        cpu = {"value": round(npx * done / dt / 1e6, 4), "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} full multi-resolution SSAO frames at {W}x{H} (configurations 0..{done - 1}), "
-                         f"numpy single thread, {dt:.1f}s"}
-        log(f"[bench] cpu oracle: {cpu['value']} Mpixels/s")
-        # the same oracle with its per-texel estimator over the host's cores
-        # (the box's share of them, at most 16), multi-resolution and naive
-        from concurrent.futures import ThreadPoolExecutor
-        nthr = min(len(os.sched_getaffinity(0)), 16)
-        cpu_threads = {"cores": nthr, "host_cores_visible": len(os.sched_getaffinity(0)), "kind": "oracle",
-                       "unit": "Mpixels/s"}
-        with threadpool_limits(limits=1), ThreadPoolExecutor(nthr) as pool:
-            for multires in (True, False):
-                t_c = time.perf_counter()
-                done = 0
-                for k in range(nf):
-                    gb = frames[k]["gb"]
-                    oracle_ssao_threads(gb.depth, gb.normal, gb.focal, omp, op, pool, nthr, multires)
-                    done += 1
-                    if time.perf_counter() - t_c > 10:
-                        break
-                dt = time.perf_counter() - t_c
-                cpu_threads["multires" if multires else "plain"] = {
-                    "value": round(npx * done / dt / 1e6, 4), "frames": done, "seconds": round(dt, 2)}
-        log(f"[bench] cpu oracle on {nthr} threads: {cpu_threads}")
+            pr = subprocess.run(cmd, cwd=os.path.dirname(os.path.abspath(__file__)), stdout=subprocess.PIPE,
+                                text=True, timeout=900)
+            if pr.returncode != 0:
+                raise RuntimeError(f"oracle timing exited with {pr.returncode}")
+            cpu_protocol = json.loads(pr.stdout.strip().splitlines()[-1])
+            cpu_protocol["seconds"] = round(time.perf_counter() - t_c, 1)
+            ref = {key: np.load(os.path.join(tmp, f"oracle_{qW}x{qH}_{key}.npy")) for key in ("multires", "plain")}
+        dm = gq["multires"].astype(np.float64)
+        quality_1080p = {
+            "resolution": f"{qW}x{qH}",
+            "inputs": cpu_protocol["inputs"],
+            "max_abs_multires_vs_oracle_multires": float(np.max(np.abs(dm - ref["multires"]))),
+            "max_abs_plain_vs_oracle_plain": float(np.max(np.abs(gq["plain"].astype(np.float64) - ref["plain"]))),
+            "mad_multires_vs_oracle_plain": round(float(np.mean(np.abs(dm - ref["plain"]))), 6),
+            "rms_multires_vs_oracle_plain": round(float(np.sqrt(np.mean((dm - ref["plain"]) ** 2))), 6),
+        }
+        ma = cpu_protocol["resolutions"][f"{W}x{H}"]["mode_a"]
+        cpu = {"value": ma["multires_mpixels_s"], "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
+               "sample": f"one multi-resolution SSAO frame at {W}x{H} (configuration 0: scene seed 1, camera 0), "
+                         f"oracle.frame in one process on one thread, 1 warm-up + median of 3 runs "
+                         f"({', '.join(f'{t:.2f}' for t in ma['multires_s'])} s)"}
+        log(f"[bench] cpu oracle: {json.dumps(cpu_protocol)}")
+        log(f"[bench] quality at 1080p against the oracle: {quality_1080p}")
+
+    cfg = np.arange(args.steps) % nf
+    per_cfg = [float(np.median(lat_p[cfg == c]) / np.median(lat_m[cfg == c])) for c in range(nf) if np.any(cfg == c)]
+
+    def host_latency(h):
+        return {"p50_ms": round(float(np.percentile(h[:, 1], 50)), 4),
+                "p99_ms": round(float(np.percentile(h[:, 1], 99)), 4),
+                "submit_p50_us": round(float(np.percentile(h[:, 0], 50)) * 1e3, 1)}
 
     res = {
         "metric": "Mpixels/s multi-res vs full-res SSAO at 4K (HBM %); p50/p99 frame latency",
@@ -616,6 +605,8 @@ def main():
         "p99_ms": round(float(np.percentile(lat_m, 99)), 4),
         "plain_p50_ms": round(float(np.percentile(lat_p, 50)), 4),
         "plain_p99_ms": round(float(np.percentile(lat_p, 99)), 4),
+        "speedup_per_config_mean": round(float(np.mean(per_cfg)), 3),
+        "host_latency": {"multires": host_latency(host_m), "plain": host_latency(host_p)},
         "mad_vs_plain": round(float(np.mean(mads)), 6) if mads else None,
         "rms_vs_plain": round(float(np.mean(rmss)), 6) if rmss else None,
         "concurrent": conc,
@@ -626,8 +617,9 @@ def main():
         "sweeps": sweeps,
         "pcss_4k": pcss,
         "serving": serving_res,
+        "quality_1080p_vs_oracle": quality_1080p,
         "cpu_baseline": cpu,
-        "cpu_baseline_threads": cpu_threads,
+        "cpu_protocol": cpu_protocol,
     }
     print(json.dumps(res), flush=True)
 
