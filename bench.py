@@ -16,9 +16,11 @@ speedup.  Progress goes to stderr; stdout gets one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -28,10 +30,8 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 # FP32 arithmetic pipe: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-fused,
 # non-packed FP32 add / multiply / divide step per lane and clock (the
 # bit-exact contract rules out FMA contraction and packed FP32): 157.3 TFLOP/s
-# / 4.  A stream of independent v_add_f32 / v_mul_f32 / v_fma_f32 measured
-# 38.7 T lane-ops/s on the box.  Integer, compare and select instructions
-# issue at twice that rate there (measured 64.5 T), so they are not counted
-# against this pipe.
+# / 4.  A stream of independent v_add_f32 ran at 37.7 T lane-ops/s on the box
+# (4.17 cycles per wave64 instruction).
 FP32_PIPE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic FP32 arithmetic of the SSAO estimator (Sec. 2.4 reading):
 # per sample the sample point (9 multiplies + 9 adds), the reciprocal of its
@@ -44,18 +44,53 @@ SSAO_FP32_PER_SAMPLE = 28
 SSAO_FP32_PER_TEXEL = 31
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (profiles/ssao_4k_hbm_counters.md), scaled by the
-# copy-kernel calibration; None once the kernel changes, until re-measured
-TRAFFIC_BYTES = {"k_ssao_multi": 61866903}
-# VALU issue of the dominant kernel from the SQ_INSTS_VALU_* counters
-# (profiles/ssao_4k_eval_valu_issue.md): wave instructions per launch of the
-# FP32 arithmetic classes (add, multiply, FMA, transcendental, conversion; 4
-# cycles per wave64 instruction) and of all other VALU instructions (2
-# cycles); None once the kernel changes, until re-measured
-VALU_ISSUE = {"k_ssao_multi": {"fp32_arith": 12909635, "other": 7702172}}
+# copy-kernel calibration
+TRAFFIC_BYTES = {"k_ssao_multi": 61843937}
+# VALU wave instructions per launch (SQ_INSTS_VALU,
+# profiles/ssao_4k_eval_valu_issue.md) of the multi-resolution evaluation and
+# of the naive pass, which runs the same per-sample code densely over every
+# pixel: the ratio of their instruction rates is the launch's VALU issue
+# relative to the rate that code sustains
+VALU_INSTS = {"k_ssao_multi": 20600129, "k_ssao_plain": 206263552}
+# the counters above hold for the kernels built from these sources only: the
+# SHA-256 of their .hip file and every header it includes
+# (source_closure_sha256) when they were taken.  Any other hash reports them
+# as null.
+COUNTER_SOURCES = {"k_ssao_multi": ("k_ssao.hip", "a4975c7650d0d45fb5a07638cd1d67208a71a0c565f20742730b1715ee30ac02")}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_closure_sha256(name, dirs=None):
+    """SHA-256 over a kernel source of the library and every header it
+    includes with quotes, transitively (files in name order, each preceded
+    by its name); files are looked up in `dirs` (default: the library's
+    sources and public headers)."""
+    if dirs is None:
+        root = os.path.dirname(os.path.abspath(__file__))
+        dirs = [os.path.join(root, "paper_1906_04576_amd", "csrc"), os.path.join(root, "include")]
+    seen, todo = {}, [name]
+    while todo:
+        n = todo.pop()
+        if n in seen:
+            continue
+        path = next((os.path.join(d, n) for d in dirs if os.path.isfile(os.path.join(d, n))), None)
+        if path is None:
+            raise FileNotFoundError(f"{n} (included from the sources of {name})")
+        with open(path, "rb") as f:
+            seen[n] = f.read()
+        todo += [m.decode() for m in re.findall(rb'^\s*#\s*include\s+"([^"]+)"', seen[n], re.M)]
+    h = hashlib.sha256()
+    for n in sorted(seen):
+        h.update(n.encode() + b"\0" + seen[n])
+    return h.hexdigest()
+
+
+def counters_current(kernel):
+    src, digest = COUNTER_SOURCES[kernel]
+    return source_closure_sha256(src) == digest
 
 
 def parse():
@@ -494,20 +529,24 @@ def main():
         # dominant kernel of the multi-resolution frame: the per-level SSAO
         # evaluation, one launch per frame bracketed by events [1] and [2]
         achieved = ops_multi / t_eval / 1e12
+        fresh = counters_current("k_ssao_multi")
+        if not fresh:
+            log("[bench] the evaluation kernel's sources changed since its counters were taken: "
+                "traffic and VALU issue are reported as null")
         roofline = {"kernel": "k_ssao<float, true, true> (all levels of one frame in one launch)", "bound": "alu",
                     "achieved": round(achieved, 3), "peak": round(FP32_PIPE_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                    "frac": round(achieved / FP32_PIPE_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi"),
-                    "launch_ms": stages["multi_eval_ms"],
+                    "frac": round(achieved / FP32_PIPE_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi") if fresh else None,
+                    "launch_ms": stages["multi_eval_ms"], "counters_match_sources": fresh,
                     "basis": f"algorithmic FP32 arithmetic ({SSAO_FP32_PER_SAMPLE} per sample, "
                              f"{SSAO_FP32_PER_TEXEL} per texel) of {int(evaluated)} evaluated texels per launch "
                              "against the non-fused, non-packed FP32 pipe (157.3 TFLOP/s / 4)"}
-        vi = VALU_ISSUE.get("k_ssao_multi")
-        if vi:
-            # counter-backed issue use: FP32 arithmetic wave instructions at 4
-            # cycles, the other VALU instructions at 2, against every SIMD's
-            # cycles over the launch
-            cyc = 4 * vi["fp32_arith"] + 2 * vi["other"]
-            roofline["valu_issue_frac"] = round(cyc / (1024 * 2.4e9 * t_eval), 4)
+        roofline["valu_rate_vs_plain"] = None
+        if fresh:
+            # VALU wave instructions per second of this launch against the
+            # naive pass's, both from the counters and this run's launch times
+            rate_m = VALU_INSTS["k_ssao_multi"] / t_eval
+            rate_p = VALU_INSTS["k_ssao_plain"] / (stages["plain_eval_ms"] * 1e-3)
+            roofline["valu_rate_vs_plain"] = round(rate_m / rate_p, 4)
         log("[bench] stages (ms): " + ", ".join(f"{k}={v}" for k, v in stages.items() if k.endswith("_ms")))
 
     # ---------------- batched uneven SSGI frames (graph-replayed batch) ----------------

@@ -33,33 +33,43 @@ __device__ __forceinline__ bool ndot_lt(const float* a, const float* b, float cn
 template <typename NT>
 struct NormalRow;
 
+// Raw loads of normal components (raw4: four consecutive pixels, raw1: one)
+// and their conversion to FP32; the conversion is kept apart from the load so
+// that a load can be issued long before its value is used.
 template <>
 struct NormalRow<float> {
     static constexpr unsigned kSize = 4;
-    __device__ static void load4(__amdgpu_buffer_rsrc_t r, unsigned e, float* o) {
-        const float4 v = buf_f4(r, e * 4u);
+    typedef float4 raw4;
+    typedef float raw1;
+    __device__ static raw4 ld4(__amdgpu_buffer_rsrc_t r, unsigned e) { return buf_f4(r, e * 4u); }
+    __device__ static raw1 ld1(__amdgpu_buffer_rsrc_t r, unsigned e) { return buf_f1(r, e * 4u); }
+    __device__ static void cvt4(const raw4& v, float* o) {
         o[0] = v.x;
         o[1] = v.y;
         o[2] = v.z;
         o[3] = v.w;
     }
-    __device__ static float load1(__amdgpu_buffer_rsrc_t r, unsigned e) { return buf_f1(r, e * 4u); }
+    __device__ static float cvt1(raw1 v) { return v; }
 };
 
 template <>
 struct NormalRow<_Float16> {
     static constexpr unsigned kSize = 2;
-    __device__ static void load4(__amdgpu_buffer_rsrc_t r, unsigned e, float* o) {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 v = __builtin_bit_cast(h4, __builtin_amdgcn_raw_buffer_load_b64(r, e * 2u, 0, 0));
+    typedef _Float16 raw4 __attribute__((ext_vector_type(4)));
+    typedef _Float16 raw1;
+    __device__ static raw4 ld4(__amdgpu_buffer_rsrc_t r, unsigned e) {
+        return __builtin_bit_cast(raw4, __builtin_amdgcn_raw_buffer_load_b64(r, e * 2u, 0, 0));
+    }
+    __device__ static raw1 ld1(__amdgpu_buffer_rsrc_t r, unsigned e) {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, e * 2u, 0, 0));
+    }
+    __device__ static void cvt4(const raw4& v, float* o) {
         o[0] = (float)v.x;
         o[1] = (float)v.y;
         o[2] = (float)v.z;
         o[3] = (float)v.w;
     }
-    __device__ static float load1(__amdgpu_buffer_rsrc_t r, unsigned e) {
-        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, e * 2u, 0, 0));
-    }
+    __device__ static float cvt1(raw1 v) { return (float)v; }
 };
 
 // Row shifts within the 16-lane DPP rows: lane i takes src of lane i - 1
@@ -81,86 +91,163 @@ __device__ __forceinline__ float dpp_shl1(float own, float src) {
 // that a block reads 1 KB runs of every row; levels up to 4 only (the 8 x 8
 // pooling blocks stay inside one wave).  Otherwise they are stacked (64 x 32
 // tile) and levels 5 and 6 are pooled across the waves through LDS.
-// One tile of the edge image; tile k also zeroes counter words 256 k ..
-// 256 k + 255 (those below zero_n).
-template <typename NT, bool HARD, bool BITS, bool WIDE>
-__device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, unsigned tiles_x) {
-    __shared__ uint8_t p4[4][8];
-    if (a.zero && tile * 256u + threadIdx.x < a.zero_n) a.zero[tile * 256u + threadIdx.x] = 0u;
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int x0 = WIDE ? (int)(tile % tiles_x) * (4 * kEdgeTW) + wave * kEdgeTW : (int)(tile % tiles_x) * kEdgeTW;
-    const int y0 = WIDE ? (int)(tile / tiles_x) * 8 : (int)(tile / tiles_x) * kEdgeTH;
-    const int W = a.W, H = a.H;
-    const int cg = lane & 15, rp = lane >> 4;
-    const int xb = x0 + 4 * cg, yb = y0 + (WIDE ? 0 : 8 * wave) + 2 * rp;
-    const bool any = xb < W && yb < H;
-    const unsigned plane = (unsigned)W * (unsigned)H;
+
+// Where a lane's pixels of one tile lie: a 4 x 2 pixel block at (xb, yb),
+// the clamped element offsets ro of rows yb - 1 .. yb + 2, the clamped
+// column xc of the block's four-pixel loads and the wave's clamped outer
+// columns xl = x0 - 1 and xr = x0 + 64.
+struct EdgeGeom {
+    int wave, lane, x0, y0, cg, rp, xb, yb, xc;
+    bool any;
+    unsigned ro[4], xl, xr;
+};
+
+template <bool WIDE>
+__device__ __forceinline__ EdgeGeom edge_geom(const EdgeArgs& a, unsigned tile, unsigned tiles_x) {
+    EdgeGeom g;
+    const int t = threadIdx.x;
+    g.wave = t >> 6;
+    g.lane = t & 63;
+    g.x0 = WIDE ? (int)(tile % tiles_x) * (4 * kEdgeTW) + g.wave * kEdgeTW : (int)(tile % tiles_x) * kEdgeTW;
+    g.y0 = WIDE ? (int)(tile / tiles_x) * 8 : (int)(tile / tiles_x) * kEdgeTH;
+    g.cg = g.lane & 15;
+    g.rp = g.lane >> 4;
+    g.xb = g.x0 + 4 * g.cg;
+    g.yb = g.y0 + (WIDE ? 0 : 8 * g.wave) + 2 * g.rp;
+    g.any = g.xb < a.W && g.yb < a.H;
+    g.xc = min(g.xb, a.W - 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) g.ro[r] = (unsigned)min(max(g.yb - 1 + r, 0), a.H - 1) * (unsigned)a.W;
+    g.xl = (unsigned)max(g.x0 - 1, 0);
+    g.xr = (unsigned)min(g.x0 + 64, a.W - 1);
+    return g;
+}
+
+// Everything one tile reads from memory, as loaded (normals not yet
+// converted): a lane's own rows yb and yb + 1, the wave's halo row (row
+// yb - 1 for the first row pair of the wave, yb + 2 for the last), and the
+// side columns x0 - 1 and x0 + 64 of its own rows (with WIDE only the
+// block's outer columns; the inner ones come from the neighbouring wave).
+template <typename NT, bool HARD>
+struct EdgeLoads {
+    typedef typename NormalRow<NT>::raw4 N4;
+    typedef typename NormalRow<NT>::raw1 N1;
+    float4 z[2], hz;
+    N4 n[2][3], hn[3];
+    unsigned h[2], hh;
+    float zs[2][2];
+    N1 ns[2][2][3];
+    unsigned hs[2][2];
+};
+
+// Issues every load of one tile, the block's outer side columns included,
+// before any of them is waited for.  (Loading the outer columns after the
+// exchange of the inner ones through LDS put a second memory latency on the
+// outer waves, which the exchange's barrier passed on to the whole block.)
+template <typename NT, bool HARD, bool WIDE>
+__device__ __forceinline__ void edges_load(const EdgeArgs& a, const EdgeGeom& g, EdgeLoads<NT, HARD>& L) {
+    typedef NormalRow<NT> NR;
+    const unsigned plane = (unsigned)a.W * (unsigned)a.H;
     const __amdgpu_buffer_rsrc_t rz = buf_rsrc(a.depth, plane * 4u);
     const NT* nrm = static_cast<const NT*>(a.normal);
-    const unsigned nb = plane * NormalRow<NT>::kSize;
-    const __amdgpu_buffer_rsrc_t rn0 = buf_rsrc(nrm, nb), rn1 = buf_rsrc(nrm + plane, nb),
-                                 rn2 = buf_rsrc(nrm + 2 * plane, nb);
+    const unsigned nb = plane * NR::kSize;
+    const __amdgpu_buffer_rsrc_t rn[3] = {buf_rsrc(nrm, nb), buf_rsrc(nrm + plane, nb), buf_rsrc(nrm + 2 * plane, nb)};
     const __amdgpu_buffer_rsrc_t rh = buf_rsrc(a.hard, HARD ? plane : 0u);
-    // clamped element offsets of rows yb-1 .. yb+2 and the side columns
-    const int xc = min(xb, W - 4);
-    unsigned ro[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ro[r] = (unsigned)min(max(yb - 1 + r, 0), H - 1) * (unsigned)W;
-    // Side columns xb - 1 and xb + 4 are the neighbouring lanes' pixels (the
-    // 16 lanes of a DPP row cover the wave's 64 columns of one row pair);
-    // only the wave's outer columns x0 - 1 and x0 + 64 come from elsewhere.
-    const unsigned xl = (unsigned)max(x0 - 1, 0), xr = (unsigned)min(x0 + 64, W - 1);
+    for (int r = 0; r < 2; ++r) {
+        const unsigned e = g.ro[r + 1] + (unsigned)g.xc;
+        L.z[r] = buf_f4(rz, e * 4u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L.n[r][c] = NR::ld4(rn[c], e);
+        L.h[r] = HARD ? __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0) : 0u;
+    }
+    const bool top = g.rp == 0, bot = g.rp == 3;
+    L.hz = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L.hn[c] = typename NR::raw4{};
+    L.hh = 0u;
+    if (top || bot) {
+        const unsigned e = (top ? g.ro[0] : g.ro[3]) + (unsigned)g.xc;
+        L.hz = buf_f4(rz, e * 4u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L.hn[c] = NR::ld4(rn[c], e);
+        if (HARD) L.hh = __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            L.zs[r][sd] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) L.ns[r][sd][c] = typename NR::raw1{};
+            L.hs[r][sd] = 0u;
+            // with WIDE only the block's outer columns (a wave-uniform test)
+            if (!WIDE || (sd ? g.wave == 3 : g.wave == 0)) {
+                const unsigned e = g.ro[r + 1] + (sd ? g.xr : g.xl);
+                L.zs[r][sd] = buf_f1(rz, e * 4u);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) L.ns[r][sd][c] = NR::ld1(rn[c], e);
+                if (HARD) L.hs[r][sd] = __builtin_amdgcn_raw_buffer_load_b8(rh, e, 0, 0);
+            }
+        }
+}
 
+// One tile of the edge image from its loads; tile k also zeroes counter
+// words 256 k .. 256 k + 255 (those below zero_n).
+template <typename NT, bool HARD, bool BITS, bool WIDE>
+__device__ __forceinline__ void edges_process(const EdgeArgs& a, const EdgeGeom& g, unsigned tile,
+                                              const EdgeLoads<NT, HARD>& L) {
+    typedef NormalRow<NT> NR;
+    __shared__ uint8_t p4[4][8];
+    if (a.zero && tile * 256u + threadIdx.x < a.zero_n) a.zero[tile * 256u + threadIdx.x] = 0u;
+    const int t = threadIdx.x, wave = g.wave, lane = g.lane, x0 = g.x0, y0 = g.y0, cg = g.cg, rp = g.rp;
+    const int xb = g.xb, yb = g.yb;
+    const bool any = g.any;
+    const int W = a.W, H = a.H;
     float z[4][4], n[4][4][3];
     float zs[2][2], ns[2][2][3];
-    unsigned hrow[4] = {0, 0, 0, 0}, hside[2][2] = {{0, 0}, {0, 0}};
-    // Rows yb - 1 .. yb + 2: a lane loads its own rows yb, yb + 1; the row
+    unsigned hrow[4] = {0u, L.h[0], L.h[1], 0u}, hside[2][2];
+    // Rows yb - 1 .. yb + 2: a lane has its own rows yb, yb + 1; the row
     // above is the second own row of the lane 16 below (the wave's row pairs
     // are consecutive) and the row below the first own row of the lane 16
-    // above, except for the wave's first and last row pair, which load the
+    // above, except for the wave's first and last row pair, which have the
     // wave's halo rows.  Every row of the wave is read once.
 #pragma unroll
     for (int r = 1; r <= 2; ++r) {
-        const unsigned e = ro[r] + (unsigned)xc;
-        const float4 zv = buf_f4(rz, e * 4u);
-        z[r][0] = zv.x;
-        z[r][1] = zv.y;
-        z[r][2] = zv.z;
-        z[r][3] = zv.w;
-        float t0[4], t1[4], t2[4];
-        NormalRow<NT>::load4(rn0, e, t0);
-        NormalRow<NT>::load4(rn1, e, t1);
-        NormalRow<NT>::load4(rn2, e, t2);
+        z[r][0] = L.z[r - 1].x;
+        z[r][1] = L.z[r - 1].y;
+        z[r][2] = L.z[r - 1].z;
+        z[r][3] = L.z[r - 1].w;
+        float t3[3][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            n[r][k][0] = t0[k];
-            n[r][k][1] = t1[k];
-            n[r][k][2] = t2[k];
-        }
-        if (HARD) hrow[r] = __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0);
+        for (int c = 0; c < 3; ++c) NR::cvt4(L.n[r - 1][c], t3[c]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) n[r][k][c] = t3[c][k];
     }
     const bool top = rp == 0, bot = rp == 3;
-    float hz[4] = {0.0f, 0.0f, 0.0f, 0.0f}, hn[4][3] = {};
-    unsigned hh = 0u;
-    if (top || bot) {
-        const unsigned e = (top ? ro[0] : ro[3]) + (unsigned)xc;
-        const float4 zv = buf_f4(rz, e * 4u);
-        hz[0] = zv.x;
-        hz[1] = zv.y;
-        hz[2] = zv.z;
-        hz[3] = zv.w;
-        float t0[4], t1[4], t2[4];
-        NormalRow<NT>::load4(rn0, e, t0);
-        NormalRow<NT>::load4(rn1, e, t1);
-        NormalRow<NT>::load4(rn2, e, t2);
+    const float hz[4] = {L.hz.x, L.hz.y, L.hz.z, L.hz.w};
+    float hn[4][3];
+    {
+        float t3[3][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            hn[k][0] = t0[k];
-            hn[k][1] = t1[k];
-            hn[k][2] = t2[k];
-        }
-        if (HARD) hh = __builtin_amdgcn_raw_buffer_load_b32(rh, e, 0, 0);
+        for (int c = 0; c < 3; ++c) NR::cvt4(L.hn[c], t3[c]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hn[k][c] = t3[c][k];
     }
+    const unsigned hh = L.hh;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            zs[r][sd] = L.zs[r][sd];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ns[r][sd][c] = NR::cvt1(L.ns[r][sd][c]);
+            hside[r][sd] = L.hs[r][sd];
+        }
     const int lup = (lane + 48) & 63, ldn = (lane + 16) & 63;  // lanes 16 below / above
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -182,16 +269,8 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
     // Side columns x0 - 1 and x0 + 64 of the own rows.  With WIDE the four
     // waves of the block sit side by side: a wave's side column is a
     // neighbouring wave's first or last column, passed through LDS; only
-    // the block's outer columns are loaded.  Otherwise every lane of a row
-    // loads them from the same address (one cache line).
-    auto load_side = [&](int r, int sd) {
-        const unsigned e = ro[r + 1] + (sd ? xr : xl);
-        zs[r][sd] = buf_f1(rz, e * 4u);
-        ns[r][sd][0] = NormalRow<NT>::load1(rn0, e);
-        ns[r][sd][1] = NormalRow<NT>::load1(rn1, e);
-        ns[r][sd][2] = NormalRow<NT>::load1(rn2, e);
-        if (HARD) hside[r][sd] = __builtin_amdgcn_raw_buffer_load_b8(rh, e, 0, 0);
-    };
+    // the block's outer columns were loaded.  Otherwise every lane of a row
+    // loaded them from the same address (one cache line).
     if (WIDE) {
         __shared__ float sidex[4][2][8][5];  // [wave][first / last column][row][z, n, hard bits]
         const int rr = 2 * rp;
@@ -213,9 +292,7 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
 #pragma unroll
             for (int sd = 0; sd < 2; ++sd) {
                 const int nw = sd ? wave + 1 : wave - 1;  // the neighbouring wave (uniform)
-                if (nw < 0 || nw > 3) {
-                    load_side(r, sd);
-                } else {
+                if (nw >= 0 && nw <= 3) {
                     const float* i = sidex[nw][1 - sd][rr + r];
                     zs[r][sd] = i[0];
                     ns[r][sd][0] = i[1];
@@ -224,12 +301,6 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
                     hside[r][sd] = __float_as_uint(i[4]);
                 }
             }
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            load_side(r, 0);
-            load_side(r, 1);
         }
     }
 #pragma unroll
@@ -387,6 +458,15 @@ __device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, uns
             if (X < a.Wi[5] && Y < a.Hi[5]) a.Ei[5][(unsigned)Y * (unsigned)a.Wi[5] + (unsigned)X] = o;
         }
     }
+}
+
+// One tile of the edge image: its loads, then the classification.
+template <typename NT, bool HARD, bool BITS, bool WIDE>
+__device__ __forceinline__ void edges_tile(const EdgeArgs& a, unsigned tile, unsigned tiles_x) {
+    const EdgeGeom g = edge_geom<WIDE>(a, tile, tiles_x);
+    EdgeLoads<NT, HARD> L;
+    edges_load<NT, HARD, WIDE>(a, g, L);
+    edges_process<NT, HARD, BITS, WIDE>(a, g, tile, L);
 }
 
 }  // namespace mr
