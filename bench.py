@@ -52,22 +52,48 @@ TRAFFIC_BYTES = {"k_ssao_multi": 61843937}
 # pixel: the ratio of their instruction rates is the launch's VALU issue
 # relative to the rate that code sustains
 VALU_INSTS = {"k_ssao_multi": 20600129, "k_ssao_plain": 206263552}
-# the counters above hold for the kernels built from these sources only: the
-# SHA-256 of their .hip file and every header it includes
-# (source_closure_sha256) when they were taken.  Any other hash reports them
-# as null.
-COUNTER_SOURCES = {"k_ssao_multi": ("k_ssao.hip", "a4975c7650d0d45fb5a07638cd1d67208a71a0c565f20742730b1715ee30ac02")}
+# the counters above hold for the kernels built from this code only: the
+# SHA-256 of the code of their .hip file and every header it includes
+# (source_closure_sha256: comments and white space aside) when they were
+# taken.  Any other hash reports them as null.
+COUNTER_SOURCES = {"k_ssao_multi": ("k_ssao.hip", "7626fccf826358a8e74be2132a04337a018d74670ab109fa1e60d95a15260e00")}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_only(text: bytes) -> bytes:
+    """C/C++ source without its comments, runs of white space as one space:
+    what a change must alter to change the compiled code."""
+    out = bytearray()
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i:i + 1]
+        if text.startswith(b"//", i):
+            j = text.find(b"\n", i)
+            i = n if j < 0 else j
+        elif text.startswith(b"/*", i):
+            j = text.find(b"*/", i + 2)
+            i = n if j < 0 else j + 2
+            out += b" "
+        elif c in (b'"', b"'"):
+            j = i + 1
+            while j < n and text[j:j + 1] != c:
+                j += 2 if text[j:j + 1] == b"\\" else 1
+            out += text[i:j + 1]
+            i = j + 1
+        else:
+            out += c
+            i += 1
+    return re.sub(rb"\s+", b" ", bytes(out)).strip()
+
+
 def source_closure_sha256(name, dirs=None):
-    """SHA-256 over a kernel source of the library and every header it
-    includes with quotes, transitively (files in name order, each preceded
-    by its name); files are looked up in `dirs` (default: the library's
-    sources and public headers)."""
+    """SHA-256 over the code (code_only) of a kernel source of the library
+    and every header it includes with quotes, transitively (files in name
+    order, each preceded by its name); files are looked up in `dirs`
+    (default: the library's sources and public headers)."""
     if dirs is None:
         root = os.path.dirname(os.path.abspath(__file__))
         dirs = [os.path.join(root, "paper_1906_04576_amd", "csrc"), os.path.join(root, "include")]
@@ -84,7 +110,7 @@ def source_closure_sha256(name, dirs=None):
         todo += [m.decode() for m in re.findall(rb'^\s*#\s*include\s+"([^"]+)"', seen[n], re.M)]
     h = hashlib.sha256()
     for n in sorted(seen):
-        h.update(n.encode() + b"\0" + seen[n])
+        h.update(n.encode() + b"\0" + code_only(seen[n]) + b"\0")
     return h.hexdigest()
 
 

@@ -47,8 +47,11 @@ __device__ __forceinline__ float ld(const T* p, long long i) {
 }
 
 // Raw buffer resource over `bytes` bytes at `p` (gfx9 family: dword 3 =
-// 0x00020000).  Every load issued through these below is kept in range by
-// clamping its offset; the hardware range check is never relied on.
+// 0x00020000).  With stride 0 the hardware checks each load's byte offset
+// against `bytes`: a load at or past the end returns 0 and makes no memory
+// access.  Most loads through these keep their offset in range by clamping;
+// the SSAO sample gathers rely on the check for off-screen samples, whose
+// values are never used.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }

@@ -1,6 +1,7 @@
 """The bench reports a kernel's stored counters only while the kernel's
-sources are the ones they were taken with: the hash covers the .hip file and
-every header it includes, transitively."""
+code is the one they were taken with: the hash covers the code of the .hip
+file and every header it includes, transitively, comments and white space
+aside."""
 import os
 import sys
 
@@ -27,8 +28,15 @@ def test_hash_covers_included_headers(tmp_path):
     _write(b, "y.h", "int v = 2;\n")              # a header two levels down
     h1 = bench.source_closure_sha256("k.hip", [str(a), str(b)])
     assert h1 != h0
-    _write(a, "x.hpp", '#pragma once\n#include "y.h"\n')  # whitespace of an include line
+    _write(b, "y.h", "int v = 2;  // a comment\n/* another */\n")  # comments and white space only
+    assert bench.source_closure_sha256("k.hip", [str(a), str(b)]) == h1
+    _write(b, "y.h", 'const char* s = "// kept"; int v = 2;\n')  # a string is code
     assert bench.source_closure_sha256("k.hip", [str(a), str(b)]) != h1
+
+
+def test_code_only():
+    src = b'int a; // c\n/* x\n y */ const char* s = "/* no */";  char q = \'\\\'\';\n\tint  b;'
+    assert bench.code_only(src) == b'int a; const char* s = "/* no */"; char q = \'\\\'\'; int b;'
 
 
 def test_missing_header_is_an_error(tmp_path):
