@@ -460,6 +460,11 @@ def main():
                          "fullres_fewer_samples_mpixels_s": round(npx / t_full / 1e6, 2),
                          "fullres_fewer_samples_samples": [int(max(1, S >> (i - 1))) for i in (1, 2, 3, 4)],
                          "fullres_fewer_samples_mad_vs_plain": round(float(np.mean(mad_full)), 6) if mad_full else None})
+        # the frame tuner (mr_frame_tune) on configuration 0: how the
+        # coarsest level's evaluation gathers its depth
+        tr = mr.FrameRunner("ssao", frames[0]["d"], frames[0]["n"], focal, mp, True, params=sp, workspace=ws)
+        halo, ms = tr.tune(reps=20)
+        variants["frame_tune"] = {"chosen_eval_halo": halo, "ms_per_eval_halo": {h: round(t, 5) for h, t in ms.items()}}
         log("[bench] variants: " + ", ".join(f"{k}={v}" for k, v in variants.items()))
 
     # ---------------- quality: multi-res vs naive on every configuration ----------------

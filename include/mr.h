@@ -350,6 +350,19 @@ MR_API int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, cons
  * ws / ws_bytes: at least mr_workspace_bytes(&d->cam, &d->mp, d->effect). */
 MR_API int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream);
 
+/* Autotuner for one frame configuration: how the evaluation of the coarsest
+ * level gathers its depth (Sec. 4.1 renders each sub-image; eval_halo above).
+ * Times mr_frame on `stream` with eval_halo = 0, 8, 16 and 24 (one warm-up
+ * run, then `reps` runs, 1..1000), skipping the values the frame does not
+ * admit (only 0 for the naive pass, effects other than SSAO and more than
+ * 256 samples), and stores the fastest in d->eval_halo.  ms, when not NULL,
+ * receives 4 floats: the milliseconds per frame of each value, -1 for one
+ * that was skipped.  d as given must be valid for mr_frame (ws of at least
+ * mr_workspace_bytes); its stage events are not recorded.  Runs the frame on
+ * its current inputs, writes d->out and waits for the stream: not for use
+ * under graph capture.  On an error d is unchanged. */
+MR_API int mr_frame_tune(mr_frame_desc* d, void* ws, size_t ws_bytes, int reps, float* ms, void* stream);
+
 /* A frame whose mask pyramid stays resident in caller memory across frames
  * (serving a static scene: the masks of Sec. 3.1 depend only on the
  * G-buffer, so requests after the first skip the mask kernels).  Compact

@@ -716,6 +716,7 @@ int mark(const mr_frame_desc* d, int k, hipStream_t s) {
 // eval_halo: 0, or an LDS halo for the SSAO evaluation of the dense coarsest
 // level (multi-resolution SSAO frames of at most kTiledSamples samples)
 constexpr int kTiledSamplesHost = 256;
+constexpr int kFrameHalos = 4;  // eval_halo choices of mr_frame_tune
 int check_halo(const mr_frame_desc* d) {
     const int h = d->eval_halo;
     if (h == 0) return MR_OK;
@@ -1328,8 +1329,10 @@ int mr_eval_ssao_fullres(const mr_gbuffer* gb, const mr_camera* cam, const mr_ma
 
 // The whole frame; `path_only`: the workspace need only hold the layout of
 // the path these parameters take (the static-scratch entry point), else
-// that of either path (what mr_workspace_bytes reports).
-static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStream_t s, bool path_only) {
+// that of either path (what mr_workspace_bytes reports).  `check_only`:
+// validate the arguments and return before anything is enqueued.
+static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStream_t s, bool path_only,
+                     bool check_only = false) {
     if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
     const int effect = d->effect;
     int st = check_effect_params(effect, d->ssao, d->shadow, d->ssgi);
@@ -1348,6 +1351,7 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
         st = check_geo(&d->cam, nullptr, g);
         if (!st) st = check_gbuffer(&d->g, effect != MR_EFFECT_SHADOW, effect == MR_EFFECT_SSGI);
         if (st) return st;
+        if (check_only) return MR_OK;
         float* out[kMaxLevels] = {d->out};
         if ((st = mark(d, 0, s)) || (st = mark(d, 1, s))) return st;
         if ((st = do_eval(effect, &d->g, &d->cam, g, nullptr, params, out, s))) return st;
@@ -1370,13 +1374,14 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
     const size_t need = path_only ? (lean ? lean_bytes : f.bytes) : (f.bytes > lean_bytes ? f.bytes : lean_bytes);
     if (!ws || ws_bytes < need) return fail(MR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
     if (misaligned(ws)) return fail(MR_E_PARAM, "workspace is not 16-byte aligned");
+    if (!lean && d->level_dtype == MR_F16)
+        return fail(MR_E_DTYPE, "f16 sub-image storage needs the compact frame path (coarsest level <= 4, width "
+                                "divisible by 128, blur radii <= 8 with positive taps)");
+    if (check_only) return MR_OK;
     if (lean) {
         uint8_t* b = static_cast<uint8_t*>(ws);
         return do_frame_lean(d, g, params, b, b + lean_layout(g, effect).pyramid, true, s);
     }
-    if (d->level_dtype == MR_F16)
-        return fail(MR_E_DTYPE, "f16 sub-image storage needs the compact frame path (coarsest level <= 4, width "
-                                "divisible by 128, blur radii <= 8 with positive taps)");
     uint8_t* b = static_cast<uint8_t*>(ws);
     mr_masks m{};
     m.edge = b + f.edge;
@@ -1424,6 +1429,49 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
 
 int mr_frame(const mr_frame_desc* d, void* ws, size_t ws_bytes, void* stream) {
     return frame_run(d, ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+}
+
+int mr_frame_tune(mr_frame_desc* d, void* ws, size_t ws_bytes, int reps, float* ms, void* stream) {
+    if (!d) return fail(MR_E_NULL, "frame descriptor is NULL");
+    if (reps < 1 || reps > 1000) return fail(MR_E_PARAM, "reps %d outside [1, 1000]", reps);
+    static const int kHalos[kFrameHalos] = {0, 8, 16, 24};
+    // the descriptor as given must be valid; candidates it rejects are skipped
+    mr_frame_desc c = *d;
+    for (int k = 0; k < MR_FRAME_EVENTS; ++k) c.stage_events[k] = nullptr;  // the caller's events stay untouched
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int st = frame_run(&c, ws, ws_bytes, s, false, true);
+    if (st) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(MR_E_DEVICE, "event creation failed");
+    }
+    int best = d->eval_halo;
+    float best_ms = std::numeric_limits<float>::infinity();
+    for (int k = 0; k < kFrameHalos && !st; ++k) {
+        if (ms) ms[k] = -1.0f;
+        c.eval_halo = kHalos[k];
+        if (check_halo(&c) != MR_OK) continue;  // not a choice for this frame
+        st = frame_run(&c, ws, ws_bytes, s, false);  // warm-up
+        if (!st && hipEventRecord(e0, s) != hipSuccess) st = fail(MR_E_DEVICE, "event record failed");
+        for (int i = 0; i < reps && !st; ++i) st = frame_run(&c, ws, ws_bytes, s, false);
+        float t = 0.0f;
+        if (!st && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            st = fail(MR_E_DEVICE, "frame timing failed");
+        if (st) break;
+        t /= (float)reps;
+        if (ms) ms[k] = t;
+        if (t < best_ms) {
+            best_ms = t;
+            best = kHalos[k];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    d->eval_halo = best;
+    return MR_OK;
 }
 
 int mr_pyramid_bytes(const mr_camera* cam, const mr_mask_params* mp, int effect, size_t* pyramid, size_t* scratch) {

@@ -140,6 +140,8 @@ SIGNATURES = {
     "mr_upsample_merge": (ctypes.c_int, [ctypes.POINTER(mr_camera), ctypes.POINTER(mr_mask_params),
                                          ctypes.POINTER(mr_masks), ctypes.POINTER(c_ptr6), ctypes.c_int, _P, _P]),
     "mr_frame": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P, ctypes.c_size_t, _P]),
+    "mr_frame_tune": (ctypes.c_int, [ctypes.POINTER(mr_frame_desc), _P, ctypes.c_size_t, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_float), _P]),
     "mr_eval_ssao_fullres": (ctypes.c_int, [ctypes.POINTER(mr_gbuffer), ctypes.POINTER(mr_camera),
                                             ctypes.POINTER(mr_mask_params), ctypes.POINTER(mr_masks),
                                             ctypes.POINTER(ctypes.POINTER(mr_ssao_params) * MR_MAX_LEVELS),
@@ -627,6 +629,15 @@ class FrameRunner:
         self._hold_for(stream)
         _check(self._fn(ctypes.byref(self.desc), self._ws, self._nws, _stream(stream)))
         return self.out
+
+    def tune(self, reps=10, stream=None):
+        """mr_frame_tune: time the frame with every depth-halo size it admits
+        and keep the fastest in the descriptor.  Returns (eval_halo, {halo:
+        ms per frame}) for the sizes that were timed."""
+        self._hold_for(stream)
+        ms = (ctypes.c_float * 4)()
+        _check(lib().mr_frame_tune(ctypes.byref(self.desc), self._ws, self._nws, int(reps), ms, _stream(stream)))
+        return self.desc.eval_halo, {h: float(t) for h, t in zip((0, 8, 16, 24), ms) if t >= 0.0}
 
     def layout(self) -> mr_frame_layout:
         return mr_frame_workspace_layout(self.desc.cam, self.desc.mp, self.effect)

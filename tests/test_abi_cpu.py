@@ -155,6 +155,15 @@ def test_entry_points_reject_null_and_bad_shapes_without_enqueueing():
     assert L.mr_frame(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 30, None) == mr.MR_E_PARAM  # width 64
     assert "compact" in mr.mr_last_error()
     d.eval_halo = 0
+    # the frame tuner validates the frame before it creates its events
+    assert L.mr_frame_tune(None, ctypes.c_void_p(4096), 1 << 30, 3, None, None) == mr.MR_E_NULL
+    for reps in (0, 1001):
+        assert L.mr_frame_tune(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 30, reps, None, None) == mr.MR_E_PARAM
+    assert L.mr_frame_tune(ctypes.byref(d), ctypes.c_void_p(4096), 100, 3, None, None) == mr.MR_E_WORKSPACE
+    d.eval_halo = 4
+    assert L.mr_frame_tune(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 30, 3, None, None) == mr.MR_E_PARAM
+    assert d.eval_halo == 4  # unchanged on an error
+    d.eval_halo = 0
     # merge: bad channel count
     mm = mr.mr_masks()
     arr = mr.c_ptr6()

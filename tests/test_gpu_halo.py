@@ -67,3 +67,40 @@ def test_halo_frame_with_background_matches_oracle():
     got = got.cpu().numpy()
     assert np.abs(got - ref.out).max() <= 1e-4
     assert np.array_equal(got, ref.out)
+
+
+def test_frame_tuner_keeps_a_valid_halo_and_the_image():
+    """mr_frame_tune times every halo the frame admits and keeps the
+    fastest; the image after tuning equals the untuned one.  Frames that
+    admit only the depth plane (SSGI, the naive pass) time only halo 0."""
+    W, H = 1920, 1080
+    s = scenegen.make_scene(2, 200, 50)
+    gb = scenegen.render_gbuffer(s, scenegen.orbit_view(1), W, H)
+    d = torch.from_numpy(gb.depth).to(DEV)
+    n = torch.from_numpy(gb.normal).to(DEV)
+    p = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(32)).to(DEV), 1.0, 0.02)
+    mp = mask_params()
+    log(f"[gpu] mr_frame_tune SSAO {W}x{H}")
+    r = mr.FrameRunner("ssao", d, n, gb.focal, mp, True, params=p)
+    ref = r().clone()
+    halo, ms = r.tune(reps=3)
+    torch.cuda.synchronize()
+    assert halo in (0, 8, 16, 24) and r.desc.eval_halo == halo
+    assert sorted(ms) == [0, 8, 16, 24] and all(t > 0.0 for t in ms.values())
+    assert ms[halo] == min(ms.values())
+    assert torch.equal(r(), ref)
+    torch.cuda.synchronize()
+    log("[gpu] mr_frame_tune naive pass and SSGI")
+    plain = mr.FrameRunner("ssao", d, n, gb.focal, mp, False, params=p)
+    halo_p, ms_p = plain.tune(reps=2)
+    assert halo_p == 0 and list(ms_p) == [0]
+    t = scenegen.TABLE1["ssgi"]
+    mpg = mr.MaskParams(num_levels=4, level_enable=0b1101, sigma2=t["sigma2"], weight=t["weight"], normal_cos=COS25)
+    col = torch.from_numpy(scenegen.lambert_color(s, gb)).to(DEV)
+    gp = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(16)).to(DEV), 2.0, 0.02)
+    g = mr.FrameRunner("ssgi", d, n, gb.focal, mpg, True, color=col, params=gp)
+    ref_g = g().clone()
+    halo_g, ms_g = g.tune(reps=2)
+    assert halo_g == 0 and list(ms_g) == [0]
+    assert torch.equal(g(), ref_g)
+    torch.cuda.synchronize()
