@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmr.so")
 
 MR_MAX_LEVELS = 6
+MR_MAX_DIM = 16384
 MR_OK, MR_E_NULL, MR_E_SHAPE, MR_E_PARAM, MR_E_WORKSPACE, MR_E_DTYPE, MR_E_DEVICE = 0, -1, -2, -3, -4, -5, -6
 MR_F32, MR_F16 = 0, 1
 MR_EFFECT_SSAO, MR_EFFECT_SHADOW, MR_EFFECT_SSGI = 0, 1, 2

@@ -270,3 +270,19 @@ def test_frame_on_another_stream_holds_its_memory(monkeypatch):
     assert fr.workspace.streams == [] and fr.out.streams == []
     fr._hold_for(other)
     assert fr.workspace.streams == [other] and fr.out.streams == [other]
+
+
+def test_binding_constants_mirror_the_header():
+    """Every MR_* integer constant the binding defines equals the header's
+    #define of the same name (and the header defines it)."""
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mr.h")).read()
+    defs = {}
+    for name, val in re.findall(r"^#define (MR_[A-Z0-9_]+)\s+\(?(-?\d+)\)?\s*(?:/\*|$)", hdr, re.M):
+        defs[name] = int(val)
+    for name, a, b in re.findall(r"^#define (MR_[A-Z0-9_]+)\s+\((\d+)u?\s*<<\s*(\d+)\)", hdr, re.M):
+        defs[name] = int(a) << int(b)
+    names = [n for n in dir(mr) if n.startswith("MR_") and isinstance(getattr(mr, n), int)]
+    assert len(names) > 15
+    for n in names:
+        assert n in defs, f"{n} is not defined in mr.h"
+        assert getattr(mr, n) == defs[n], n

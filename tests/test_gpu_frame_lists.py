@@ -71,3 +71,29 @@ def test_frame_path_lists_and_image_match_the_oracle(name):
         for a, b in zip(first[i], again[i]):
             assert np.array_equal(a, b), f"level {i} changed between runs"
     assert np.array_equal(fr.out.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("W,H", [(16384, 512), (512, 16384)])
+def test_maximum_dimensions(W, H):
+    """Width or height at MR_MAX_DIM (16384): rows of 512 words, 128
+    ranking tiles across a level-1 row, 2048 edge tiles down a column.  The
+    frame path's lists and image and the naive pass equal the oracle's."""
+    assert max(W, H) == mr.MR_MAX_DIM
+    log(f"[gpu] maximum dimensions {W}x{H}")
+    scene = scenegen.make_scene(5, 200, 50)
+    gb = scenegen.render_gbuffer(scene, scenegen.orbit_view(4), W, H)
+    K = scenegen.ssao_kernel(16)
+    op = oracle.SSAOParams(K, 1.0, 0.02)
+    ref = oracle.frame("ssao", gb.depth, gb.normal, gb.focal, params(oracle), op)
+    ref_plain = oracle.frame("ssao", gb.depth, gb.normal, gb.focal, params(oracle), op, multires=False).out
+    d = torch.from_numpy(gb.depth).to(DEV)
+    n = torch.from_numpy(gb.normal).to(DEV)
+    p = mr.ssao_params(torch.from_numpy(K).to(DEV), 1.0, 0.02)
+    fr = mr.FrameRunner("ssao", d, n, gb.focal, params(mr), True, params=p)
+    fr()
+    torch.cuda.synchronize()
+    check_frame_lists(fr.lists(), ref.pyramid)
+    assert np.array_equal(fr.out.cpu().numpy(), ref.out)
+    plain = mr.FrameRunner("ssao", d, n, gb.focal, params(mr), False, params=p)()
+    torch.cuda.synchronize()
+    assert np.array_equal(plain.cpu().numpy(), ref_plain)
