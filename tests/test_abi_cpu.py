@@ -286,3 +286,23 @@ def test_binding_constants_mirror_the_header():
     for n in names:
         assert n in defs, f"{n} is not defined in mr.h"
         assert getattr(mr, n) == defs[n], n
+
+
+def test_a_c_client_builds_and_runs():
+    """tests/native/abi_host.c includes mr.h as a C11 header, links libmr.so
+    and calls the host-side entry points (sizes, layouts, validation)."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.join(root, "paper_1906_04576_amd")
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = os.path.join(tmp, "abi_host")
+        r = subprocess.run([gcc, "-std=c11", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(root, "include"),
+                            os.path.join(root, "tests", "native", "abi_host.c"), "-L", libdir, "-lmr",
+                            "-Wl,-rpath," + libdir, "-o", exe], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+        assert r.returncode == 0, r.stdout + r.stderr
+        assert "0 failure(s)" in r.stdout and "FAIL" not in r.stdout
