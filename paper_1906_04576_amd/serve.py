@@ -189,11 +189,15 @@ class Server:
     all of them.  With resident pyramids only requests whose pyramid is
     built are batched, and the batch evaluates and merges on those pyramids
     (mr_batch_setup_cached); without, the batch builds its masks
-    (mr_batch_setup_async).  A request that finds no partner runs alone."""
+    (mr_batch_setup_async).  A request that finds no partner runs alone, and
+    so does a frame of more than batch_pixels pixels: a frame that fills the
+    GPU by itself runs faster alone (a batch streams every frame through each
+    stage, so its evaluation no longer finds the frame's depth in the caches
+    its edge kernel filled)."""
 
     def __init__(self, pool: Pool, slots: int = 4, budget_bytes: int = 64 << 30, multires: bool = True,
                  level_dtype=torch.float32, keep_outputs: bool = False, resident_masks: bool = True,
-                 batch_max: int = 0):
+                 batch_max: int = 0, batch_pixels: int = 2560 * 1440):
         self.pool, self.multires, self.level_dtype, self.keep = pool, multires, level_dtype, keep_outputs
         self.cached = multires and resident_masks
         self.budget = budget_bytes
@@ -202,13 +206,15 @@ class Server:
         self.ws = [torch.empty(ws, dtype=torch.uint8, device=pool.device) for _ in range(slots)]
         self.ws_bytes = ws
         self.batch_max = batch_max if multires else 0
+        self.batch_pixels = batch_pixels
         self.batched = 0  # requests served in batches of two or more
         self.slots_b = []
         self.batch_ws_bytes = 0
         if self.batch_max >= 2:
             nws, nst = 0, 0
             for e in ("ssao", "ssgi"):
-                ks = [k for k in range(len(pool.scenes)) if pool.compact(k, e)]
+                ks = [k for k in range(len(pool.scenes))
+                      if pool.compact(k, e) and pool.scenes[k].W * pool.scenes[k].H <= batch_pixels]
                 if not ks:
                     continue
                 big = max(ks, key=lambda k: pool.scenes[k].W * pool.scenes[k].H)
@@ -225,6 +231,9 @@ class Server:
 
     def _batchable(self, req: Request) -> bool:
         if self.batch_max < 2 or req.effect not in ("ssao", "ssgi") or not self.pool.compact(req.scene, req.effect):
+            return False
+        sc = self.pool.scenes[req.scene]
+        if sc.W * sc.H > self.batch_pixels:
             return False
         if self.cached:  # its pyramid must be built (the first request builds it alone)
             pyr = self.pool.pyramids.get((req.scene, req.effect))

@@ -96,6 +96,11 @@ def test_batched_requests_equal_requests_alone():
     k = next(i for i, r in enumerate(reqs) if r.effect == "ssgi" and p.scenes[r.scene].W == 384)
     ref = oracle_frame(p, reqs[k].scene, "ssgi")
     assert np.array_equal(mix[k].out.cpu().numpy(), ref)
+    # frames above batch_pixels run alone
+    solo = serve.Server(p, slots=2, keep_outputs=True, batch_max=4, batch_pixels=1)
+    done = solo.run(reqs, realtime=False)
+    assert solo.batched == 0
+    assert all(torch.equal(a.out, b.out) for a, b in zip(done, mix))
 
 
 def test_budget_limits_requests_in_flight():
