@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 # FP32 arithmetic pipe: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-fused,
 # non-packed FP32 add / multiply / divide step per lane and clock (the
 # bit-exact contract rules out FMA contraction and packed FP32): 157.3 TFLOP/s
-# / 4.  A stream of independent v_add_f32 ran at 37.7 T lane-ops/s on the box
+# / 4.  A stream of independent v_add_f32 ran at 37.7 T lane-ops/s on an MI355X
 # (4.17 cycles per wave64 instruction).
 FP32_PIPE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic FP32 arithmetic of the SSAO estimator (Sec. 2.4 reading):
