@@ -58,6 +58,33 @@ int main(void) {
     mr_camera odd = {1000, 1002, 50.0f};
     check(mr_workspace_bytes(&odd, &mp, MR_EFFECT_SSAO) == 0, "a size not divisible by 2^(N-1) is refused");
 
+    check(mr_version() == MR_VERSION, "mr_version is the header's MR_VERSION");
+
+    /* a frame whose parameters are out of range is refused before anything
+     * is enqueued (the device pointers are never dereferenced) */
+    mr_ssao_params sp = {(const float*)(void*)4096, 16, 0.5f, 0.02f};
+    mr_frame_desc d;
+    memset(&d, 0, sizeof(d));
+    d.effect = MR_EFFECT_SSAO;
+    d.multires = 1;
+    d.g.depth = (const float*)(void*)4096;
+    d.g.normal = (const void*)8192;
+    d.g.normal_dtype = MR_F32;
+    d.cam = cam;
+    d.mp = mp;
+    d.ssao = &sp;
+    d.out = (float*)(void*)4096;
+    d.mp.sigma2[0] = -1.0f;
+    check(mr_frame(&d, (void*)4096, ws, NULL) == MR_E_PARAM, "sigma2 < 0 is MR_E_PARAM");
+    d.mp = mp;
+    d.mp.normal_cos = 2.0f;
+    check(mr_frame(&d, (void*)4096, ws, NULL) == MR_E_PARAM, "normal_cos outside [-1, 1] is MR_E_PARAM");
+    d.mp = mp;
+    sp.samples = 0;
+    check(mr_frame(&d, (void*)4096, ws, NULL) == MR_E_PARAM, "0 samples is MR_E_PARAM");
+    sp.samples = 16;
+    check(mr_frame(&d, (void*)4096, 100, NULL) == MR_E_WORKSPACE, "a small workspace is MR_E_WORKSPACE");
+
     int named = 1;
     const int codes[] = {MR_OK, MR_E_NULL, MR_E_SHAPE, MR_E_PARAM, MR_E_WORKSPACE, MR_E_DTYPE, MR_E_DEVICE};
     for (int i = 0; i < 7; ++i) named &= mr_status_string(codes[i]) != NULL && strlen(mr_status_string(codes[i])) > 0;
