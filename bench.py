@@ -16,11 +16,9 @@ speedup.  Progress goes to stderr; stdout gets one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
-import re
 import sys
 import time
 
@@ -52,71 +50,30 @@ TRAFFIC_BYTES = {"k_ssao_multi": 61843937}
 # pixel: the ratio of their instruction rates is the launch's VALU issue
 # relative to the rate that code sustains
 VALU_INSTS = {"k_ssao_multi": 20600129, "k_ssao_plain": 206263552}
-# the counters above hold for the kernels built from this code only: the
-# SHA-256 of the code of their .hip file and every header it includes
-# (source_closure_sha256: comments and white space aside) when they were
-# taken.  Any other hash reports them as null.
-COUNTER_SOURCES = {"k_ssao_multi": ("k_ssao.hip", "7626fccf826358a8e74be2132a04337a018d74670ab109fa1e60d95a15260e00")}
+# the counters above hold for the kernels of this machine code only: the
+# SHA-256 of the gfx950 code built from k_ssao.hip (libmr.code.json) when
+# they were taken.  Any other code reports them as null.
+COUNTER_CODE = {"k_ssao_multi": ("k_ssao.hip", "5256826d3eef46370ca48e2621235c90f809c1ccb1e0a8ab83deae9103fa34ca")}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def code_only(text: bytes) -> bytes:
-    """C/C++ source without its comments, runs of white space as one space:
-    what a change must alter to change the compiled code."""
-    out = bytearray()
-    i, n = 0, len(text)
-    while i < n:
-        c = text[i:i + 1]
-        if text.startswith(b"//", i):
-            j = text.find(b"\n", i)
-            i = n if j < 0 else j
-        elif text.startswith(b"/*", i):
-            j = text.find(b"*/", i + 2)
-            i = n if j < 0 else j + 2
-            out += b" "
-        elif c in (b'"', b"'"):
-            j = i + 1
-            while j < n and text[j:j + 1] != c:
-                j += 2 if text[j:j + 1] == b"\\" else 1
-            out += text[i:j + 1]
-            i = j + 1
-        else:
-            out += c
-            i += 1
-    return re.sub(rb"\s+", b" ", bytes(out)).strip()
+def built_code_sha256(src, path=None):
+    """SHA-256 of a source's gfx950 machine code in the built library
+    (libmr.code.json, written by the build), or None."""
+    path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1906_04576_amd", "libmr.code.json")
+    try:
+        with open(path) as f:
+            return json.load(f).get(src)
+    except (OSError, ValueError):
+        return None
 
 
-def source_closure_sha256(name, dirs=None):
-    """SHA-256 over the code (code_only) of a kernel source of the library
-    and every header it includes with quotes, transitively (files in name
-    order, each preceded by its name); files are looked up in `dirs`
-    (default: the library's sources and public headers)."""
-    if dirs is None:
-        root = os.path.dirname(os.path.abspath(__file__))
-        dirs = [os.path.join(root, "paper_1906_04576_amd", "csrc"), os.path.join(root, "include")]
-    seen, todo = {}, [name]
-    while todo:
-        n = todo.pop()
-        if n in seen:
-            continue
-        path = next((os.path.join(d, n) for d in dirs if os.path.isfile(os.path.join(d, n))), None)
-        if path is None:
-            raise FileNotFoundError(f"{n} (included from the sources of {name})")
-        with open(path, "rb") as f:
-            seen[n] = f.read()
-        todo += [m.decode() for m in re.findall(rb'^\s*#\s*include\s+"([^"]+)"', seen[n], re.M)]
-    h = hashlib.sha256()
-    for n in sorted(seen):
-        h.update(n.encode() + b"\0" + code_only(seen[n]) + b"\0")
-    return h.hexdigest()
-
-
-def counters_current(kernel):
-    src, digest = COUNTER_SOURCES[kernel]
-    return source_closure_sha256(src) == digest
+def counters_current(kernel, path=None):
+    src, digest = COUNTER_CODE[kernel]
+    return built_code_sha256(src, path) == digest
 
 
 def parse():
@@ -562,12 +519,12 @@ def main():
         achieved = ops_multi / t_eval / 1e12
         fresh = counters_current("k_ssao_multi")
         if not fresh:
-            log("[bench] the evaluation kernel's sources changed since its counters were taken: "
+            log("[bench] the evaluation kernels' machine code is not the one their counters were taken on: "
                 "traffic and VALU issue are reported as null")
         roofline = {"kernel": "k_ssao<float, true, true> (all levels of one frame in one launch)", "bound": "alu",
                     "achieved": round(achieved, 3), "peak": round(FP32_PIPE_PEAK_TOPS, 2), "unit": "TFLOP/s",
                     "frac": round(achieved / FP32_PIPE_PEAK_TOPS, 4), "traffic": TRAFFIC_BYTES.get("k_ssao_multi") if fresh else None,
-                    "launch_ms": stages["multi_eval_ms"], "counters_match_sources": fresh,
+                    "launch_ms": stages["multi_eval_ms"], "counters_match_code": fresh,
                     "basis": f"algorithmic FP32 arithmetic ({SSAO_FP32_PER_SAMPLE} per sample, "
                              f"{SSAO_FP32_PER_TEXEL} per texel) of {int(evaluated)} evaluated texels per launch "
                              "against the non-fused, non-packed FP32 pipe (157.3 TFLOP/s / 4)"}

@@ -38,7 +38,7 @@ def test_bench_line():
     assert ro["bound"] in ("hbm", "mfma", "alu") and ro["unit"] in ("GB/s", "TFLOP/s")
     assert 0 < ro["achieved"] <= ro["peak"] and abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-3
     fresh = bench.counters_current("k_ssao_multi")
-    assert ro["counters_match_sources"] is fresh
+    assert ro["counters_match_code"] is fresh
     if fresh:
         assert ro["traffic"] == bench.TRAFFIC_BYTES["k_ssao_multi"]
         assert 0 < ro["valu_rate_vs_plain"] < 1.2
