@@ -99,35 +99,46 @@ def test_maximum_dimensions(W, H):
     assert np.array_equal(plain.cpu().numpy(), ref_plain)
 
 
-def test_largest_frame():
-    """A 16384 x 16384 frame (MR_MAX_DIM in both directions: 268 M pixels,
-    byte offsets up to 2^30 within a plane).  The oracle cannot run a whole
-    frame of this size, so the checks are ones that hold at any size: the
-    naive pass at sampled pixels equals the oracle's estimator there (it
-    gathers from the full level images), and at every edge pixel of six
-    windows (the oracle's edge image of the window; a_1 w_1 >= 1 there, so
-    Eq. 1 returns c_1 exactly) the multi-resolution image equals the naive
-    pass and the pixel's owner level is 1."""
+@pytest.mark.parametrize("effect", ["ssao", "ssgi"])
+def test_largest_frame(effect):
+    """A 16384 x 16384 frame (MR_MAX_DIM in both directions: 268 M pixels;
+    the third FP32 normal plane, and for SSGI the third output plane, start
+    2^31 bytes in).  The oracle cannot run a whole frame of this size, so the
+    checks are ones that hold at any size: the naive pass at sampled pixels
+    equals the oracle's estimator there (it gathers from the full level
+    images), and at every edge pixel of six windows (the oracle's edge image
+    of the window; a_1 w_1 >= 1 there, so Eq. 1 returns c_1 exactly) the
+    multi-resolution image equals the naive pass and the pixel's owner level
+    is 1."""
     W = H = mr.MR_MAX_DIM
-    log(f"[gpu] largest frame {W}x{H}")
+    log(f"[gpu] largest frame {effect} {W}x{H}")
     scene = scenegen.make_scene(6, 200, 50)
     gb = scenegen.render_gbuffer(scene, scenegen.orbit_view(1), W, H)
     K = scenegen.ssao_kernel(16)
-    op = oracle.SSAOParams(K, 1.0, 0.02)
+    col = scenegen.lambert_color(scene, gb) if effect == "ssgi" else None
+    t = scenegen.TABLE1[effect]
+    en = 0b1101 if effect == "ssgi" else 0xF
+    mpg = mr.MaskParams(num_levels=4, level_enable=en, sigma2=t["sigma2"], weight=t["weight"], normal_cos=COS25)
     d = torch.from_numpy(gb.depth).to(DEV)
     n = torch.from_numpy(gb.normal).to(DEV)
+    c = torch.from_numpy(col).to(DEV) if col is not None else None
     p = mr.ssao_params(torch.from_numpy(K).to(DEV), 1.0, 0.02)
     lm = torch.zeros((H, W), dtype=torch.uint8, device=DEV)
-    multi = mr.FrameRunner("ssao", d, n, gb.focal, params(mr), True, params=p, level_map=lm)().cpu().numpy()
-    plain = mr.FrameRunner("ssao", d, n, gb.focal, params(mr), False, params=p)().cpu().numpy()
+    multi = mr.FrameRunner(effect, d, n, gb.focal, mpg, True, color=c, params=p, level_map=lm)().cpu().numpy()
+    plain = mr.FrameRunner(effect, d, n, gb.focal, mpg, False, color=c, params=p)().cpu().numpy()
     owner = lm.cpu().numpy()
-    del d, n, lm
+    del d, n, c, lm
     torch.cuda.empty_cache()
     rng = np.random.default_rng(16384)
     ys = np.concatenate([rng.integers(0, H, 1500), [0, H - 1, 0, H - 1]])
     xs = np.concatenate([rng.integers(0, W, 1500), [0, 0, W - 1, W - 1]])
-    ref = oracle.ssao_texels(gb.depth, gb.normal, gb.focal, 1, xs, ys, op)
-    assert np.array_equal(plain[ys, xs], ref.astype(np.float32))
+    if effect == "ssao":
+        ref = oracle.ssao_texels(gb.depth, gb.normal, gb.focal, 1, xs, ys, oracle.SSAOParams(K, 1.0, 0.02))
+        assert np.array_equal(plain[ys, xs], ref.astype(np.float32))
+    else:
+        ref = oracle.ssgi_texels(gb.depth, gb.normal, col.astype(np.float32), gb.focal, 1, xs, ys,
+                                 oracle.SSGIParams(K, 1.0, 0.02))
+        assert np.array_equal(plain[:, ys, xs], ref.astype(np.float32))
     omp = params(oracle)
     edges = 0
     for (y0, x0) in ((0, 0), (8000, 8000), (H - 1024, W - 1024), (4096, 12000), (12000, 2000), (2000, 6000)):
@@ -141,7 +152,7 @@ def test_largest_frame():
         ey, ex = np.nonzero(E[y0 - ya:y0 - ya + 1024, x0 - xa:x0 - xa + 1024])
         ey, ex = ey + y0, ex + x0
         edges += len(ey)
-        assert np.array_equal(multi[ey, ex], plain[ey, ex])
+        assert np.array_equal(multi[..., ey, ex], plain[..., ey, ex])
         assert np.all(owner[ey, ex] == 1)
     log(f"[gpu] {edges} edge pixels checked")
     assert edges > 300
