@@ -444,32 +444,35 @@ def main():
     roofline = None
     if not args.no_stages:
         def stage_times(runners, reps):
-            """Per frame: the three stage durations from the frame's events,
-            and the spacing of two events recorded back to back after it (the
-            stream time one event takes; it sits inside every stage)."""
+            """Per frame, from the frame's five events: masks ([0] to [1]),
+            evaluation ([1] to [2]), merge ([2] to [3]), edge image ([0] to
+            [4]) and ranking ([4] to [1]); and the spacing of two events
+            recorded back to back after it (the stream time one event takes;
+            it sits inside every interval, twice inside the masks)."""
             sets = []
             stream = torch.cuda.current_stream()
             runners[0]()
             plain[0]()
             for rep in range(reps):
                 for k in range(nf):
-                    e = [mr.DeviceEvent() for _ in range(6)]
-                    runners[k].set_stage_events(e[:4])
+                    e = [mr.DeviceEvent() for _ in range(mr.MR_FRAME_EVENTS + 2)]
+                    runners[k].set_stage_events(e[:mr.MR_FRAME_EVENTS])
                     runners[k]()
-                    mr.record(e[4], stream)
                     mr.record(e[5], stream)
+                    mr.record(e[6], stream)
                     sets.append(e)
             torch.cuda.synchronize()
             for r in runners:
                 r.set_stage_events(None)
-            t = np.array([[e[j].elapsed_ms(e[j + 1]) for j in (0, 1, 2, 4)] for e in sets])  # ms
-            return t
+            pairs = ((0, 1), (1, 2), (2, 3), (5, 6), (0, 4), (4, 1))
+            return np.array([[e[a].elapsed_ms(e[b]) for a, b in pairs] for e in sets])  # ms
 
         reps = max(1, 96 // nf)
         tm = stage_times(multi, reps)
         tp = stage_times(plain, reps)
         ev_ms = float(np.median(np.concatenate([tm[:, 3], tp[:, 3]])))
-        for j, nm in enumerate(["masks", "eval", "merge"]):
+        stages["multi_masks_ms"] = round(float(tm[:, 0].mean()) - 2 * ev_ms, 5)
+        for j, nm in ((1, "eval"), (2, "merge"), (4, "edges"), (5, "rank")):
             stages[f"multi_{nm}_ms"] = round(float(tm[:, j].mean()) - ev_ms, 5)
         stages["plain_eval_ms"] = round(float(tp[:, 1].mean()) - ev_ms, 5)
         stages["event_ms"] = round(ev_ms, 5)
@@ -492,9 +495,10 @@ def main():
         nb = n[0] + n[1] + n[2]  # texels of the list levels (one bit each in the bit masks)
         # algorithmic bytes per stage of the multi-resolution frame:
         # compulsory reads and writes, sample gathers excluded
-        b_masks = (16 * n[0] + nb / 8 + 4 * (n[1] + n[2] + n[3])   # edges: G-buffer in, edge bits + level depth out
-                   + nb / 8 + nb / 8                               # stencil: edge bits in, stencil bits out
-                   + nb / 8 + 4 * nb / 32 + 4 * listed)            # ranks and lists
+        b_edges = 16 * n[0] + nb / 8 + 4 * (n[1] + n[2] + n[3])  # G-buffer in, edge bits + level depth out
+        b_rank = (nb / 8 + nb / 8                                 # stencil: edge bits in, stencil bits out
+                  + nb / 8 + 4 * nb / 32 + 4 * listed)            # ranks and lists
+        b_masks = b_edges + b_rank
         b_eval = 4 * listed + 16 * evaluated + nb / 8 + 4 * evaluated + 4 * listed
         b_merge = nb / 8 + 4 * nb / 32 + 8 * listed + 4 * n[3] + 4 * n[0]
         b_frame = b_masks + b_eval + b_merge
@@ -509,6 +513,8 @@ def main():
             "frame_hbm_frac": round(b_frame / t_frame / (HBM_PEAK_GBS * 1e9), 4),
             "frame_hbm_frac_incl_gathers": round((b_frame + 4.0 * S * evaluated) / t_frame / (HBM_PEAK_GBS * 1e9), 4),
             "masks_hbm_frac": round(b_masks / (stages["multi_masks_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "edges_hbm_frac": round(b_edges / (stages["multi_edges_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "rank_hbm_frac": round(b_rank / (stages["multi_rank_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "merge_hbm_frac": round(b_merge / (stages["multi_merge_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "eval_multi_fp32_frac": round(ops_multi / t_eval / (FP32_PIPE_PEAK_TOPS * 1e12), 4),
             "eval_plain_fp32_frac": round(ops_plain / (stages["plain_eval_ms"] * 1e-3) / (FP32_PIPE_PEAK_TOPS * 1e12),

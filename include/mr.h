@@ -66,7 +66,7 @@ extern "C" {
 #define MR_MAX_SAMPLES 8192
 #define MR_MAX_DIM 16384
 #define MR_VERSION 100
-#define MR_FRAME_EVENTS 4  /* stage events of mr_frame_desc */
+#define MR_FRAME_EVENTS 5  /* stage events of mr_frame_desc */
 
 /* status codes */
 #define MR_OK 0
@@ -247,10 +247,13 @@ typedef struct {
  * stage_events  optional hipEvent_t handles (each may be NULL), recorded on
  *            the frame's stream: [0] before the first kernel, [1] after the
  *            masks and work lists (after the hard-shadow pass on the naive
- *            path), [2] after the per-level evaluation, [3] after the merge.
+ *            path), [2] after the per-level evaluation, [3] after the merge,
+ *            and [4] after the edge image (Sec. 3.1) on the compact frame
+ *            path when it builds its masks, else at the same point as [1].
  *            They are owned by the caller and must have been created on the
- *            stream's device; event [k+1] minus event [k] is the GPU time of
- *            that stage.
+ *            stream's device; event [k+1] minus event [k] (k < 3) is the GPU
+ *            time of that stage, [4] minus [0] that of the edge image and [1]
+ *            minus [4] that of the stencils, ranks and lists.
  * bilateral  optional blur of the SSAO sub-images (levels = 0: off); needs
  *            MR_EFFECT_SSAO, multires = 1 and the compact frame path, else
  *            MR_E_PARAM.  Counted in the evaluation stage.

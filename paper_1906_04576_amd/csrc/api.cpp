@@ -951,7 +951,10 @@ int do_frame_lean(const mr_frame_desc* d, const Geo& g, const void* params, uint
         if (P.has_hard && launch_hard(P.ha, s) != hipSuccess)
             return fail(MR_E_DEVICE, "hard shadow kernel launch failed");
         if (launch_edges(P.ea, d->g.normal_dtype, s) != hipSuccess) return fail(MR_E_DEVICE, "edge kernel launch failed");
+        if ((st = mark(d, 4, s))) return st;
         if (launch_lean_masks(P.la, s) != hipSuccess) return fail(MR_E_DEVICE, "lean mask kernels launch failed");
+    } else if ((st = mark(d, 4, s))) {
+        return st;
     }
     if (P.has_map && launch_lean_level_map(P.lm, s) != hipSuccess)
         return fail(MR_E_DEVICE, "level map kernel launch failed");
@@ -1353,7 +1356,7 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
         if (st) return st;
         if (check_only) return MR_OK;
         float* out[kMaxLevels] = {d->out};
-        if ((st = mark(d, 0, s)) || (st = mark(d, 1, s))) return st;
+        if ((st = mark(d, 0, s)) || (st = mark(d, 4, s)) || (st = mark(d, 1, s))) return st;
         if ((st = do_eval(effect, &d->g, &d->cam, g, nullptr, params, out, s))) return st;
         if ((st = mark(d, 2, s))) return st;
         return mark(d, 3, s);
@@ -1417,7 +1420,7 @@ static int frame_run(const mr_frame_desc* d, void* ws, size_t ws_bytes, hipStrea
     }
     st = do_build_masks(&d->g, g, &d->mp, hard, &m, b + f.scratch, s);
     if (st) return st;
-    if ((st = mark(d, 1, s))) return st;
+    if ((st = mark(d, 4, s)) || (st = mark(d, 1, s))) return st;
     st = do_eval(effect, &d->g, &d->cam, g, &m, params, lo, s);
     if (st) return st;
     if ((st = mark(d, 2, s))) return st;

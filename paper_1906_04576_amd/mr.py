@@ -24,7 +24,7 @@ MR_OK, MR_E_NULL, MR_E_SHAPE, MR_E_PARAM, MR_E_WORKSPACE, MR_E_DTYPE, MR_E_DEVIC
 MR_F32, MR_F16 = 0, 1
 MR_EFFECT_SSAO, MR_EFFECT_SHADOW, MR_EFFECT_SSGI = 0, 1, 2
 MR_WS_MASKS = -1
-MR_FRAME_EVENTS = 4
+MR_FRAME_EVENTS = 5
 MR_MAX_BATCH = 64
 MR_BATCH_PLAN_BYTES = 512
 MR_STATIC_SCRATCH_BYTES = 64 << 20

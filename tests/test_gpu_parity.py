@@ -302,6 +302,11 @@ def test_stage_events(multires):
     assert all(x >= 0 for x in t)
     assert abs(sum(t) - ev[0].elapsed_time(ev[3])) <= 1e-3 + 1e-3 * sum(t)
     assert t[1] > 0  # the evaluation kernel runs between events 1 and 2
+    # event 4 (the edge image done) lies between events 0 and 1
+    e4 = (ev[0].elapsed_time(ev[4]), ev[4].elapsed_time(ev[1]))
+    assert min(e4) >= 0 and abs(sum(e4) - t[0]) <= 1e-3 + 1e-3 * t[0]
+    if multires:
+        assert e4[0] > 0 and e4[1] > 0  # the edge kernel, then the ranking
     fr.set_stage_events(None)
     assert torch.equal(fr(), ref)
     dv = [mr.DeviceEvent() for _ in range(mr.MR_FRAME_EVENTS)]
