@@ -1,0 +1,112 @@
+"""GPU parity over seeded random frame configurations: for each seed a scene,
+camera, size, level count and enabled set, blur variances and weights,
+effect (SSAO, PCSS or SSGI), sample counts and the normals' storage (FP32
+or FP16) are drawn, and mr_frame's
+multi-resolution and naive images are compared bit for bit with the
+oracle's (Sec. 3-4; the naive pass of Sec. 5).
+
+The draws cover both frame paths: widths that are multiples of 128 with at
+most four levels take the compact path (bit-packed stencils, ranked lists),
+the others the dense one; sizes are ragged multiples of 2^(N-1) from one
+coarsest texel upwards, so that tiles of every kernel are cut at the image
+border.  The configurations are fixed by their seeds: every run checks the
+same frames.  With FP16 normals the oracle takes the same normals rounded
+to FP16 (the kernels widen them exactly)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from paper_1906_04576_amd import mr
+
+DEV = "cuda"
+COS25 = float(np.float32(math.cos(math.radians(25.0))))
+SEEDS = range(64)
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def draw(seed):
+    """One frame configuration, a pure function of the seed."""
+    rng = np.random.default_rng(9100 + seed)
+    effect = str(rng.choice(["ssao", "ssao", "ssgi", "shadow"]))
+    N = int(rng.integers(2, 6))
+    s = 1 << (N - 1)
+    en = 1 | (1 << (N - 1))
+    for i in range(1, N - 1):
+        en |= int(rng.integers(0, 2)) << i
+    if N <= 4 and rng.random() < 0.5:
+        W = 128 * int(rng.integers(1, 9))
+    else:
+        W = s * int(rng.integers(1, 1100 // s + 1))
+    H = s * int(rng.integers(1, 600 // s + 1))
+    sigma2 = tuple(float(rng.choice([0.0, 0.924, 1.848, 3.696])) for _ in range(N - 1)) + (0.0,)
+    weight = tuple(float(rng.choice([1.0, 20.0, 50.0, 100.0, 1000.0])) for _ in range(N - 1)) + (1.0,)
+    return dict(effect=effect, N=N, en=en, W=W, H=H, sigma2=sigma2, weight=weight,
+                S=int(rng.choice([1, 3, 8, 16, 33])), radius=float(rng.choice([0.5, 1.0, 2.0])),
+                scene=(int(rng.integers(1, 1000)), int(rng.integers(5, 120)), int(rng.integers(0, 30))),
+                cam=int(rng.integers(0, 8)), sm=int(rng.choice([256, 512])),
+                blockers=int(rng.integers(1, 17)), pcf=int(rng.integers(1, 33)), f16=bool(rng.random() < 0.25))
+
+
+def test_draws_cover_both_paths_and_all_effects():
+    cfgs = [draw(k) for k in SEEDS]
+    compact = [c["W"] % 128 == 0 and c["N"] <= 4 for c in cfgs]
+    assert any(compact) and not all(compact)
+    assert {c["effect"] for c in cfgs} == {"ssao", "ssgi", "shadow"}
+    assert {c["N"] for c in cfgs} >= {2, 3, 4, 5}
+    assert any(c["W"] % 128 and c["W"] < 64 for c in cfgs) or any(c["H"] <= 16 for c in cfgs)
+    assert any(c["f16"] for c in cfgs) and not all(c["f16"] for c in cfgs)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", list(SEEDS))
+def test_random_frame(seed):
+    c = draw(seed)
+    log(f"[gpu] random frame {seed}: {c}")
+    W, H, N, en = c["W"], c["H"], c["N"], c["en"]
+    sc = scenegen.make_scene(*c["scene"])
+    gb = scenegen.render_gbuffer(sc, scenegen.orbit_view(c["cam"]), W, H)
+    mp = mr.MaskParams(num_levels=N, level_enable=en, sigma2=c["sigma2"], weight=c["weight"],
+                       radius=(-1,) * N, normal_cos=COS25)
+    omp = oracle.MaskParams(num_levels=N, level_enable=en, sigma2=c["sigma2"], weight=c["weight"],
+                            radius=(-1,) * N, normal_cos=COS25)
+    nrm = gb.normal.astype(np.float16) if c["f16"] else gb.normal
+    d = torch.from_numpy(gb.depth).to(DEV)
+    n = torch.from_numpy(nrm).to(DEV)
+    nrm = nrm.astype(np.float32)
+    color = None
+    if c["effect"] == "shadow":
+        si = scenegen.render_shadow_inputs(sc, gb.view, c["sm"])
+        bd = scenegen.disk_samples(c["blockers"], 11 + seed)
+        pd = scenegen.disk_samples(c["pcf"], 12 + seed)
+        op = oracle.ShadowParams(si.shadow_map, si.view_to_light, si.light_focal, si.light_size, si.light_near,
+                                 np.float32(0.05), bd, pd)
+        sp = mr.shadow_params(torch.from_numpy(si.shadow_map).to(DEV), si.view_to_light, si.light_focal,
+                              si.light_size, si.light_near, 0.05, torch.from_numpy(bd).to(DEV),
+                              torch.from_numpy(pd).to(DEV))
+    else:
+        K = scenegen.ssao_kernel(c["S"], seed=500 + seed)
+        sp = mr.ssao_params(torch.from_numpy(K).to(DEV), c["radius"], 0.02)
+        if c["effect"] == "ssao":
+            op = oracle.SSAOParams(K, c["radius"], 0.02)
+        else:
+            op = oracle.SSGIParams(K, c["radius"], 0.02)
+            color = scenegen.lambert_color(sc, gb)
+    ct = None if color is None else torch.from_numpy(color).to(DEV)
+    multi = mr.mr_frame(c["effect"], d, n, gb.focal, mp, sp, color=ct, multires=True)
+    plain = mr.mr_frame(c["effect"], d, n, gb.focal, mp, sp, color=ct, multires=False)
+    torch.cuda.synchronize()
+    rf = oracle.frame(c["effect"], gb.depth, nrm, gb.focal, omp, op, color=color).out
+    rp = oracle.frame(c["effect"], gb.depth, nrm, gb.focal, omp, op, multires=False, color=color).out
+    m, p = multi.cpu().numpy(), plain.cpu().numpy()
+    assert m.shape == rf.shape and p.shape == rp.shape
+    assert np.array_equal(m, rf), f"multi-resolution frame: max |d| {np.abs(m - rf).max()}"
+    assert np.array_equal(p, rp), f"naive frame: max |d| {np.abs(p - rp).max()}"
