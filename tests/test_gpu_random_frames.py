@@ -1,9 +1,10 @@
 """GPU parity over seeded random frame configurations: for each seed a scene,
 camera, size, level count and enabled set, blur variances and weights,
 effect (SSAO, PCSS or SSGI), sample counts and the normals' storage (FP32
-or FP16) are drawn, and mr_frame's
-multi-resolution and naive images are compared bit for bit with the
-oracle's (Sec. 3-4; the naive pass of Sec. 5).
+or FP16) are drawn; the mask pyramid of mr_build_masks (edge image, hard
+shadow bits, level map, a_i, stencils, work lists and counts, level depth)
+and mr_frame's multi-resolution and naive images are compared bit for bit
+with the oracle's (Sec. 3-4; the naive pass of Sec. 5).
 
 The draws cover both frame paths: widths that are multiples of 128 with at
 most four levels take the compact path (bit-packed stencils, ranked lists),
@@ -101,11 +102,33 @@ def test_random_frame(seed):
             op = oracle.SSGIParams(K, c["radius"], 0.02)
             color = scenegen.lambert_color(sc, gb)
     ct = None if color is None else torch.from_numpy(color).to(DEV)
+    # the mask pyramid through the step entry point (Sec. 3.1, 4.1)
+    hard = mr.mr_shadow_hard(d, gb.focal, sp) if c["effect"] == "shadow" else None
+    masks = mr.mr_build_masks(d, n, gb.focal, mp, hard_shadow=hard)
     multi = mr.mr_frame(c["effect"], d, n, gb.focal, mp, sp, color=ct, multires=True)
     plain = mr.mr_frame(c["effect"], d, n, gb.focal, mp, sp, color=ct, multires=False)
     torch.cuda.synchronize()
     rf = oracle.frame(c["effect"], gb.depth, nrm, gb.focal, omp, op, color=color).out
     rp = oracle.frame(c["effect"], gb.depth, nrm, gb.focal, omp, op, multires=False, color=color).out
+    E = oracle.edge_image(gb.depth, nrm, omp.depth_ratio, omp.normal_cos)
+    if c["effect"] == "shadow":
+        ref_hard = oracle.hard_shadow(gb.depth, gb.focal, 1, op)
+        assert np.array_equal(hard.cpu().numpy(), ref_hard), "hard shadow bits"
+        E = E | oracle.shadow_edges(ref_hard, gb.depth)
+    pyr = oracle.build_pyramid(E, omp)
+    assert np.array_equal(masks.edge.cpu().numpy(), pyr.E), "edge image"
+    assert np.array_equal(masks.level_map.cpu().numpy(), pyr.level_map), "level map"
+    cnt = masks.count.cpu().numpy().view(np.uint32)
+    for i in pyr.levels:
+        if i >= 2:
+            assert np.array_equal(masks.level_depth[i].cpu().numpy(), oracle.level_sample(gb.depth, i)), f"depth {i}"
+        if i == pyr.levels[-1]:
+            continue
+        assert np.array_equal(masks.alpha[i].cpu().numpy().view(np.uint32), pyr.alpha[i].view(np.uint32)), f"a_{i}"
+        assert np.array_equal(masks.stencil[i].cpu().numpy(), pyr.stencil[i]), f"stencil {i}"
+        k = len(pyr.worklist[i])
+        assert cnt[i - 1] == k, f"count {i}"
+        assert np.array_equal(masks.worklist[i][:k].cpu().numpy().view(np.uint32), pyr.worklist[i]), f"list {i}"
     m, p = multi.cpu().numpy(), plain.cpu().numpy()
     assert m.shape == rf.shape and p.shape == rp.shape
     assert np.array_equal(m, rf), f"multi-resolution frame: max |d| {np.abs(m - rf).max()}"
