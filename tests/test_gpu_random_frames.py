@@ -2,9 +2,11 @@
 camera, size, level count and enabled set, blur variances and weights,
 effect (SSAO, PCSS or SSGI), sample counts and the normals' storage (FP32
 or FP16) are drawn; the mask pyramid of mr_build_masks (edge image, hard
-shadow bits, level map, a_i, stencils, work lists and counts, level depth)
-and mr_frame's multi-resolution and naive images are compared bit for bit
-with the oracle's (Sec. 3-4; the naive pass of Sec. 5).
+shadow bits, level map, a_i, stencils, work lists and counts, level depth),
+the per-level values of the mr_eval_* entry points on their stencils, the
+image of mr_upsample_merge, and mr_frame's multi-resolution and naive
+images are compared bit for bit with the oracle's (Sec. 3-4; the naive
+pass of Sec. 5).
 
 The draws cover both frame paths: widths that are multiples of 128 with at
 most four levels take the compact path (bit-packed stencils, ranked lists),
@@ -95,7 +97,8 @@ def test_random_frame(seed):
                               torch.from_numpy(pd).to(DEV))
     else:
         K = scenegen.ssao_kernel(c["S"], seed=500 + seed)
-        sp = mr.ssao_params(torch.from_numpy(K).to(DEV), c["radius"], 0.02)
+        sp_kernel = torch.from_numpy(K).to(DEV)
+        sp = mr.ssao_params(sp_kernel, c["radius"], 0.02)
         if c["effect"] == "ssao":
             op = oracle.SSAOParams(K, c["radius"], 0.02)
         else:
@@ -105,6 +108,14 @@ def test_random_frame(seed):
     # the mask pyramid through the step entry point (Sec. 3.1, 4.1)
     hard = mr.mr_shadow_hard(d, gb.focal, sp) if c["effect"] == "shadow" else None
     masks = mr.mr_build_masks(d, n, gb.focal, mp, hard_shadow=hard)
+    # the per-level evaluation and the merge through their step entry points
+    if c["effect"] == "shadow":
+        lo = mr.mr_eval_shadow(d, gb.focal, sp, mp=mp, masks=masks)
+    elif c["effect"] == "ssao":
+        lo = mr.mr_eval_ssao(d, n, gb.focal, sp_kernel, c["radius"], 0.02, mp=mp, masks=masks)
+    else:
+        lo = mr.mr_eval_ssgi(d, n, ct, gb.focal, sp_kernel, c["radius"], 0.02, mp=mp, masks=masks)
+    steps = mr.mr_upsample_merge(gb.focal, mp, masks, lo, channels=3 if c["effect"] == "ssgi" else 1)
     multi = mr.mr_frame(c["effect"], d, n, gb.focal, mp, sp, color=ct, multires=True)
     plain = mr.mr_frame(c["effect"], d, n, gb.focal, mp, sp, color=ct, multires=False)
     torch.cuda.synchronize()
@@ -132,4 +143,20 @@ def test_random_frame(seed):
     m, p = multi.cpu().numpy(), plain.cpu().numpy()
     assert m.shape == rf.shape and p.shape == rp.shape
     assert np.array_equal(m, rf), f"multi-resolution frame: max |d| {np.abs(m - rf).max()}"
+    assert np.array_equal(steps.cpu().numpy(), rf), "step entry points"
+    # every level's values on its stencil (the coarsest level everywhere)
+    L = pyr.levels[-1]
+    for i in pyr.levels:
+        zi = oracle.level_sample(gb.depth, i)
+        st = None if i == L else pyr.stencil[i]
+        if c["effect"] == "shadow":
+            ref = oracle.pcss_level(zi, gb.focal, i, op, st)
+        elif c["effect"] == "ssao":
+            ref = oracle.ssao_level(zi, oracle.level_sample(nrm, i), gb.focal, i, op, st)
+        else:
+            ref = oracle.ssgi_level(zi, oracle.level_sample(nrm, i), oracle.level_sample(color, i), gb.focal, i,
+                                    op, st)
+        g = lo[i].cpu().numpy()
+        sel = np.ones(zi.shape, bool) if st is None else st.astype(bool)
+        assert np.array_equal(g[..., sel], ref[..., sel]), f"level {i} values"
     assert np.array_equal(p, rp), f"naive frame: max |d| {np.abs(p - rp).max()}"
