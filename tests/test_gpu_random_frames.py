@@ -4,9 +4,10 @@ effect (SSAO, PCSS or SSGI), sample counts and the normals' storage (FP32
 or FP16) are drawn; the mask pyramid of mr_build_masks (edge image, hard
 shadow bits, level map, a_i, stencils, work lists and counts, level depth),
 the per-level values of the mr_eval_* entry points on their stencils, the
-image of mr_upsample_merge, and mr_frame's multi-resolution and naive
-images are compared bit for bit with the oracle's (Sec. 3-4; the naive
-pass of Sec. 5).
+image of mr_upsample_merge, mr_frame's multi-resolution and naive images,
+and for SSAO the variant with every level at full resolution and fewer
+samples (mr_eval_ssao_fullres, Sec. 6) are compared bit for bit with the
+oracle's (Sec. 3-4; the naive pass of Sec. 5).
 
 The draws cover both frame paths: widths that are multiples of 128 with at
 most four levels take the compact path (bit-packed stencils, ranked lists),
@@ -159,4 +160,17 @@ def test_random_frame(seed):
         g = lo[i].cpu().numpy()
         sel = np.ones(zi.shape, bool) if st is None else st.astype(bool)
         assert np.array_equal(g[..., sel], ref[..., sel]), f"level {i} values"
+    if c["effect"] == "ssao":
+        # the same masks with every level at full resolution and its own,
+        # smaller sample set (Sec. 6)
+        rng = np.random.default_rng(4400 + seed)
+        Ks = {i: scenegen.ssao_kernel(max(1, c["S"] >> int(rng.integers(0, i))), seed=600 + 7 * seed + i)
+              for i in pyr.levels}
+        rs = {i: float(rng.choice([0.5, 1.0, 2.0])) for i in pyr.levels}
+        lp = {i: mr.ssao_params(torch.from_numpy(Ks[i]).to(DEV), rs[i], 0.02) for i in pyr.levels}
+        fr = mr.mr_eval_ssao_fullres(d, n, gb.focal, mp, masks, lp)
+        torch.cuda.synchronize()
+        ref = oracle.frame_fullres_levels(gb.depth, nrm, gb.focal, omp,
+                                          {i: oracle.SSAOParams(Ks[i], rs[i], 0.02) for i in pyr.levels}).out
+        assert np.array_equal(fr.cpu().numpy(), ref), "full-resolution levels with fewer samples"
     assert np.array_equal(p, rp), f"naive frame: max |d| {np.abs(p - rp).max()}"
