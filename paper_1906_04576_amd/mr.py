@@ -278,6 +278,17 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _hold(stream, *tensors):
+    """Work enqueued on a stream other than torch's current one keeps the
+    memory it uses alive for that stream: torch's caching allocator would
+    otherwise hand that memory to the next allocation on the current stream
+    while the work still runs."""
+    if stream is not None and stream != torch.cuda.current_stream():
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
 def level_dims(W, H, i):
     return W >> (i - 1), H >> (i - 1)
 
@@ -296,6 +307,13 @@ class Masks:
     worklist: dict = field(default_factory=dict)
     level_depth: dict = field(default_factory=dict)
     workspace: torch.Tensor = None
+
+    def tensors(self) -> list:
+        """Every device tensor of the pyramid, its workspace included."""
+        t = [self.edge, self.count, self.level_map, self.workspace]
+        for d in (self.alpha, self.stencil, self.worklist, self.level_depth):
+            t.extend(d.values())
+        return [x for x in t if x is not None]
 
     def c(self) -> mr_masks:
         m = mr_masks()
@@ -356,6 +374,7 @@ def mr_build_masks(depth, normal, focal, mp: MaskParams, hard_shadow=None, masks
     cam = camera(W, H, focal)
     cmp = mp.c()
     cm = masks.c()
+    _hold(stream, *masks.tensors())
     _check(lib().mr_build_masks(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cmp), _ptr(hard_shadow),
                                 ctypes.byref(cm), _ptr(masks.workspace), masks.workspace.numel(),
                                 _stream(stream)))
@@ -382,6 +401,7 @@ def _eval(name, g, W, H, focal, mp, masks, params_c, C, out, stream):
     cmp = mp.c() if mp is not None else None
     cm = masks.c() if masks is not None else None
     fn = getattr(lib(), name)
+    _hold(stream, *out.values())
     _check(fn(ctypes.byref(g[0]), ctypes.byref(cam), ctypes.byref(cmp) if cmp is not None else None,
               ctypes.byref(cm) if cm is not None else None, ctypes.byref(params_c), ctypes.byref(arr),
               _stream(stream)))
@@ -408,6 +428,7 @@ class FullresRunner:
         self._fn = lib().mr_eval_ssao_fullres
 
     def __call__(self, stream=None):
+        _hold(stream, self.out)
         _check(self._fn(ctypes.byref(self.g), ctypes.byref(self.cam), ctypes.byref(self.cmp), ctypes.byref(self.cm),
                         ctypes.byref(self.lp), _ptr(self.out), _stream(stream)))
         return self.out
@@ -470,6 +491,7 @@ def mr_shadow_hard(depth, focal, sp: mr_shadow_params, hard=None, stream=None):
         hard = torch.empty((H, W), dtype=torch.uint8, device=depth.device)
     g = gbuffer(depth)
     cam = camera(W, H, focal)
+    _hold(stream, hard)
     _check(lib().mr_shadow_hard(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(sp), _ptr(hard), _stream(stream)))
     return hard
 
@@ -499,6 +521,7 @@ def mr_upsample_merge(focal, mp: MaskParams, masks: Masks, level_out: dict, chan
     cam = camera(W, H, focal)
     cmp = mp.c()
     cm = masks.c()
+    _hold(stream, out)
     _check(lib().mr_upsample_merge(ctypes.byref(cam), ctypes.byref(cmp), ctypes.byref(cm), ctypes.byref(arr),
                                    int(channels), _ptr(out), _stream(stream)))
     return out
@@ -622,9 +645,7 @@ class FrameRunner:
         keeps its workspace and output alive for that stream: torch's caching
         allocator would otherwise hand their memory to the next allocation on
         the current stream while the frame still runs."""
-        if stream is not None and stream != torch.cuda.current_stream():
-            self.workspace.record_stream(stream)
-            self.out.record_stream(stream)
+        _hold(stream, self.workspace, self.out)
 
     def __call__(self, stream=None):
         self._hold_for(stream)
@@ -705,10 +726,7 @@ class CachedFrameRunner(FrameRunner):
         self._cfn = lib().mr_frame_cached
 
     def __call__(self, stream=None, build=True):
-        if stream is not None and stream != torch.cuda.current_stream():
-            self.workspace.record_stream(stream)
-            self.out.record_stream(stream)
-            self.pyramid.record_stream(stream)
+        _hold(stream, self.workspace, self.out, self.pyramid)
         _check(self._cfn(ctypes.byref(self.desc), self._pyr, self._npyr, 1 if build else 0, self._ws, self._nws,
                          _stream(stream)))
         return self.out
@@ -727,8 +745,7 @@ class StaticFrameRunner(FrameRunner):
         self._fn = lib().mr_frame_static
 
     def __call__(self, stream=None):
-        if stream is not None and stream != torch.cuda.current_stream():
-            self.out.record_stream(stream)
+        _hold(stream, self.out)
         _check(self._fn(ctypes.byref(self.desc), _stream(stream)))
         return self.out
 
@@ -792,6 +809,7 @@ class Batch:
         self._run = lib().mr_batch_run
 
     def __call__(self, stream=None):
+        _hold(stream, self.workspace, *self.outs)
         _check(self._run(ctypes.cast(self.plan, ctypes.c_void_p), _stream(stream)))
         return self.outs
 
@@ -854,12 +872,7 @@ class BatchSlot:
         mask pyramid (mr_batch_setup_cached: evaluation and merge only)."""
         eff = EFFECTS[effect] if isinstance(effect, str) else int(effect)
         descs, outs, keep = _batch_descs(eff, frames, mp, params, level_dtype)
-        if stream is not None and stream != torch.cuda.current_stream():
-            self.workspace.record_stream(stream)
-            for o in outs:
-                o.record_stream(stream)
-            for t in pyramids or ():
-                t.record_stream(stream)
+        _hold(stream, self.workspace, *outs, *(pyramids or ()))
         if pyramids is not None:
             pp = (ctypes.c_void_p * len(frames))(*[t.data_ptr() for t in pyramids])
             keep = keep + [pyramids, pp]

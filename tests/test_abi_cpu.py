@@ -272,6 +272,31 @@ def test_frame_on_another_stream_holds_its_memory(monkeypatch):
     assert fr.workspace.streams == [other] and fr.out.streams == [other]
 
 
+def test_step_calls_on_another_stream_hold_what_they_use(monkeypatch):
+    """The step entry points record a foreign stream on every tensor they
+    write (the mask pyramid with its workspace, the level outputs, the merged
+    image), and on none for the current stream or no stream."""
+    class FakeTensor:
+        def __init__(self):
+            self.streams = []
+
+        def record_stream(self, s):
+            self.streams.append(s)
+
+    current, other = object(), object()
+    monkeypatch.setattr(mr.torch.cuda, "current_stream", lambda: current)
+    m = mr.Masks(W=64, H=64, mp=mr.MaskParams(), edge=FakeTensor(), count=FakeTensor(), level_map=FakeTensor(),
+                 alpha={2: FakeTensor()}, stencil={2: FakeTensor()}, worklist={2: FakeTensor()},
+                 level_depth={2: FakeTensor(), 4: FakeTensor()}, workspace=FakeTensor())
+    ts = m.tensors()
+    assert len(ts) == 9 and len({id(t) for t in ts}) == 9
+    mr._hold(None, *ts)
+    mr._hold(current, *ts)
+    assert all(t.streams == [] for t in ts)
+    mr._hold(other, *ts, None)
+    assert all(t.streams == [other] for t in ts)
+
+
 def test_binding_constants_mirror_the_header():
     """Every MR_* integer constant the binding defines equals the header's
     #define of the same name (and the header defines it)."""
