@@ -518,7 +518,13 @@ MR_API int mr_batch_setup_cached(const mr_frame_desc* frames, void* const* pyram
  *                       a frame's workers share its chunks through per-XCD
  *                       counters
  *   tiles_per_ticket    persistent launch: edge and merge tiles per ticket
- *                       (1 .. 64; 0: 16) */
+ *                       (1 .. 64; 0: 16)
+ *   eval_halo           SSAO batches that build their masks, staged
+ *                       launches with eval_queue = 0 and at most 256
+ *                       samples: 0, or 8, 16 or 24 to evaluate every frame's
+ *                       dense coarsest level in 16 x 16 texel tiles whose
+ *                       depth, with a border of that many texels, is staged
+ *                       in LDS (as mr_frame_desc.eval_halo) */
 typedef struct mr_batch_config {
     int edge_tile;
     int eval_queue;
@@ -528,6 +534,7 @@ typedef struct mr_batch_config {
     int eval_items;
     int worker_pixels;
     int tiles_per_ticket;
+    int eval_halo;
 } mr_batch_config;
 
 /* Read or replace a filled plan's configuration (MR_E_PARAM for a plan not
@@ -539,9 +546,10 @@ MR_API int mr_batch_set_config(void* plan, const mr_batch_config* cfg);
 /* Autotuner: times the batch (one warm-up run, then `reps` runs, 1..1000) on
  * `stream` under candidate configurations, one choice at a time (the
  * evaluation's schedule and grid cap first, then the edge tile shape and
- * the merge kernel, then the persistent launch with two worker sizes and
- * one or two texels per evaluation thread and, if it is the faster, its
- * tiles per ticket), keeps the
+ * the merge kernel, then for SSAO the LDS depth-tile halo of 8, 16 or 24
+ * texels, then the persistent launch with two worker sizes and one or two
+ * texels per evaluation thread and, if it is the faster, its tiles per
+ * ticket), keeps the
  * fastest in the plan and, when best is not NULL, in *best.  It runs the batch on its current inputs and waits for the
  * stream: not for use under graph capture.  Outputs after it are those of a
  * plain run. */

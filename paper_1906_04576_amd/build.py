@@ -26,7 +26,8 @@ LIB = os.path.join(HERE, "libmr.so")
 CODE = os.path.join(HERE, "libmr.code.json")
 LLVM = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin")
 
-SOURCES = ["api.cpp", "k_masks.hip", "k_compact.hip", "k_ssao.hip", "k_shadow.hip", "k_ssgi.hip", "k_fused.hip",
+SOURCES = ["api.cpp", "k_masks.hip", "k_compact.hip", "k_ssao.hip", "k_ssao_tiles.hip", "k_shadow.hip", "k_ssgi.hip",
+           "k_fused.hip",
            "k_merge.hip",
            "k_lean.hip", "k_bilateral.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1099,6 +1099,13 @@ int check_config(const BatchPlan& P, const mr_batch_config& c) {
         return fail(MR_E_PARAM, "worker_pixels %d not 0 or in [4096, 2^24]", c.worker_pixels);
     if (c.tiles_per_ticket < 0 || c.tiles_per_ticket > 64)
         return fail(MR_E_PARAM, "tiles_per_ticket %d outside [0, 64]", c.tiles_per_ticket);
+    if (c.eval_halo != 0) {
+        if (c.eval_halo != 8 && c.eval_halo != 16 && c.eval_halo != 24)
+            return fail(MR_E_PARAM, "eval_halo %d is not 0, 8, 16 or 24", c.eval_halo);
+        if (P.effect != MR_EFFECT_SSAO || P.cached || c.persistent || c.eval_queue || P.S > kTiledSamplesHost)
+            return fail(MR_E_PARAM, "eval_halo applies to SSAO batches that build their masks, with staged "
+                                    "launches, eval_queue = 0 and at most %d samples", kTiledSamplesHost);
+    }
     return MR_OK;
 }
 
@@ -1144,7 +1151,10 @@ int run_plan(const BatchPlan& P, hipStream_t s) {
     }
     const BatchSchedule bs{c.eval_queue != 0, c.eval_blocks_per_cu, P.queue};
     hipError_t e;
-    if (P.effect == MR_EFFECT_SSAO)
+    if (P.effect == MR_EFFECT_SSAO && c.eval_halo)
+        e = launch_ssao_batch_tiled(static_cast<const SsaoArgs*>(P.tv), P.n, P.S, P.ndt, c.eval_halo, P.eval_hint,
+                                    s);
+    else if (P.effect == MR_EFFECT_SSAO)
         e = launch_ssao_batch(static_cast<const SsaoArgs*>(P.tv), P.n, P.S, P.ndt, P.eval_hint, bs, s);
     else
         e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.S, P.ndt, P.cdt, P.eval_hint, bs, s);
@@ -1874,6 +1884,13 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
         c.merge_generic = 1 - bc.merge_generic;
         consider(c);
     }
+    // SSAO: the dense coarsest level in LDS depth tiles (fixed strides)
+    for (int h : {8, 16, 24}) {
+        mr_batch_config c = bc;
+        c.eval_queue = 0;
+        c.eval_halo = h;
+        consider(c);  // check_config skips what does not apply
+    }
     // the persistent launch, with the staged launches' merge choice
     if (fused_ok(P)) {
         const mr_batch_config staged = bc;
@@ -1881,6 +1898,7 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
             for (int it : {1, 2}) {
                 mr_batch_config c = staged;
                 c.persistent = 1;
+                c.eval_halo = 0;
                 c.worker_pixels = wp;
                 c.eval_items = it;
                 consider(c);

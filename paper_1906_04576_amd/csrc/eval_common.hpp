@@ -24,6 +24,9 @@ struct ItemMap {
 constexpr int kDenseTile = 16;
 __host__ __device__ __forceinline__ unsigned dense_tiles_x(int W) { return (unsigned)(W + kDenseTile - 1) / kDenseTile; }
 
+// TILES: the dense coarsest level in 16 x 16 texel tiles even where
+// c.dense_tiles is not set (the batch launch with LDS depth tiles)
+template <bool TILES = false>
 __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
     ItemMap m;
     m.nlev = c.nlev;
@@ -35,7 +38,7 @@ __device__ __forceinline__ ItemMap make_item_map(const EvalCommon& c) {
             const EvalLevel& L = c.lv[j];
             // a list never holds more entries than its level has texels
             n = L.list ? min(c.counts[L.count_idx], L.dense_n) : L.dense_n;
-            if (c.dense_tiles && j == c.nlev - 1 && !L.list) {
+            if ((TILES || c.dense_tiles) && j == c.nlev - 1 && !L.list) {
                 n = dense_tiles_x(L.W) * ((unsigned)(L.H + kDenseTile - 1) / kDenseTile) * 256u;
                 m.cum[j] = (m.cum[j] + 255u) & ~255u;  // a chunk per tile
             }
@@ -127,14 +130,14 @@ constexpr int kMaxBatch = kMaxBatchFrames;
 
 // cbase[f] = first chunk (of `per` items, a multiple of 256) of frame f in a
 // batch's item space, cbase[n] = total: each frame's item range (from its
-// device counts) rounded up to whole chunks.  Computed by the first wave;
-// ends with a barrier.
-template <typename Args>
+// device counts; TILES: with the dense coarsest level in tiles) rounded up
+// to whole chunks.  Computed by the first wave; ends with a barrier.
+template <bool TILES = false, typename Args>
 __device__ __forceinline__ void batch_chunk_bases(const Args* T, int n, unsigned per, unsigned* cbase) {
     if (threadIdx.x < 64) {
         const int f = threadIdx.x;
         unsigned cnt = 0;
-        if (f < n) cnt = (item_total(make_item_map(T[f].c)) + per - 1u) / per;
+        if (f < n) cnt = (item_total(make_item_map<TILES>(T[f].c)) + per - 1u) / per;
         unsigned inc = cnt;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {

@@ -18,7 +18,6 @@ __global__ __launch_bounds__(256) void k_ssao(SsaoArgs a) {
 // The compact frame path with the coarsest level in 16 x 16 tiles whose depth
 // (with a halo of H texels) is staged in LDS; at most kTiledSamples samples,
 // staged in LDS as well.
-constexpr int kTiledSamples = 256;
 template <typename NT, int H>
 __global__ __launch_bounds__(256) void k_ssao_tiled(SsaoArgs a) {
     __shared__ float ks[3 * kTiledSamples];

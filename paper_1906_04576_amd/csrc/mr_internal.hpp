@@ -400,6 +400,10 @@ struct BatchSchedule {
 };
 hipError_t launch_ssao_batch(const SsaoArgs* T, int n, int S, int normal_dtype, unsigned total_hint,
                              const BatchSchedule& bs, hipStream_t s);
+// the SSAO batch with LDS depth tiles of the dense coarsest level (halo 8, 16
+// or 24 texels; at most 256 samples)
+hipError_t launch_ssao_batch_tiled(const SsaoArgs* T, int n, int S, int normal_dtype, int halo, unsigned total_hint,
+                                   hipStream_t s);
 hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int S, int normal_dtype, int color_dtype,
                              unsigned total_hint, const BatchSchedule& bs, hipStream_t s);
 hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,

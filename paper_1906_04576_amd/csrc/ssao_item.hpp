@@ -246,6 +246,52 @@ __device__ __forceinline__ void ssao_items_tiled(const SsaoArgs& a, const float*
     }
 }
 
+// One chunk c of a frame's item space with the dense coarsest level in
+// tiles (m built with TILES): a chunk of list items, or one 16 x 16 tile of
+// the dense level evaluated from its LDS depth tile as in ssao_items_tiled.
+// Every thread of the block takes part (the tile staging ends with
+// barriers).  Used by the batch launch, whose frames share the LDS.
+template <typename NT, int H>
+__device__ __forceinline__ void ssao_chunk_tiled(const SsaoArgs& a, const ItemMap& m, unsigned c, const float* ks,
+                                                 const float* eg, float kmax, float* zt) {
+    constexpr int TW = kDenseTile + 2 * H;
+    const unsigned total = item_total(m);
+    const int jd = m.nlev - 1;  // the dense coarsest level
+    unsigned dense0 = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) dense0 = k == jd ? m.cum[k] : dense0;
+    if (c * 256u < dense0) {
+        const unsigned item = c * 256u + threadIdx.x;
+        if (item < total) ssao_item<NT, true, true>(a, m, item, ks, eg, kmax);
+        return;
+    }
+    const NT* nrm = static_cast<const NT*>(a.c.normal);
+    const unsigned plane = (unsigned)a.c.plane;
+    const EvalLevel& L = a.c.lv[jd];
+    const unsigned tile = c - dense0 / 256u, tx = dense_tiles_x(L.W);
+    const int x0 = (int)(tile % tx) * kDenseTile, y0 = (int)(tile / tx) * kDenseTile;
+    for (int i = threadIdx.x; i < TW * TW; i += 256) {
+        const int ry = i / TW, rx = i - ry * TW;
+        const int gx = min(max(x0 - H + rx, 0), L.W - 1), gy = min(max(y0 - H + ry, 0), L.H - 1);
+        zt[i] = L.z[(unsigned)gy * (unsigned)L.zpy + (unsigned)gx * (unsigned)L.zpx];
+    }
+    __syncthreads();
+    const int x = x0 + (int)(threadIdx.x % kDenseTile), y = y0 + (int)(threadIdx.x / kDenseTile);
+    if (x < L.W && y < L.H) {
+        const float z = zt[(y - y0 + H) * TW + (x - x0 + H)];
+        float res = 0.0f;
+        if (valid_depth(z)) {
+            const DepthTile dt{zt, (unsigned)(x0 - H), (unsigned)(y0 - H), (unsigned)TW};
+            res = ssao_texel<NT, kGroupMulti, true>(a, L, nrm, plane, ks, kmax, x, y, z, dt);
+        }
+        store_out(L, (unsigned)y * (unsigned)L.W + (unsigned)x, res);
+    }
+    __syncthreads();  // the next tile's staging overwrites zt
+}
+
+// samples of the tiled evaluation (staged in LDS with the depth tile)
+constexpr int kTiledSamples = 256;
+
 // Per block: the blur taps (AL) and, KLDS, the S <= kLdsSamples samples in
 // LDS; returns the largest |component| of the samples (+inf when not staged).
 template <bool AL, bool KLDS>

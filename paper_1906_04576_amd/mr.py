@@ -107,7 +107,7 @@ class mr_frame_desc(ctypes.Structure):
 class mr_batch_config(ctypes.Structure):
     _fields_ = [("edge_tile", ctypes.c_int), ("eval_queue", ctypes.c_int), ("eval_blocks_per_cu", ctypes.c_int),
                 ("merge_generic", ctypes.c_int), ("persistent", ctypes.c_int), ("eval_items", ctypes.c_int),
-                ("worker_pixels", ctypes.c_int), ("tiles_per_ticket", ctypes.c_int)]
+                ("worker_pixels", ctypes.c_int), ("tiles_per_ticket", ctypes.c_int), ("eval_halo", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -181,7 +181,7 @@ def test_graph_capture_replays_to_eager():
 
 
 CONFIGS = [dict(edge_tile=t, eval_queue=q, eval_blocks_per_cu=b, merge_generic=m, persistent=0, eval_items=i,
-                worker_pixels=0, tiles_per_ticket=0)
+                worker_pixels=0, tiles_per_ticket=0, eval_halo=0)
            for t, q, b, m, i in ((0, 0, 0, 0, 0), (1, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 1, 2, 0, 0), (0, 0, 1, 0, 0),
                                  (0, 0, 0, 1, 0), (1, 1, 3, 1, 0))]
 
@@ -213,11 +213,67 @@ def test_config_rejects_out_of_range_values():
     _, _, p = effect_params("ssao")
     b = mr.Batch("ssao", frames_for("ssao", SIZES[:2]), mp, p)
     for bad in (dict(edge_tile=2), dict(eval_queue=-1), dict(eval_blocks_per_cu=65), dict(merge_generic=3),
-                dict(persistent=2), dict(eval_items=3), dict(worker_pixels=100), dict(tiles_per_ticket=65)):
+                dict(persistent=2), dict(eval_items=3), dict(worker_pixels=100), dict(tiles_per_ticket=65),
+                dict(eval_halo=5), dict(eval_halo=8, eval_queue=1), dict(eval_halo=16, persistent=1)):
         with pytest.raises(mr.MRError) as e:
             b.config = bad
         assert e.value.status == mr.MR_E_PARAM
         assert b.config == CONFIGS[0]
+    # LDS depth tiles apply to SSAO only
+    mg = mask_params("ssgi")
+    _, _, pg = effect_params("ssgi")
+    bg = mr.Batch("ssgi", frames_for("ssgi", SIZES[:2]), mg, pg)
+    with pytest.raises(mr.MRError) as e:
+        bg.config = dict(eval_halo=8)
+    assert e.value.status == mr.MR_E_PARAM and "SSAO" in str(e.value)
+
+
+@pytest.mark.parametrize("level_dtype,f16n", [(torch.float32, False), (torch.float16, True)])
+def test_lds_depth_tiles_in_a_batch(level_dtype, f16n):
+    """eval_halo 8, 16 and 24: every frame's dense coarsest level evaluated
+    from LDS depth tiles gives the images of the plane-gathering batch and of
+    the frames alone, bit for bit; one frame also against the oracle."""
+    mp = mask_params("ssao")
+    K, r, p = effect_params("ssao")
+    fr = frames_for("ssao", SIZES, f16n)
+    b = mr.Batch("ssao", fr, mp, p, level_dtype=level_dtype)
+    ref = [o.clone() for o in b()]
+    torch.cuda.synchronize()
+    for f, o in zip(fr, ref):
+        assert torch.equal(o, alone("ssao", f, mp, p, level_dtype))
+    for h in (8, 16, 24):
+        log(f"[gpu] batch with LDS depth tiles, halo {h}, {level_dtype}, f16 normals={f16n}")
+        b.config = dict(eval_halo=h)
+        for o in b.outs:
+            o.fill_(float("nan"))
+        b()
+        torch.cuda.synchronize()
+        for o, rr in zip(b.outs, ref):
+            assert torch.equal(o, rr)
+    sc = scene(*SIZES[1], 1)
+    nrm = sc["gb"].normal.astype(np.float16).astype(np.float32) if f16n else sc["gb"].normal
+    want = oracle.frame("ssao", sc["gb"].depth, nrm, sc["gb"].focal, mask_params("ssao", oracle),
+                        oracle.SSAOParams(K, r, 0.02),
+                        level_dtype=np.float16 if level_dtype == torch.float16 else None).out
+    assert np.array_equal(b.outs[1].cpu().numpy(), want)
+
+
+def test_tuner_of_an_ssao_batch_keeps_the_outputs():
+    mp = mask_params("ssao")
+    _, _, p = effect_params("ssao")
+    b = mr.Batch("ssao", frames_for("ssao", SIZES), mp, p)
+    ref = [o.clone() for o in b()]
+    torch.cuda.synchronize()
+    log("[gpu] tuning an SSAO batch")
+    cfg = b.tune(reps=2)
+    log(f"[gpu] tuned {cfg}")
+    assert b.config == cfg and cfg["eval_halo"] in (0, 8, 16, 24)
+    assert not (cfg["eval_halo"] and (cfg["persistent"] or cfg["eval_queue"]))
+    b()
+    b.check()
+    torch.cuda.synchronize()
+    for o, rr in zip(b.outs, ref):
+        assert torch.equal(o, rr)
 
 
 def test_tuner_keeps_a_valid_configuration_and_the_outputs():

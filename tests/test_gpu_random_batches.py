@@ -2,7 +2,8 @@
 seed an effect (SSAO or SSGI), 2-4 levels with a random enabled set, the
 samples, the sub-image storage (FP32 or FP16) and 1-9 frames of random
 sizes, scenes and cameras are drawn; the batch runs with one launch per
-stage and as one persistent launch (Sec. 3-4 for a set of frames), and every
+stage and as one persistent launch (Sec. 3-4 for a set of frames), SSAO
+batches also with LDS depth tiles of the dense coarsest level, and every
 frame's image equals the oracle's frame bit for bit.
 
 Batched frames take the compact path, so widths are multiples of 128 and
@@ -104,7 +105,8 @@ def test_random_batch(seed):
     st = torch.cuda.current_stream()
     batch = mr.Batch(b["effect"], frames, mp, sp, level_dtype=torch.float16 if b["f16"] else torch.float32,
                      stream=st)
-    for cfg in CONFIGS:
+    extra = (dict(persistent=0, eval_halo=(8, 16, 24)[seed % 3]),) if b["effect"] == "ssao" else ()
+    for cfg in CONFIGS + extra:
         batch.config = cfg
         for o in batch.outs:
             o.fill_(-1.0)
