@@ -65,7 +65,7 @@ extern "C" {
 #define MR_MAX_RADIUS 16   /* largest blur radius in level texels */
 #define MR_MAX_SAMPLES 8192
 #define MR_MAX_DIM 16384
-#define MR_VERSION 100
+#define MR_VERSION 101
 #define MR_FRAME_EVENTS 5  /* stage events of mr_frame_desc */
 
 /* status codes */

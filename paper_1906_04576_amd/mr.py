@@ -18,6 +18,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmr.so")
 
+# the header version whose structs this module mirrors
+MR_VERSION = 101
 MR_MAX_LEVELS = 6
 MR_MAX_DIM = 16384
 MR_OK, MR_E_NULL, MR_E_SHAPE, MR_E_PARAM, MR_E_WORKSPACE, MR_E_DTYPE, MR_E_DEVICE = 0, -1, -2, -3, -4, -5, -6
@@ -194,6 +196,9 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.mr_version() != MR_VERSION:
+            raise RuntimeError(f"{LIB_PATH} is version {L.mr_version()}, this binding mirrors version {MR_VERSION}; "
+                               "rebuild it with paper_1906_04576_amd/build.py")
         _lib = L
     return _lib
 

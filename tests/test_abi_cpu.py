@@ -72,10 +72,20 @@ def test_struct_layout_matches_the_c_compiler(tmp_path):
 
 
 def test_version_and_status_strings():
-    assert mr.mr_version() == 100
+    assert mr.mr_version() == mr.MR_VERSION == 101
     assert mr.mr_status_string(0) == "MR_OK"
     for s in range(-6, 0):
         assert mr.mr_status_string(s).startswith("MR_E_")
+
+
+def test_binding_refuses_a_library_of_another_version(monkeypatch):
+    """A libmr.so built from another header version (other struct layouts)
+    is refused when it is loaded, not misread later."""
+    mr.lib()
+    monkeypatch.setattr(mr, "_lib", None)
+    monkeypatch.setattr(mr, "MR_VERSION", mr.MR_VERSION + 1)
+    with pytest.raises(RuntimeError, match="version"):
+        mr.lib()
 
 
 def test_workspace_bytes_validation():
