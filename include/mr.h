@@ -502,11 +502,12 @@ MR_API int mr_batch_setup_cached(const mr_frame_desc* frames, void* const* pyram
  *                       1: the general merge
  *   persistent          0: one launch per stage; 1: the whole batch in one
  *                          launch of resident blocks that take tickets from
- *                          one counter in stage order (every edge tile, then
- *                          every ranking tile twice -- stencil, then list --,
- *                          evaluation workers, merge tiles; frames in order
- *                          within a stage), a ticket first waiting until the
- *                          previous stage of its frame has finished.  Needs
+ *                          one counter in stage order (edge tiles, then the
+ *                          ranking tiles twice -- stencil, then list -- in
+ *                          groups of 8, evaluation workers, merge tiles; frames
+ *                          in order within a stage), a ticket first waiting
+ *                          until the previous stage of its frame has
+ *                          finished.  Needs
  *                          frames of at most 4 levels and at most 256
  *                          samples (else MR_E_PARAM); edge_tile,
  *                          eval_queue and eval_blocks_per_cu do not apply.
