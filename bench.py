@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the paper variants (bilateral blur, foveated mask, fewer samples at full resolution)")
     ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batched uneven-frame SSGI measurement (24 frames, 640x360..3840x2160)")
+                    help="skip the batched uneven-frame SSGI and SSAO measurements (24 frames, 640x360..3840x2160)")
     ap.add_argument("--no-sweeps", action="store_true",
                     help="skip the sample-count sweep (16..256 at 4K) and the resolution sweep (720p..4K at S = 64)")
     ap.add_argument("--no-pcss", action="store_true",
@@ -543,13 +543,16 @@ def main():
             roofline["valu_rate_vs_plain"] = round(rate_m / rate_p, 4)
         log("[bench] stages (ms): " + ", ".join(f"{k}={v}" for k, v in stages.items() if k.endswith("_ms")))
 
-    # ---------------- batched uneven SSGI frames (graph-replayed batch) ----------------
-    batched = None
+    # ---------------- batched uneven SSGI and SSAO frames (graph-replayed batches) ----------------
+    batched = batched_ssao = None
     if not args.no_batch:
         from paper_1906_04576_amd import batched as batched_mod
         batched = batched_mod.measure(steps=20, device=dev)
         log(f"[bench] batched SSGI: {batched['mpixels_s']} Mpixels/s, {batched['speedup_vs_plain']}x naive, "
             f"{batched['speedup_vs_sequential']}x one after another")
+        batched_ssao = batched_mod.measure_ssao(steps=20, device=dev)
+        log(f"[bench] batched SSAO: {batched_ssao['mpixels_s']} Mpixels/s, by eval_halo "
+            f"{batched_ssao['graph_ms_by_eval_halo']} ms, tuned eval_halo {batched_ssao['tuned_config']['eval_halo']}")
 
     # ---------------- sweeps, soft shadows at 4K, serving ----------------
     sweeps = None
@@ -647,6 +650,7 @@ def main():
         "roofline": roofline,
         "variants": variants,
         "batched_ssgi": batched,
+        "batched_ssao": batched_ssao,
         "sweeps": sweeps,
         "pcss_4k": pcss,
         "serving": serving_res,

@@ -143,6 +143,65 @@ def measure(steps=20, frames=None, device="cuda"):
     }
 
 
+def measure_ssao(steps=20, frames=None, device="cuda", samples=32):
+    """The same uneven frames as one SSAO batch (Table 1 SSAO masks, all four
+    levels): graph-replayed staged launches with the dense coarsest level's
+    depth gathered from the plane (eval_halo 0) and from LDS tiles with a halo
+    of 8, 16 and 24 texels, the tuner's choice, and the frames one after
+    another."""
+    import scenegen
+    frames = [dict(f, color=None) for f in (frames or make_frames(device=device))]
+    npx = sum(f["depth"].numel() for f in frames)
+    t = scenegen.TABLE1["ssao"]
+    mp = mr.MaskParams(num_levels=4, level_enable=0xF, sigma2=t["sigma2"], weight=t["weight"],
+                       normal_cos=float(np.float32(math.cos(math.radians(25.0)))))
+    p = mr.ssao_params(torch.from_numpy(scenegen.ssao_kernel(samples)).to(device), 1.0, 0.02)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        b = mr.Batch("ssao", frames, mp, p, stream=st)
+        b(st)
+    st.synchronize()
+    ms, outs = {}, {}
+    for h in (0, 8, 16, 24):
+        b.config = dict(eval_halo=h)
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=st):
+            b(st)
+        gr.replay()
+        ms[h] = round(_wall(gr.replay, steps) * 1e3, 4)
+        outs[h] = [o.clone() for o in b.outs]
+    b.config = dict(eval_halo=0)
+    with torch.cuda.stream(st):
+        cfg = b.tune(reps=3, stream=st)
+    st.synchronize()
+    nws = max(mr.mr_workspace_bytes(f["depth"].shape[1], f["depth"].shape[0], f["focal"], mp, mr.MR_EFFECT_SSAO)
+              for f in frames)
+    ws = torch.empty(nws, dtype=torch.uint8, device=device)
+    seq = [mr.FrameRunner("ssao", f["depth"], f["normal"], f["focal"], mp, True, params=p, workspace=ws)
+           for f in frames]
+
+    def run_all():
+        for r in seq:
+            r()
+
+    run_all()
+    t_seq = _wall(run_all, steps)
+    same = True
+    for r, k in zip(seq, range(len(seq))):
+        r()
+        torch.cuda.synchronize()
+        same = same and all(torch.equal(outs[h][k], r.out) for h in outs)
+    log(f"[batched] SSAO batch ms by eval_halo {ms}, tuned {cfg}, one after another {t_seq * 1e3:.3f} ms")
+    return {
+        "workload": f"{len(frames)} SSAO frames of uneven sizes (640x360..3840x2160), {samples} samples r=1.0, "
+                    f"4 levels",
+        "mpixels": round(npx / 1e6, 3), "graph_ms_by_eval_halo": {str(h): v for h, v in ms.items()},
+        "mpixels_s": round(npx / (ms[0] * 1e-3) / 1e6, 2), "tuned_config": cfg,
+        "sequential_ms": round(t_seq * 1e3, 4), "speedup_vs_sequential": round(t_seq * 1e3 / ms[0], 3),
+        "identical_to_frames_alone": bool(same),
+    }
+
+
 def main():
     print(json.dumps(measure()), flush=True)
 
