@@ -497,8 +497,8 @@ MR_API int mr_batch_setup_cached(const mr_frame_desc* frames, void* const* pyram
  *                          from a counter in the workspace
  *   eval_blocks_per_cu  cap on evaluation blocks per CU, 0..64; 0: as many
  *                       as can be resident
- *   merge_generic       0: the four-level merge with fixed tap geometry
- *                          where it applies (levels 1..4 all enabled),
+ *   merge_generic       0: a merge with fixed tap geometry where one applies
+ *                          (the levels 1, 2, 3, 4 or 1, 3, 4 enabled),
  *                       1: the general merge
  *   persistent          0: one launch per stage; 1: the whole batch in one
  *                          launch of resident blocks that take tickets from

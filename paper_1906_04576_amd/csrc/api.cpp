@@ -976,6 +976,7 @@ struct BatchPlan {
     uint32_t magic;
     int n, effect, ndt, cdt, S, C;
     bool c16, m4_ok, wide_ok;
+    int merge_geo;  // merge kernel of the frames (merge_geometry) when merge_generic = 0
     bool cached;  // evaluation and merge on resident mask pyramids only
     mr_batch_config cfg;
     const EdgeArgs* te;
@@ -1160,7 +1161,7 @@ int run_plan(const BatchPlan& P, hipStream_t s) {
         e = launch_ssgi_batch(static_cast<const SsgiArgs*>(P.tv), P.n, P.S, P.ndt, P.cdt, P.eval_hint, bs, s);
     if (e != hipSuccess) return fail(MR_E_DEVICE, "batched evaluation kernel launch failed");
     if (launch_lean_merge_batch(P.tm, P.merge_base, P.merge_tx, P.n, P.merge_total, P.C, P.c16,
-                                P.m4_ok && !c.merge_generic, s) != hipSuccess)
+                                c.merge_generic ? kMergeGeneral : P.merge_geo, s) != hipSuccess)
         return fail(MR_E_DEVICE, "batched merge kernel launch failed");
     return MR_OK;
 }
@@ -1721,6 +1722,7 @@ int batch_setup(const mr_frame_desc* frames, void* const* pyramids, int n, void*
         hint += L.ev.hint + 1024u;  // + padding of the levels' and frame's item ranges
         if (k == 0) {
             P.m4_ok = merge4_applies(L.ma);
+            P.merge_geo = merge_geometry(L.ma);
             P.S = effect == MR_EFFECT_SSAO ? L.ev.sa.S : L.ev.gi.S;
         }
     }
@@ -1879,7 +1881,7 @@ int mr_batch_tune(void* plan, int reps, mr_batch_config* best, void* stream) {
         c.edge_tile = t;
         if (t != bc.edge_tile) consider(c);
     }
-    if (P.m4_ok) {
+    if (P.merge_geo != kMergeGeneral) {
         mr_batch_config c = bc;
         c.merge_generic = 1 - bc.merge_generic;
         consider(c);

@@ -89,23 +89,25 @@ void k_lean_merge(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
     merge_tile<C, VT>(a, xcd_remap(blockIdx.x, ntiles), tiles_x, la, ls, lc, lvl_any);
 }
 
-template <int C, typename VT>
+// L2 false: the levels 1, 3 and 4
+template <int C, typename VT, bool L2>
 __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned tiles_x, unsigned ntiles) {
     __shared__ Merge4Lds<C> sm;
-    merge4_tile<C, VT>(a, xcd_remap(blockIdx.x, ntiles), tiles_x, sm);
+    merge4_tile<C, VT, L2>(a, xcd_remap(blockIdx.x, ntiles), tiles_x, sm);
 }
 
-// frames of a batch: tile_base[f] = first merge tile of frame f
-template <int C, typename VT, bool M4>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M4 ? 1 : merge_waves(C))))
+// frames of a batch: tile_base[f] = first merge tile of frame f; GEO one of
+// kMergeGeneral, kMerge1234, kMerge134
+template <int C, typename VT, int GEO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEO != kMergeGeneral ? 1 : merge_waves(C))))
 void k_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base,
                                                           const unsigned* tiles_x, int n) {
     const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
     int f = 0;
     for (int k = 1; k < n; ++k) f += g >= tile_base[k] ? 1 : 0;
-    if constexpr (M4) {
+    if constexpr (GEO != kMergeGeneral) {
         __shared__ Merge4Lds<C> sm;
-        merge4_tile<C, VT>(T[f], g - tile_base[f], tiles_x[f], sm);
+        merge4_tile<C, VT, GEO == kMerge1234>(T[f], g - tile_base[f], tiles_x[f], sm);
     } else {
         __shared__ float la[kMergeLDS];
         __shared__ uint8_t ls[kMergeLDS];
@@ -123,21 +125,33 @@ bool merge4_applies(const LeanMergeArgs& a) {
     return true;
 }
 
+// levels 1, 3, 4 with level 1 by rank (SSGI's Table 1 column)
+bool merge134_applies(const LeanMergeArgs& a) {
+    return a.nlev == 3 && a.fine1 && (a.W & 3) == 0 && a.lv[0].sh == 0 && a.lv[1].sh == 2 && a.lv[2].sh == 3;
+}
+
+int merge_geometry(const LeanMergeArgs& a) {
+    return merge4_applies(a) ? kMerge1234 : (merge134_applies(a) ? kMerge134 : kMergeGeneral);
+}
+
 template <typename VT>
 hipError_t launch_lean_merge_t(const LeanMergeArgs& a, hipStream_t s) {
     const unsigned tx = (a.W + kMergeTW - 1) / kMergeTW, ty = (a.H + kMergeTH - 1) / kMergeTH;
-    const bool m4 = merge4_applies(a);
-    if (a.C == 3) {
-        if (m4)
-            hipLaunchKernelGGL((k_lean_merge4<3, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
-        else
-            hipLaunchKernelGGL((k_lean_merge<3, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
-    } else {
-        if (m4)
-            hipLaunchKernelGGL((k_lean_merge4<1, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
-        else
-            hipLaunchKernelGGL((k_lean_merge<1, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
-    }
+    const int geo = merge_geometry(a);
+#define MR_LM(CC)                                                                                              \
+    do {                                                                                                       \
+        if (geo == kMerge1234)                                                                                 \
+            hipLaunchKernelGGL((k_lean_merge4<CC, VT, true>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);  \
+        else if (geo == kMerge134)                                                                             \
+            hipLaunchKernelGGL((k_lean_merge4<CC, VT, false>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_lean_merge<CC, VT>), dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);         \
+    } while (0)
+    if (a.C == 3)
+        MR_LM(3);
+    else
+        MR_LM(1);
+#undef MR_LM
     return hipGetLastError();
 }
 
@@ -146,26 +160,26 @@ hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
-                                   unsigned total, int C, bool c16, bool m4, hipStream_t s) {
-#define MR_MB(CC, VT, M) \
-    hipLaunchKernelGGL((k_lean_merge_batch<CC, VT, M>), dim3(total), dim3(256), 0, s, T, tile_base, tiles_x, n)
+                                   unsigned total, int C, bool c16, int geo, hipStream_t s) {
+#define MR_MB(CC, VT, G) \
+    hipLaunchKernelGGL((k_lean_merge_batch<CC, VT, G>), dim3(total), dim3(256), 0, s, T, tile_base, tiles_x, n)
+#define MR_MBG(CC, VT)                  \
+    do {                                \
+        if (geo == kMerge1234)          \
+            MR_MB(CC, VT, kMerge1234);  \
+        else if (geo == kMerge134)      \
+            MR_MB(CC, VT, kMerge134);   \
+        else                            \
+            MR_MB(CC, VT, kMergeGeneral); \
+    } while (0)
     if (C == 3) {
-        if (c16) {
-            if (m4) MR_MB(3, _Float16, true);
-            else MR_MB(3, _Float16, false);
-        } else {
-            if (m4) MR_MB(3, float, true);
-            else MR_MB(3, float, false);
-        }
+        if (c16) MR_MBG(3, _Float16);
+        else MR_MBG(3, float);
     } else {
-        if (c16) {
-            if (m4) MR_MB(1, _Float16, true);
-            else MR_MB(1, _Float16, false);
-        } else {
-            if (m4) MR_MB(1, float, true);
-            else MR_MB(1, float, false);
-        }
+        if (c16) MR_MBG(1, _Float16);
+        else MR_MBG(1, float);
     }
+#undef MR_MBG
 #undef MR_MB
     return hipGetLastError();
 }

@@ -625,10 +625,10 @@ __device__ __forceinline__ void blend4(const float* la, const float (*lc)[Region
 }
 
 // one staged texel: index k of the (kMergeTW >> SH) + 2 columns wide region
-// of level LV (scale 2^SH) around the tile at (x0, y0), clamped to the level;
-// LV = 3 is dense, the others are read by rank (a = 0 and values 0 off the
-// stencil)
-template <int LV, int SH, int RW, int C, typename VT>
+// of the level in argument slot LV (scale 2^SH) around the tile at (x0, y0),
+// clamped to the level; DENSE: the coarsest level, read densely, the others
+// by rank (a = 0 and values 0 off the stencil)
+template <int LV, int SH, int RW, int C, typename VT, bool DENSE = LV == 3>
 __device__ __forceinline__ void stage4(const LeanMergeArgs& a, int k, int x0, int y0, float& av, float (&cv)[C]) {
     const LeanMergeLevel& L = a.lv[LV];
     const int yy = k / RW, xx = k - yy * RW;
@@ -637,7 +637,7 @@ __device__ __forceinline__ void stage4(const LeanMergeArgs& a, int k, int x0, in
     av = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) cv[c] = 0.0f;
-    if (LV == 3) {
+    if (DENSE) {
         const unsigned p = (unsigned)Yl * (unsigned)L.W + (unsigned)Xl;
 #pragma unroll
         for (int c = 0; c < C; ++c) cv[c] = cval<VT>(L.c, c * L.c_plane + p);
@@ -661,9 +661,12 @@ struct Merge4Lds {
     int any2, any3;
 };
 
-template <int C, typename VT>
+// L2 false: the levels 1, 3 and 4 (SSGI's Table 1 column), in argument
+// slots 0, 1 and 2: the same merge without level 2's staging and blend.
+template <int C, typename VT, bool L2 = true>
 __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned tile, unsigned tiles_x,
                                             Merge4Lds<C>& sm) {
+    constexpr int I3 = L2 ? 2 : 1, I4 = L2 ? 3 : 2;  // argument slots of levels 3 and 4
     using R2 = Region4<1>;
     using R3 = Region4<2>;
     using R4 = Region4<3>;
@@ -684,19 +687,21 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
     // remaining texels on threads [0, nB), level 4 on [nB, nB + n4), level 3
     // on [128, 128 + n3).  Each slot's level is fixed at compile time, so its
     // parameters are scalar and its divisions by the region width constant.
+    // Without level 2: level 4 on threads [0, n4), level 3 on [128, 128 + n3).
     constexpr int nB = R2::n - 256;
+    constexpr int n4lo = L2 ? nB : 0;  // first thread staging level 4
     static_assert(nB > 0 && nB + R4::n <= 128 && 128 + R3::n <= 256, "merge staging layout");
     float av[2], cv[2][C];
-    stage4<1, 1, R2::rw, C, VT>(a, t, x0, y0, av[0], cv[0]);
-    av[1] = 0.0f;
+    av[0] = av[1] = 0.0f;
 #pragma unroll
-    for (int c = 0; c < C; ++c) cv[1][c] = 0.0f;
-    if (t < nB)
+    for (int c = 0; c < C; ++c) cv[0][c] = cv[1][c] = 0.0f;
+    if constexpr (L2) stage4<1, 1, R2::rw, C, VT>(a, t, x0, y0, av[0], cv[0]);
+    if (L2 && t < nB)
         stage4<1, 1, R2::rw, C, VT>(a, 256 + t, x0, y0, av[1], cv[1]);
-    else if (t < nB + R4::n)
-        stage4<3, 3, R4::rw, C, VT>(a, t - nB, x0, y0, av[1], cv[1]);
+    else if (t >= n4lo && t < n4lo + R4::n)
+        stage4<I4, 3, R4::rw, C, VT, true>(a, t - n4lo, x0, y0, av[1], cv[1]);
     else if (t >= 128 && t < 128 + R3::n)
-        stage4<2, 2, R3::rw, C, VT>(a, t - 128, x0, y0, av[1], cv[1]);
+        stage4<I3, 2, R3::rw, C, VT, false>(a, t - 128, x0, y0, av[1], cv[1]);
     // a wave covers a 16 x 16 pixel square of the tile (four pixels of a row
     // per thread), so that the pixels near a stencil, where the blends run,
     // fill fewer waves
@@ -728,18 +733,21 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
             }
         }
     }
-    la2[t] = av[0];
+    bool nz2 = false, nz3 = false;
+    if constexpr (L2) {
+        la2[t] = av[0];
 #pragma unroll
-    for (int c = 0; c < C; ++c) lc2[c][t] = cv[0][c];
-    bool nz2 = av[0] != 0.0f, nz3 = false;
-    if (t < nB) {
+        for (int c = 0; c < C; ++c) lc2[c][t] = cv[0][c];
+        nz2 = av[0] != 0.0f;
+    }
+    if (L2 && t < nB) {
         la2[256 + t] = av[1];
 #pragma unroll
         for (int c = 0; c < C; ++c) lc2[c][256 + t] = cv[1][c];
         nz2 = nz2 || av[1] != 0.0f;
-    } else if (t < nB + R4::n) {
+    } else if (t >= n4lo && t < n4lo + R4::n) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) lc4[c][t - nB] = cv[1][c];
+        for (int c = 0; c < C; ++c) lc4[c][t - n4lo] = cv[1][c];
     } else if (t >= 128 && t < 128 + R3::n) {
         la3[t - 128] = av[1];
 #pragma unroll
@@ -755,7 +763,7 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
     {
         // coarsest level (scale 8): plain bilinear, normalising sum exactly 1
         using XT = XTaps4<3>;
-        const LeanMergeLevel& L = a.lv[3];
+        const LeanMergeLevel& L = a.lv[I4];
         int ya, yb;
         float fy;
         taps4<3>(Y, L.H, (y0 >> 3) - 1, ya, yb, fy);
@@ -777,8 +785,8 @@ __device__ __forceinline__ void merge4_tile(const LeanMergeArgs& a, unsigned til
             }
         }
     }
-    if (any3) blend4<2, C>(la3, lc3, a.lv[2], x0, y0, XQ, Y, out);
-    if (any2) blend4<1, C>(la2, lc2, a.lv[1], x0, y0, XQ, Y, out);
+    if (any3) blend4<2, C>(la3, lc3, a.lv[I3], x0, y0, XQ, Y, out);
+    if (L2 && any2) blend4<1, C>(la2, lc2, a.lv[1], x0, y0, XQ, Y, out);
     if (nib) {
         const float w1 = a.lv[0].w;
 #pragma unroll

@@ -376,6 +376,10 @@ hipError_t launch_lean_merge(const LeanMergeArgs& a, hipStream_t s);
 hipError_t launch_bilateral(const BilateralArgs& a, unsigned total_hint, hipStream_t s);
 hipError_t launch_ssao_fullres(const FullresArgs& a, int normal_dtype, hipStream_t s);
 bool merge4_applies(const LeanMergeArgs& a);
+// merge kernels: the general one, or fixed tap geometry for the levels 1-4
+// or 1, 3, 4 (level 1 by rank, width divisible by 4)
+constexpr int kMergeGeneral = 0, kMerge1234 = 1, kMerge134 = 2;
+int merge_geometry(const LeanMergeArgs& a);
 
 // edge kernel tiling for an image (the choice launch_edges makes)
 void edges_grid(int W, int H, int num_levels, bool& wide, unsigned& tiles_x, unsigned& ntiles);
@@ -407,7 +411,7 @@ hipError_t launch_ssao_batch_tiled(const SsaoArgs* T, int n, int S, int normal_d
 hipError_t launch_ssgi_batch(const SsgiArgs* T, int n, int S, int normal_dtype, int color_dtype,
                              unsigned total_hint, const BatchSchedule& bs, hipStream_t s);
 hipError_t launch_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base, const unsigned* tiles_x, int n,
-                                   unsigned total, int C, bool c16, bool m4, hipStream_t s);
+                                   unsigned total, int C, bool c16, int geo, hipStream_t s);
 
 // The whole batch in one persistent launch.  Blocks take tickets from one
 // counter; tickets run in stage order (edge tiles, stencil tiles, list tiles,
