@@ -20,14 +20,15 @@ __device__ __forceinline__ int batch_frame(const unsigned* blk_base, int n, unsi
     return f;
 }
 
-__global__ __launch_bounds__(kRankThreads) void k_lean_stencil_batch(const LeanArgs* T, const unsigned* blk_base,
-                                                                     int n) {
+__global__ __launch_bounds__(kRankThreads) void k_lean_stencil_batch(const LeanArgs* __restrict__ T,
+                                                                     const unsigned* __restrict__ blk_base, int n) {
     __shared__ StencilLds<kRankThreads> sm;
     const int f = batch_frame(blk_base, n, blockIdx.x);
     stencil_block(T[f], blockIdx.x - blk_base[f], sm);
 }
 
-__global__ __launch_bounds__(kRankThreads) void k_lean_list_batch(const LeanArgs* T, const unsigned* blk_base, int n) {
+__global__ __launch_bounds__(kRankThreads) void k_lean_list_batch(const LeanArgs* __restrict__ T,
+                                                                  const unsigned* __restrict__ blk_base, int n) {
     __shared__ ListLds<kRankThreads, kRankStage> sm;
     const int f = batch_frame(blk_base, n, blockIdx.x);
     list_block(T[f], blockIdx.x - blk_base[f], sm);
@@ -100,8 +101,8 @@ __global__ __launch_bounds__(256) void k_lean_merge4(LeanMergeArgs a, unsigned t
 // kMergeGeneral, kMerge1234, kMerge134
 template <int C, typename VT, int GEO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEO != kMergeGeneral ? 1 : merge_waves(C))))
-void k_lean_merge_batch(const LeanMergeArgs* T, const unsigned* tile_base,
-                                                          const unsigned* tiles_x, int n) {
+void k_lean_merge_batch(const LeanMergeArgs* __restrict__ T, const unsigned* __restrict__ tile_base,
+                        const unsigned* __restrict__ tiles_x, int n) {
     const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
     int f = 0;
     for (int k = 1; k < n; ++k) f += g >= tile_base[k] ? 1 : 0;

@@ -11,7 +11,7 @@ namespace mr {
 // of 256, swept by a resident grid in fixed strides.  At most kTiledSamples
 // samples.
 template <typename NT, int H>
-__global__ __launch_bounds__(256) void k_ssao_batch_tiled(const SsaoArgs* T, int n) {
+__global__ __launch_bounds__(256) void k_ssao_batch_tiled(const SsaoArgs* __restrict__ T, int n) {
     __shared__ float ks[3 * kTiledSamples];
     __shared__ float eg[kMaxLevels * kEgStride];
     __shared__ float zt[(kDenseTile + 2 * H) * (kDenseTile + 2 * H)];

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void k_ssgi(SsgiArgs a) {
 
 // frames of a batch (see k_ssao_batch)
 template <typename NT, typename CT, bool Q, bool KLDS>
-__global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* T, int n, unsigned* queue) {
+__global__ __launch_bounds__(256) void k_ssgi_batch(const SsgiArgs* __restrict__ T, int n, unsigned* queue) {
     __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
     __shared__ unsigned cbase[kMaxBatch + 1];
