@@ -43,7 +43,7 @@ SSAO_FP32_PER_TEXEL = 31
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (profiles/ssao_4k_hbm_counters.md), scaled by the
 # copy-kernel calibration
-TRAFFIC_BYTES = {"k_ssao_multi": 61843937}
+TRAFFIC_BYTES = {"k_ssao_multi": 61812084}
 # VALU wave instructions per launch (SQ_INSTS_VALU,
 # profiles/ssao_4k_eval_valu_issue.md) of the multi-resolution evaluation and
 # of the naive pass, which runs the same per-sample code densely over every
@@ -53,7 +53,7 @@ VALU_INSTS = {"k_ssao_multi": 20600129, "k_ssao_plain": 206263552}
 # the counters above hold for the kernels of this machine code only: the
 # SHA-256 of the gfx950 code built from k_ssao.hip (libmr.code.json) when
 # they were taken.  Any other code reports them as null.
-COUNTER_CODE = {"k_ssao_multi": ("k_ssao.hip", "5256826d3eef46370ca48e2621235c90f809c1ccb1e0a8ab83deae9103fa34ca")}
+COUNTER_CODE = {"k_ssao_multi": ("k_ssao.hip", "541f790742ecc6e2535f3fe93b9d578eea324b7db4de9de0325f33b68d3b06fb")}
 
 
 def log(*a):

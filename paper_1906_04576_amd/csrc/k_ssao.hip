@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_ssao_tiled(SsaoArgs a) {
 // space over all frames, each frame's range padded to whole chunks of 256,
 // swept by a resident grid like the single-frame launch.
 template <typename NT, bool AL, bool KLDS, bool Q>
-__global__ __launch_bounds__(256) void k_ssao_batch(const SsaoArgs* T, int n, unsigned* queue) {
+__global__ __launch_bounds__(256) void k_ssao_batch(const SsaoArgs* __restrict__ T, int n, unsigned* queue) {
     __shared__ float ks[KLDS ? 3 * kLdsSamples : 1];
     __shared__ float eg[kMaxLevels * kEgStride];
     __shared__ unsigned cbase[kMaxBatch + 1];
