@@ -174,6 +174,11 @@ def measure_ssao(steps=20, frames=None, device="cuda", samples=32):
     with torch.cuda.stream(st):
         cfg = b.tune(reps=3, stream=st)
     st.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=st):
+        b(st)
+    gr.replay()
+    t_tuned = _wall(gr.replay, steps)
     nws = max(mr.mr_workspace_bytes(f["depth"].shape[1], f["depth"].shape[0], f["focal"], mp, mr.MR_EFFECT_SSAO)
               for f in frames)
     ws = torch.empty(nws, dtype=torch.uint8, device=device)
@@ -191,12 +196,14 @@ def measure_ssao(steps=20, frames=None, device="cuda", samples=32):
         r()
         torch.cuda.synchronize()
         same = same and all(torch.equal(outs[h][k], r.out) for h in outs)
-    log(f"[batched] SSAO batch ms by eval_halo {ms}, tuned {cfg}, one after another {t_seq * 1e3:.3f} ms")
+    log(f"[batched] SSAO batch ms by eval_halo {ms}, tuned {cfg} {t_tuned * 1e3:.3f} ms, "
+        f"one after another {t_seq * 1e3:.3f} ms")
     return {
         "workload": f"{len(frames)} SSAO frames of uneven sizes (640x360..3840x2160), {samples} samples r=1.0, "
                     f"4 levels",
         "mpixels": round(npx / 1e6, 3), "graph_ms_by_eval_halo": {str(h): v for h, v in ms.items()},
         "mpixels_s": round(npx / (ms[0] * 1e-3) / 1e6, 2), "tuned_config": cfg,
+        "tuned_graph_ms": round(t_tuned * 1e3, 4), "tuned_mpixels_s": round(npx / t_tuned / 1e6, 2),
         "sequential_ms": round(t_seq * 1e3, 4), "speedup_vs_sequential": round(t_seq * 1e3 / ms[0], 3),
         "identical_to_frames_alone": bool(same),
     }
