@@ -85,6 +85,26 @@ __device__ __forceinline__ unsigned fused_bcast(unsigned* slot, unsigned v) {
     return r;
 }
 
+// Stage calls through restrict-qualified table parameters: inlined, they
+// keep the tables' no-alias guarantee, so a frame's fields need not be read
+// again after the stage's own stores.
+template <typename NT>
+__device__ __forceinline__ void fused_edges(const EdgeArgs* __restrict__ te, int f, unsigned i, unsigned tx) {
+    edges_tile<NT, false, true, true>(te[f], i, tx);
+}
+template <bool LIST, typename LDS>
+__device__ __forceinline__ void fused_rank(const LeanArgs* __restrict__ tl, int f, unsigned i, LDS& sm) {
+    if constexpr (LIST)
+        list_block<256, kFusedListStage>(tl[f], i, sm);
+    else
+        stencil_block<256>(tl[f], i, sm);
+}
+template <int C, typename VT, typename LDS>
+__device__ __forceinline__ void fused_merge4(const LeanMergeArgs* __restrict__ tm, int f, unsigned i, unsigned tx,
+                                             LDS& sm) {
+    merge4_tile<C, VT>(tm[f], i, tx, sm);
+}
+
 template <int C>
 union FusedLds {
     StencilLds<256> st;
@@ -173,7 +193,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             const unsigned nt = A.base[0][f + 1] - A.base[0][f];
             for (unsigned i = tile0; i < nt && i < tile0 + G; ++i) {
                 if (i > tile0) __syncthreads();  // the previous tile's LDS reads are done
-                edges_tile<NT, false, true, true>(A.te[f], i, A.edge_tx[f]);
+                fused_edges<NT>(A.te, f, i, A.edge_tx[f]);
             }
         } else if (s == 1 || s == 2) {
             // ranking tiles [j R, min((j + 1) R, n)): the stencil pass, or the
@@ -182,9 +202,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             for (unsigned i = j * kFusedRankGroup; i < nt && i < (j + 1u) * kFusedRankGroup; ++i) {
                 if (i > j * kFusedRankGroup) __syncthreads();  // the previous tile's LDS reads are done
                 if (s == 1)
-                    stencil_block<256>(A.tl[f], i, u.st);
+                    fused_rank<false>(A.tl, f, i, u.st);
                 else
-                    list_block<256, kFusedListStage>(A.tl[f], i, u.li);
+                    fused_rank<true>(A.tl, f, i, u.li);
             }
         } else if (s == 3) {
             // an evaluation worker: chunks of the frame's items until none is left
@@ -219,9 +239,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                 if (i > tile0) __syncthreads();  // the previous tile's LDS reads are done
                 if constexpr (M4) {
                     if (ma.c16)
-                        merge4_tile<C, _Float16>(ma, i, A.merge_tx[f], u.m4);
+                        fused_merge4<C, _Float16>(A.tm, f, i, A.merge_tx[f], u.m4);
                     else
-                        merge4_tile<C, float>(ma, i, A.merge_tx[f], u.m4);
+                        fused_merge4<C, float>(A.tm, f, i, A.merge_tx[f], u.m4);
                 } else {
                     if (ma.c16)
                         merge_tile<C, _Float16>(ma, i, A.merge_tx[f], u.mg.la, u.mg.ls, u.mg.lc, u.mg.lvl_any);
